@@ -1,0 +1,33 @@
+"""FP64 CPU oracle for velocity-gauge real-time TDDFTB propagation.
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, plain reference against
+which the HIP library is checked.  Only the test suite, the smoke check and
+the CPU-baseline leg of the benchmark may import it; the library itself never
+does, and the two share no code (only the seeded input generator feeds both).
+
+Every function cites the passage of the paper (arXiv 2308.09782, Section 2)
+whose computation it writes out.  Where the paper is silent the reading used
+is stated in the docstring.  All arithmetic is complex128 / float64.
+
+Pinned by tests/test_oracle_*.py (closed-form leapfrog solution, brute-force
+matrix-exponential propagation, invariants, the gauge identity, textbook sp3
+and single-orbital-chain models, SCC special cases, spectrum closed forms).
+"""
+from .tddftb import (  # noqa: F401
+    C_LIGHT,
+    bloch_sum,
+    overlap_k,
+    overlap_inverse,
+    h0_k,
+    momentum_k,
+    scc_potential,
+    hamiltonian_k,
+    mulliken,
+    ground_state,
+    occupations,
+    density_derivative,
+    observables,
+    propagate,
+    OracleState,
+)
+from .spectrum import conductivity, dielectric, absorption  # noqa: F401
