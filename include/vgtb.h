@@ -1,0 +1,206 @@
+/*
+ * vgtb.h - C ABI of the MI355X (gfx950) velocity-gauge real-time TDDFTB
+ * density-matrix propagator (Xu et al., arXiv 2308.09782).
+ *
+ * The library advances the k-dependent density matrices D_k of a periodic
+ * tight-binding system under a spatially uniform vector potential A(t):
+ *
+ *   i dD_k/dt = S_k^-1 H_k D_k - D_k H_k S_k^-1                 (Eq. 6)
+ *   D_k(t + dt) = D_k(t - dt) + 2 dt dD_k/dt(t)                 (Eq. 13)
+ *
+ * with S_k and H_k Bloch sums of real-space two-centre blocks (Eqs. 7-8),
+ * the velocity-gauge coupling realised as the phase exp(i (k + A/c) . d) on
+ * the H0 blocks, the self-consistent-charge shift of Eq. 10 from Mulliken
+ * charges, and the current of Eq. 14.
+ *
+ * Conventions shared by every call:
+ *   - Atomic units (bohr, hartree, atomic time); c = 137.035999084.
+ *   - Complex matrices are complex128 (two doubles, real then imaginary),
+ *     row-major, N x N per k-point, k-points consecutive: element (k, i, j)
+ *     sits at offset (k * N + i) * N + j.  N = n_atoms * orbs_per_atom and
+ *     orbital index i = atom * orbs_per_atom + (s, px, py, pz order).
+ *   - Pointers named "host" are host memory; pointers named "dev" are device
+ *     memory of the GPU that is current when vgtb_create is called.
+ *   - Host inputs are copied; the caller keeps ownership of every pointer it
+ *     passes.  The device arena passed to vgtb_create belongs to the caller,
+ *     must outlive the context, and must not be touched while it is alive.
+ *   - Every call returns a vgtb_status; no exception crosses the ABI.  After
+ *     VGTB_E_DEVICE or VGTB_E_NONFINITE the context is poisoned: only
+ *     vgtb_last_error and vgtb_destroy remain valid.
+ *   - A context is not thread-safe; distinct contexts are independent.  All
+ *     device work is queued on the stream given at creation.
+ */
+#ifndef VGTB_H
+#define VGTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vgtb_ctx vgtb_ctx;
+
+typedef enum {
+  VGTB_OK = 0,
+  VGTB_E_INVAL = 1,      /* bad argument or inconsistent system description      */
+  VGTB_E_STATE = 2,      /* call out of order (e.g. step before a density is set) */
+  VGTB_E_NOT_PD = 3,     /* the Cholesky factorisation of some S_k failed          */
+  VGTB_E_UNSTABLE = 4,   /* |dt| * (spectral width) >= 1: leapfrog would diverge  */
+  VGTB_E_NOMEM = 5,      /* the arena is smaller than vgtb_workspace_size          */
+  VGTB_E_DEVICE = 6,     /* a HIP / rocSOLVER call failed                          */
+  VGTB_E_NONFINITE = 7   /* a non-finite trace was observed during stepping        */
+} vgtb_status;
+
+typedef enum {
+  VGTB_FP64 = 0,   /* every product in FP64 on the FP64 matrix cores                       */
+  VGTB_FP32 = 1,   /* deviation form, S^-1 (H dD + dH D0) product in FP32 on matrix cores  */
+  VGTB_BF16X3 = 2  /* deviation form, the same product as three BF16 products (hi/lo split) */
+} vgtb_precision;
+
+/*
+ * Real-space description of one periodic system (paper Section 2, Eqs. 7-11).
+ *
+ * Block b couples the orbitals of atom blk_i[b] (rows) with those of the
+ * periodic image of atom blk_j[b] (columns) whose bond vector is
+ *   d_b = R_J + L - R_I                     (blk_d[3b..3b+2], bohr).
+ * blk_h0 / blk_s hold the real orbs_per_atom^2 values of H0 and S of that
+ * block, row-major.  On-site blocks have d = 0.  The list must contain, for
+ * every block (I, J, d), the partner (J, I, -d) with the transposed values
+ * (so that H_k and S_k are Hermitian); vgtb_create checks this.
+ *
+ * kpts are Cartesian (1/bohr), kw their weights (sum 1).  n_electrons is the
+ * electron count per k-point (f = 2 per state, Tr(D_k S_k) = n_electrons).
+ * gamma (n_atoms^2, symmetric) switches on the SCC term of Eq. 10; NULL means
+ * a non-SCC run.  z_ref is the per-atom reference charge Z_I of dq = q - Z;
+ * NULL means "the Mulliken charges of the ground state" (set by
+ * vgtb_ground_state), which makes the ground state self-consistent.
+ */
+typedef struct {
+  int32_t n_atoms;
+  int32_t orbs_per_atom;       /* 1 (s) or 4 (s, px, py, pz)                   */
+  double cell[9];              /* lattice vectors as rows, bohr                 */
+  int32_t n_blocks;
+  const int32_t *blk_i;        /* host, n_blocks                                */
+  const int32_t *blk_j;        /* host, n_blocks                                */
+  const double *blk_d;         /* host, n_blocks * 3                            */
+  const double *blk_h0;        /* host, n_blocks * orbs^2                       */
+  const double *blk_s;         /* host, n_blocks * orbs^2                       */
+  int32_t n_k;
+  const double *kpts;          /* host, n_k * 3                                 */
+  const double *kw;            /* host, n_k                                     */
+  double n_electrons;          /* per k-point                                   */
+  const double *z_ref;         /* host, n_atoms, or NULL                        */
+  const double *gamma;         /* host, n_atoms * n_atoms, or NULL (non-SCC)   */
+} vgtb_system;
+
+typedef struct {
+  double dt;                   /* time step (atomic time units), finite, nonzero */
+  int32_t precision;           /* vgtb_precision                                 */
+  int32_t rescale_every;       /* deviation forms: re-Hermitise and rescale the
+                                  trace every this many steps (0 = never)        */
+  int32_t history_capacity;    /* observables ring length in steps (>= 1)        */
+  int32_t reserved;            /* must be 0                                      */
+} vgtb_options;
+
+/* Bytes of device arena vgtb_create needs for this system and options. */
+vgtb_status vgtb_workspace_size(const vgtb_system *sys, const vgtb_options *opt,
+                                size_t *bytes);
+
+/*
+ * Validate the system, copy it to the device arena (dev_arena, arena_bytes,
+ * 256-byte aligned), build S_k (Eq. 7) and S_k^-1 by a Cholesky
+ * factorisation (VGTB_E_NOT_PD if some S_k is not positive definite), and
+ * return a context bound to hip_stream (a hipStream_t; NULL = the null
+ * stream).  The caller owns dev_arena and the stream.  *out is set only on
+ * VGTB_OK.
+ */
+vgtb_status vgtb_create(const vgtb_system *sys, const vgtb_options *opt, void *dev_arena,
+                        size_t arena_bytes, void *hip_stream, vgtb_ctx **out);
+
+/*
+ * Ground state at A = 0: solve H0_k C = S_k C eps for every k, fill states by
+ * aufbau with f = 2 (a degenerate group straddling the Fermi level shares its
+ * electrons equally), form D_k(0) = sum_n f_n c_n c_n^dag on the device and
+ * make it the current density (step index 0).  If z_ref was NULL, the
+ * Mulliken charges of this density become Z.  min_gap_host (may be NULL)
+ * receives the smallest HOMO-LUMO gap over k.  Returns VGTB_E_UNSTABLE if
+ * |dt| times the largest spectral width over k is >= 1 (the density is
+ * still set).  Synchronises the stream.
+ */
+vgtb_status vgtb_ground_state(vgtb_ctx *ctx, double *min_gap_host);
+
+/*
+ * Set D_k(0) from n_k * N * N complex128 values (on_device != 0: device
+ * pointer read on the context stream; else host).  Resets the step index to
+ * 0 and forgets the previous level.  In the deviation forms this density
+ * is the reference D0 and the deviation starts at zero.
+ */
+vgtb_status vgtb_set_density(vgtb_ctx *ctx, const void *d, int on_device);
+
+/* A(t_n) for n = 0 .. n-1 (host, n * 3 doubles, atomic units).  Steps past
+ * the table's end use its last entry. */
+vgtb_status vgtb_set_field_table(vgtb_ctx *ctx, int64_t n, const double *a_host);
+
+/* A constant vector potential from the next step on (a one-entry table). */
+vgtb_status vgtb_set_field(vgtb_ctx *ctx, const double a_host[3]);
+
+/*
+ * Queue n_steps leapfrog steps on the context stream (asynchronous).  Step n
+ * uses A(t_n), evaluates the SCC shift from the charges of D_n, records the
+ * observables of D_n in the history ring, then forms D_{n+1} (the first
+ * step after a density is set is a forward Euler step).  Deviation forms
+ * re-Hermitise and rescale the trace of both levels after every
+ * rescale_every-th step.
+ */
+vgtb_status vgtb_step(vgtb_ctx *ctx, int64_t n_steps);
+
+/* Wait for the stream; VGTB_E_NONFINITE if any recorded trace was not finite. */
+vgtb_status vgtb_synchronize(vgtb_ctx *ctx);
+
+/*
+ * Copy observables of steps [first, first + count) to host arrays (each may
+ * be NULL): J count*3 (Eq. 14, bohr^-2 a.u. current density), E count (band
+ * + SCC energy per cell), trace count (sum_k w_k Re Tr(D_k S_k)), q
+ * count*n_atoms (Mulliken charges).  Those steps must still be in the ring.
+ * Synchronises the stream.
+ */
+vgtb_status vgtb_read_observables(vgtb_ctx *ctx, int64_t first, int64_t count, double *j_host,
+                                  double *e_host, double *trace_host, double *q_host);
+
+/* Copy D at level 0 (= D_n, current) or 1 (= D_{n-1}) to out (device or
+ * host), n_k * N * N complex128.  Synchronises the stream. */
+vgtb_status vgtb_get_density(vgtb_ctx *ctx, int32_t level, void *out, int on_device);
+
+/* Reference charges Z in use (host, n_atoms doubles). */
+vgtb_status vgtb_get_reference_charges(vgtb_ctx *ctx, double *z_host);
+
+/* Checkpoint: bytes needed, save both leapfrog levels, the reference density
+ * and the step index to host memory, and restore them.  Resuming continues
+ * bit-identically to an uninterrupted run. */
+vgtb_status vgtb_state_size(const vgtb_ctx *ctx, size_t *bytes);
+vgtb_status vgtb_save_state(vgtb_ctx *ctx, void *host_buf, size_t bytes);
+vgtb_status vgtb_load_state(vgtb_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Steps taken since the density was set. */
+int64_t vgtb_step_index(const vgtb_ctx *ctx);
+
+/* Last error message of this context (NUL-terminated, owned by the context;
+ * ctx may be NULL for errors raised before a context existed). */
+const char *vgtb_last_error(const vgtb_ctx *ctx);
+
+void vgtb_destroy(vgtb_ctx *ctx);
+
+/*
+ * Stand-alone kernel entry: C = A * B for `batch` row-major N x N complex128
+ * matrices (strides N*N), on the FP64 matrix cores - the dense product
+ * S_k^-1 (H_k D_k) of Eq. 6.  Device pointers, queued on hip_stream.
+ */
+vgtb_status vgtb_zgemm(const void *a_dev, const void *b_dev, void *c_dev, int32_t n, int32_t batch,
+                       void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VGTB_H */

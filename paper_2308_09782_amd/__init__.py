@@ -1,0 +1,17 @@
+"""MI355X-native velocity-gauge real-time TDDFTB density-matrix propagation.
+
+The compute path is the HIP library libvgtb.so (C ABI in include/vgtb.h);
+this package holds its sources (csrc/), the in-tree build step (build.py)
+and the ctypes binding (vgtb.py).
+"""
+from .vgtb import (  # noqa: F401
+    EXPORTED,
+    LIB_PATH,
+    Propagator,
+    VgtbError,
+    load_library,
+    make_options,
+    make_system_struct,
+    vgtb_workspace_size,
+    vgtb_zgemm,
+)

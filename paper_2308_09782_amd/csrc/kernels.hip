@@ -1,0 +1,472 @@
+// HIP kernels (gfx950) for everything except the dense matrix-core product:
+// Bloch sums over the pair graph, fused Peierls assembly + block-sparse
+// product W = H_k D_k, Mulliken / energy / current sweeps, the single-block
+// reduction with the SCC shift, and the leapfrog update.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "vgtb_internal.h"
+
+namespace vgtb {
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void k_fill_zero(double2 *p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = make_double2(0.0, 0.0);
+}
+
+// S_k restricted to the pair graph: spk[k][p][e] = sum_images exp(i k.d) S(e)  (Eq. 7).
+__global__ void k_pair_bloch_s(PairGraph g, const double *kpts, double2 *spk) {
+  const int e2 = g.norb * g.norb;
+  const int k = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n_pairs * e2) return;
+  const int p = t / e2, e = t % e2;
+  const double kx = kpts[3 * k], ky = kpts[3 * k + 1], kz = kpts[3 * k + 2];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+    const double th = kx * g.img_d[3 * m] + ky * g.img_d[3 * m + 1] + kz * g.img_d[3 * m + 2];
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double s = g.img_s[(size_t)m * e2 + e];
+    acc.x += cs * s;
+    acc.y += sn * s;
+  }
+  spk[((size_t)k * g.n_pairs + p) * e2 + e] = acc;
+}
+
+// Scatter pair values into a dense N x N matrix per k.  which = 0: S_k from
+// spk; which = 1: H0_k at A = 0 (Eq. 8), Bloch-summed here.
+__global__ void k_scatter_pairs(PairGraph g, const double *kpts, const double2 *spk, int which,
+                                double2 *dense, int n) {
+  const int e2 = g.norb * g.norb;
+  const int k = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n_pairs * e2) return;
+  const int p = t / e2, e = t % e2;
+  // row atom of pair p: binary search in row_ptr
+  int lo = 0, hi = g.n_atoms - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.row_ptr[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const int I = lo, J = g.pair_col[p];
+  const int mu = e / g.norb, nu = e % g.norb;
+  double2 val;
+  if (which == 0) {
+    val = spk[((size_t)k * g.n_pairs + p) * e2 + e];
+  } else {
+    const double kx = kpts[3 * k], ky = kpts[3 * k + 1], kz = kpts[3 * k + 2];
+    val = make_double2(0.0, 0.0);
+    for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+      const double th = kx * g.img_d[3 * m] + ky * g.img_d[3 * m + 1] + kz * g.img_d[3 * m + 2];
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      const double h = g.img_h0[(size_t)m * e2 + e];
+      val.x += cs * h;
+      val.y += sn * h;
+    }
+  }
+  dense[(size_t)k * n * n + (size_t)(I * g.norb + mu) * n + (J * g.norb + nu)] = val;
+}
+
+// One wavefront per (atom I, k): sweep the pair blocks of row I of D_k and
+// accumulate  q = Re sum D conj(S)  (Mulliken, row I),  E = Re sum conj(D) H0,
+// J^a = Re sum conj(D) Pi^a  with Pi^a = sum_images i d^a exp(i(k+A/c).d) H0.
+template <int NO, bool DELTA>
+__global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__restrict__ d,
+                                                const double2 *__restrict__ d0, int n,
+                                                const double *kpts, StepField f,
+                                                const double2 *__restrict__ spk,
+                                                double *__restrict__ part) {
+  constexpr int E2 = NO * NO;
+  constexpr int P = 64 / E2;
+  const int I = blockIdx.x, k = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int e = lane % E2, slot = lane / E2;
+  const int mu = e / NO, nu = e % NO;
+  const double kx = kpts[3 * k] + f.ax, ky = kpts[3 * k + 1] + f.ay, kz = kpts[3 * k + 2] + f.az;
+  const size_t base = (size_t)k * n * n;
+  double q = 0.0, en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  const int p1 = g.row_ptr[I + 1];
+  for (int p = g.row_ptr[I] + slot; p < p1; p += P) {
+    const int J = g.pair_col[p];
+    const size_t idx = base + (size_t)(I * NO + mu) * n + (J * NO + nu);
+    double2 dv = d[idx];
+    if (DELTA) {
+      const double2 r = d0[idx];
+      dv.x += r.x;
+      dv.y += r.y;
+    }
+    const double2 s = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+    q += dv.x * s.x + dv.y * s.y;
+    for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+      const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
+      double sn, cs;
+      sincos(kx * dx + ky * dy + kz * dz, &sn, &cs);
+      const double h = g.img_h0[(size_t)m * E2 + e];
+      const double re = (dv.x * cs + dv.y * sn) * h;   // Re(conj(D) e^{i th} h)
+      const double im = (dv.x * sn - dv.y * cs) * h;   // Im(conj(D) e^{i th} h)
+      en += re;
+      jx -= dx * im;
+      jy -= dy * im;
+      jz -= dz * im;
+    }
+  }
+  q = wave_sum(q);
+  en = wave_sum(en);
+  jx = wave_sum(jx);
+  jy = wave_sum(jy);
+  jz = wave_sum(jz);
+  if (lane == 0) {
+    double *o = part + ((size_t)k * g.n_atoms + I) * 5;
+    o[0] = q;
+    o[1] = en;
+    o[2] = jx;
+    o[3] = jy;
+    o[4] = jz;
+  }
+}
+
+// Single workgroup: k-sums of the partials, Mulliken charges, SCC potential
+// V = gamma (q - Z) (Eq. 10), energy, current (Eq. 14) and trace; one history
+// row [Jx Jy Jz E Tr q_0 .. q_{na-1}].  Fixed summation order (deterministic).
+constexpr int kReduceThreads = 256;
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ part, int nk,
+                                                           int na, const double *__restrict__ kw,
+                                                           double jscale,
+                                                           const double *__restrict__ gamma,
+                                                           const double *__restrict__ z,
+                                                           double *__restrict__ v,
+                                                           double *__restrict__ qbuf,
+                                                           double *__restrict__ hist_row,
+                                                           int *flag) {
+  __shared__ double red[6][kReduceThreads];
+  const int t = threadIdx.x;
+  for (int I = t; I < na; I += kReduceThreads) {
+    double q = 0.0;
+    for (int k = 0; k < nk; ++k) q += kw[k] * part[((size_t)k * na + I) * 5];
+    qbuf[I] = q;
+    hist_row[5 + I] = q;
+  }
+  __syncthreads();
+  double escc = 0.0;
+  if (gamma != nullptr) {
+    for (int I = t; I < na; I += kReduceThreads) {
+      double acc = 0.0;
+      const double *gr = gamma + (size_t)I * na;
+      for (int K = 0; K < na; ++K) acc += gr[K] * (qbuf[K] - z[K]);
+      v[I] = acc;
+      escc += 0.5 * (qbuf[I] - z[I]) * acc;
+    }
+  }
+  double en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, tr = 0.0;
+  for (int idx = t; idx < nk * na; idx += kReduceThreads) {
+    const int k = idx / na;
+    const double *o = part + (size_t)idx * 5;
+    tr += kw[k] * o[0];
+    en += kw[k] * o[1];
+    jx += o[2];
+    jy += o[3];
+    jz += o[4];
+  }
+  red[0][t] = en;
+  red[1][t] = jx;
+  red[2][t] = jy;
+  red[3][t] = jz;
+  red[4][t] = tr;
+  red[5][t] = escc;
+  __syncthreads();
+  for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    hist_row[0] = red[1][0] * jscale;
+    hist_row[1] = red[2][0] * jscale;
+    hist_row[2] = red[3][0] * jscale;
+    hist_row[3] = red[0][0] + red[5][0];
+    hist_row[4] = red[4][0];
+    if (!isfinite(red[4][0]) || !isfinite(red[0][0])) *flag = 1;
+  }
+}
+
+// Fused assembly + block-sparse product.  Block (column chunk, atom I, k):
+//   W[rows of I, cols] = sum_{pairs (I,J)} H_k(I,J) D_k[rows of J, cols]
+// with H_k(I,J) = sum_images exp(i(k+A/c).d) H0 + 1/2 (V_I + V_J) S_k(I,J)
+// (Eqs. 8-10) built in LDS.  DELTA: the deviation form
+//   W = H_k dD + dH_k D0,  dH_k = H_k - H0_k(A=0)
+// with exp(i(k+A/c).d) - exp(i k.d) = 2 sin(a/2) i exp(i(k.d + a/2)), a = A.d/c.
+constexpr int kPairChunk = 64;
+
+template <int NO, bool DELTA>
+__global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d,
+                                              const double2 *__restrict__ d0, int n,
+                                              const double *kpts, StepField f,
+                                              const double2 *__restrict__ spk,
+                                              const double *__restrict__ v,
+                                              double2 *__restrict__ w) {
+  constexpr int E2 = NO * NO;
+  __shared__ double2 hs[kPairChunk * E2];
+  __shared__ double2 dhs[DELTA ? kPairChunk * E2 : 1];
+  __shared__ int cols[kPairChunk];
+  const int I = blockIdx.y, k = blockIdx.z;
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const double k0x = kpts[3 * k], k0y = kpts[3 * k + 1], k0z = kpts[3 * k + 2];
+  const size_t base = (size_t)k * n * n;
+  const double vi = v ? v[I] : 0.0;
+  double2 acc[NO];
+#pragma unroll
+  for (int mu = 0; mu < NO; ++mu) acc[mu] = make_double2(0.0, 0.0);
+  const int p0 = g.row_ptr[I], p1 = g.row_ptr[I + 1];
+  for (int pc = p0; pc < p1; pc += kPairChunk) {
+    const int npc = min(kPairChunk, p1 - pc);
+    for (int t = threadIdx.x; t < npc * E2; t += blockDim.x) {
+      const int pl = t / E2, e = t % E2, p = pc + pl;
+      double2 h = make_double2(0.0, 0.0), dh = make_double2(0.0, 0.0);
+      for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+        const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
+        const double hv = g.img_h0[(size_t)m * E2 + e];
+        const double a = f.ax * dx + f.ay * dy + f.az * dz;
+        const double kd = k0x * dx + k0y * dy + k0z * dz;
+        double sn, cs;
+        sincos(kd + a, &sn, &cs);
+        h.x += cs * hv;
+        h.y += sn * hv;
+        if (DELTA) {
+          double sh, ch;
+          sincos(kd + 0.5 * a, &sh, &ch);
+          const double amp = 2.0 * sin(0.5 * a) * hv;
+          dh.x -= amp * sh;
+          dh.y += amp * ch;
+        }
+      }
+      if (v != nullptr) {
+        const double vs = 0.5 * (vi + v[g.pair_col[p]]);
+        const double2 s = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+        h.x += vs * s.x;
+        h.y += vs * s.y;
+        if (DELTA) {
+          dh.x += vs * s.x;
+          dh.y += vs * s.y;
+        }
+      }
+      hs[t] = h;
+      if (DELTA) dhs[t] = dh;
+      if (e == 0) cols[pl] = g.pair_col[p];
+    }
+    __syncthreads();
+    if (col < n) {
+      for (int pl = 0; pl < npc; ++pl) {
+        const int J = cols[pl];
+#pragma unroll
+        for (int nu = 0; nu < NO; ++nu) {
+          const size_t idx = base + (size_t)(J * NO + nu) * n + col;
+          const double2 dv = d[idx];
+#pragma unroll
+          for (int mu = 0; mu < NO; ++mu) {
+            const double2 h = hs[pl * E2 + mu * NO + nu];
+            acc[mu].x += h.x * dv.x - h.y * dv.y;
+            acc[mu].y += h.x * dv.y + h.y * dv.x;
+          }
+          if (DELTA) {
+            const double2 rv = d0[idx];
+#pragma unroll
+            for (int mu = 0; mu < NO; ++mu) {
+              const double2 h = dhs[pl * E2 + mu * NO + nu];
+              acc[mu].x += h.x * rv.x - h.y * rv.y;
+              acc[mu].y += h.x * rv.y + h.y * rv.x;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (col < n) {
+#pragma unroll
+    for (int mu = 0; mu < NO; ++mu) w[base + (size_t)(I * NO + mu) * n + col] = acc[mu];
+  }
+}
+
+// Leapfrog (Eq. 13) in the form D_out = D_base - i fac (Y - Y^dag), Y = S^-1 H D,
+// so that dD/dt = -i (Y - Y^dag) is anti-Hermitian bit for bit.  32x32 tiles;
+// the transposed partner tile of Y is staged through LDS.
+__global__ __launch_bounds__(256) void k_update(const double2 *__restrict__ y,
+                                                const double2 *dbase, double2 *dout, int n,
+                                                double fac) {
+  __shared__ double2 tt[32][33];
+  const int k = blockIdx.z;
+  const size_t base = (size_t)k * n * n;
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int row = bj + r, c = bi + tx;
+    tt[r][tx] = (row < n && c < n) ? y[base + (size_t)row * n + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi + r, j = bj + tx;
+    if (i < n && j < n) {
+      const size_t idx = base + (size_t)i * n + j;
+      const double2 yv = y[idx];
+      const double2 yt = tt[tx][r];            // Y[j][i]
+      const double xr = yv.x - yt.x;           // X = Y - conj(Y^T)
+      const double xi = yv.y + yt.y;
+      const double2 b = dbase[idx];
+      dout[idx] = make_double2(b.x + fac * xi, b.y - fac * xr);
+    }
+  }
+}
+
+// After a lower-triangle result (row-major): m[i][j] = conj(m[j][i]) for i < j,
+// diagonal made real.
+__global__ void k_hermitian_from_lower(double2 *m, int n) {
+  const int k = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= n || j >= n) return;
+  double2 *mk = m + (size_t)k * n * n;
+  if (i < j) {
+    const double2 lo = mk[(size_t)j * n + i];
+    mk[(size_t)i * n + j] = make_double2(lo.x, -lo.y);
+  } else if (i == j) {
+    mk[(size_t)i * n + i].y = 0.0;
+  }
+}
+
+// D[i][j] = sum_n occ[n] c_n[i] conj(c_n[j]) where row n of evec holds conj(c_n)
+// (the column-major eigenvectors of the conjugated problem seen row-major).
+// Lower triangle computed, upper mirrored: exactly Hermitian.
+__global__ __launch_bounds__(256) void k_density_from_vectors(const double2 *__restrict__ evec,
+                                                              const double *__restrict__ occ,
+                                                              double2 *__restrict__ d, int n) {
+  __shared__ double2 ei[16][17];
+  __shared__ double2 ej[16][17];
+  const int k = blockIdx.z;
+  const int bi = blockIdx.y * 16, bj = blockIdx.x * 16;
+  if (bj > bi + 15) return;   // tile strictly above the diagonal
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const double2 *ek = evec + (size_t)k * n * n;
+  const double *ok = occ + (size_t)k * n;
+  const int i = bi + ty, j = bj + tx;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int n0 = 0; n0 < n; n0 += 16) {
+    const int nn = n0 + ty;
+    const double f = (nn < n) ? ok[nn] : 0.0;
+    ei[ty][tx] = (nn < n && bi + tx < n) ? ek[(size_t)nn * n + bi + tx] : make_double2(0.0, 0.0);
+    const double2 vj = (nn < n && bj + tx < n) ? ek[(size_t)nn * n + bj + tx] : make_double2(0.0, 0.0);
+    ej[ty][tx] = make_double2(f * vj.x, f * vj.y);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const double2 a = ei[s][ty];    // conj(c_n[i])
+      const double2 b = ej[s][tx];    // f conj(c_n[j])
+      // c_n[i] conj(c_n[j]) = conj(a) * b
+      acc.x += a.x * b.x + a.y * b.y;
+      acc.y += a.x * b.y - a.y * b.x;
+    }
+    __syncthreads();
+  }
+  if (i < n && j < n && i >= j) {
+    double2 *dk = d + (size_t)k * n * n;
+    if (i == j) {
+      dk[(size_t)i * n + i] = make_double2(acc.x, 0.0);
+    } else {
+      dk[(size_t)i * n + j] = acc;
+      dk[(size_t)j * n + i] = make_double2(acc.x, -acc.y);
+    }
+  }
+}
+
+inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_fill_zero(double2 *p, size_t n, hipStream_t s) {
+  unsigned b = blocks_for(n, 256);
+  if (b > 65536u) b = 65536u;
+  if (b == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3(b), dim3(256), 0, s, p, n);
+}
+
+void launch_pair_bloch_s(const PairGraph &g, const double *kpts, int nk, double2 *spk,
+                         hipStream_t s) {
+  const size_t tot = (size_t)g.n_pairs * g.norb * g.norb;
+  hipLaunchKernelGGL(k_pair_bloch_s, dim3(blocks_for(tot, 256), nk), dim3(256), 0, s, g, kpts,
+                     spk);
+}
+
+void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                          int which, double2 *dense, int n, hipStream_t s) {
+  const size_t tot = (size_t)g.n_pairs * g.norb * g.norb;
+  hipLaunchKernelGGL(k_scatter_pairs, dim3(blocks_for(tot, 256), nk), dim3(256), 0, s, g, kpts,
+                     spk, which, dense, n);
+}
+
+void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int n,
+                    const double *kpts, int nk, StepField f, const double2 *spk, double *part,
+                    hipStream_t s) {
+  dim3 grid(g.n_atoms, nk);
+  if (g.norb == 4) {
+    if (d0) hipLaunchKernelGGL((k_observe<4, true>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
+    else hipLaunchKernelGGL((k_observe<4, false>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
+  } else {
+    if (d0) hipLaunchKernelGGL((k_observe<1, true>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
+    else hipLaunchKernelGGL((k_observe<1, false>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
+  }
+}
+
+void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
+                   const double *gamma, const double *z, double *v, double *qbuf,
+                   double *hist_row, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, s, part, nk, na, kw, jscale,
+                     gamma, z, v, qbuf, hist_row, flag);
+}
+
+void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
+                 const double *kpts, int nk, StepField f, const double2 *spk, const double *v,
+                 double2 *w, hipStream_t s) {
+  const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
+  dim3 grid(blocks_for(n, threads), g.n_atoms, nk);
+  if (g.norb == 4) {
+    if (d0) hipLaunchKernelGGL((k_spmm<4, true>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
+    else hipLaunchKernelGGL((k_spmm<4, false>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
+  } else {
+    if (d0) hipLaunchKernelGGL((k_spmm<1, true>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
+    else hipLaunchKernelGGL((k_spmm<1, false>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
+  }
+}
+
+void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
+                   double fac, hipStream_t s) {
+  dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
+  hipLaunchKernelGGL(k_update, grid, dim3(256), 0, s, y, dbase, dout, n, fac);
+}
+
+void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s) {
+  dim3 grid(blocks_for(n, 16), blocks_for(n, 16), nk);
+  hipLaunchKernelGGL(k_hermitian_from_lower, grid, dim3(16, 16), 0, s, m, n);
+}
+
+void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
+                                 int nk, hipStream_t s) {
+  dim3 grid(blocks_for(n, 16), blocks_for(n, 16), nk);
+  hipLaunchKernelGGL(k_density_from_vectors, grid, dim3(256), 0, s, evec, occ, d, n);
+}
+
+}  // namespace vgtb

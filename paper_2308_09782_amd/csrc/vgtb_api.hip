@@ -1,0 +1,718 @@
+// C ABI of the propagator: validation, device arena layout, initialisation
+// (S_k, S_k^-1, ground state) and the per-step launch sequence.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "vgtb_internal.h"
+
+using vgtb::PairGraph;
+
+namespace {
+
+thread_local std::string g_global_err;
+
+vgtb_status fail(vgtb_ctx *ctx, vgtb_status st, const std::string &msg) {
+  if (ctx) {
+    ctx->err = msg;
+    if (st == VGTB_E_DEVICE || st == VGTB_E_NONFINITE) ctx->poisoned = true;
+  } else {
+    g_global_err = msg;
+  }
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                 \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return fail(ctx, VGTB_E_DEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+#define BLAS_TRY(ctx, expr)                                                                \
+  do {                                                                                     \
+    rocblas_status _s = (expr);                                                            \
+    if (_s != rocblas_status_success)                                                      \
+      return fail(ctx, VGTB_E_DEVICE,                                                      \
+                  std::string(#expr " failed: ") + rocblas_status_to_string(_s));          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Host-side pair graph: group the real-space blocks by (I, J).
+// ---------------------------------------------------------------------------
+struct HostGraph {
+  int na = 0, norb = 0;
+  std::vector<int> row_ptr, pair_col, img_ptr;
+  std::vector<double> img_d, img_h0, img_s;
+};
+
+vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
+  const int na = s->n_atoms, no = s->orbs_per_atom, nb = s->n_blocks;
+  const int e2 = no * no;
+  std::vector<int> order(nb);
+  std::iota(order.begin(), order.end(), 0);
+  for (int b = 0; b < nb; ++b) {
+    if (s->blk_i[b] < 0 || s->blk_i[b] >= na || s->blk_j[b] < 0 || s->blk_j[b] >= na) {
+      msg = "block " + std::to_string(b) + " refers to an atom outside [0, n_atoms)";
+      return VGTB_E_INVAL;
+    }
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(s->blk_d[3 * b + c])) {
+        msg = "non-finite bond vector in block " + std::to_string(b);
+        return VGTB_E_INVAL;
+      }
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (s->blk_i[a] != s->blk_i[b]) return s->blk_i[a] < s->blk_i[b];
+    return s->blk_j[a] < s->blk_j[b];
+  });
+  // Hermitian partner check: (I, J, d) needs (J, I, -d) with transposed values.
+  auto key = [&](int i, int j, const double *d) {
+    return std::make_tuple(i, j, std::llround(d[0] * 1e6), std::llround(d[1] * 1e6),
+                           std::llround(d[2] * 1e6));
+  };
+  std::map<std::tuple<int, int, long long, long long, long long>, int> index;
+  for (int b = 0; b < nb; ++b) {
+    auto k = key(s->blk_i[b], s->blk_j[b], s->blk_d + 3 * b);
+    if (!index.emplace(k, b).second) {
+      msg = "duplicate block (same atoms and bond vector) at index " + std::to_string(b);
+      return VGTB_E_INVAL;
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    const double nd[3] = {-s->blk_d[3 * b], -s->blk_d[3 * b + 1], -s->blk_d[3 * b + 2]};
+    auto it = index.find(key(s->blk_j[b], s->blk_i[b], nd));
+    if (it == index.end()) {
+      msg = "block " + std::to_string(b) + " has no Hermitian partner (J, I, -d)";
+      return VGTB_E_INVAL;
+    }
+    const int c = it->second;
+    for (int mu = 0; mu < no; ++mu)
+      for (int nu = 0; nu < no; ++nu) {
+        const double h1 = s->blk_h0[(size_t)b * e2 + mu * no + nu];
+        const double h2 = s->blk_h0[(size_t)c * e2 + nu * no + mu];
+        const double s1 = s->blk_s[(size_t)b * e2 + mu * no + nu];
+        const double s2 = s->blk_s[(size_t)c * e2 + nu * no + mu];
+        if (!(std::fabs(h1 - h2) <= 1e-12 * (1.0 + std::fabs(h1))) ||
+            !(std::fabs(s1 - s2) <= 1e-12 * (1.0 + std::fabs(s1)))) {
+          msg = "block " + std::to_string(b) + " is not the transpose of its partner";
+          return VGTB_E_INVAL;
+        }
+      }
+  }
+  hg.na = na;
+  hg.norb = no;
+  hg.row_ptr.assign(na + 1, 0);
+  int prev_i = -1, prev_j = -1;
+  for (int t = 0; t < nb; ++t) {
+    const int b = order[t];
+    const int i = s->blk_i[b], j = s->blk_j[b];
+    if (i != prev_i || j != prev_j) {
+      hg.pair_col.push_back(j);
+      hg.img_ptr.push_back((int)(hg.img_d.size() / 3));
+      hg.row_ptr[i + 1] += 1;
+      prev_i = i;
+      prev_j = j;
+    }
+    for (int c = 0; c < 3; ++c) hg.img_d.push_back(s->blk_d[3 * b + c]);
+    for (int e = 0; e < e2; ++e) {
+      hg.img_h0.push_back(s->blk_h0[(size_t)b * e2 + e]);
+      hg.img_s.push_back(s->blk_s[(size_t)b * e2 + e]);
+    }
+  }
+  hg.img_ptr.push_back((int)(hg.img_d.size() / 3));
+  for (int i = 0; i < na; ++i) hg.row_ptr[i + 1] += hg.row_ptr[i];
+  for (int i = 0; i < na; ++i)
+    if (hg.row_ptr[i + 1] == hg.row_ptr[i]) {
+      msg = "atom " + std::to_string(i) + " has no blocks (an on-site block is required)";
+      return VGTB_E_INVAL;
+    }
+  return VGTB_OK;
+}
+
+vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &msg) {
+  if (!s || !o) { msg = "null system or options"; return VGTB_E_INVAL; }
+  if (s->n_atoms <= 0) { msg = "n_atoms must be positive"; return VGTB_E_INVAL; }
+  if (s->orbs_per_atom != 1 && s->orbs_per_atom != 4) {
+    msg = "orbs_per_atom must be 1 or 4";
+    return VGTB_E_INVAL;
+  }
+  const long long n = (long long)s->n_atoms * s->orbs_per_atom;
+  if (n > 16384) { msg = "N = n_atoms * orbs_per_atom must be <= 16384"; return VGTB_E_INVAL; }
+  if (s->n_blocks <= 0 || !s->blk_i || !s->blk_j || !s->blk_d || !s->blk_h0 || !s->blk_s) {
+    msg = "missing block arrays";
+    return VGTB_E_INVAL;
+  }
+  if (s->n_k <= 0 || !s->kpts || !s->kw) { msg = "missing k-points"; return VGTB_E_INVAL; }
+  double wsum = 0.0;
+  for (int k = 0; k < s->n_k; ++k) wsum += s->kw[k];
+  if (std::fabs(wsum - 1.0) > 1e-10) { msg = "k-point weights must sum to 1"; return VGTB_E_INVAL; }
+  double vol = 0.0;
+  {
+    const double *c = s->cell;
+    vol = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) +
+          c[2] * (c[3] * c[7] - c[4] * c[6]);
+  }
+  if (!(std::fabs(vol) > 0.0) || !std::isfinite(vol)) { msg = "degenerate cell"; return VGTB_E_INVAL; }
+  if (!std::isfinite(o->dt) || o->dt == 0.0) { msg = "dt must be finite and nonzero"; return VGTB_E_INVAL; }
+  if (o->precision < VGTB_FP64 || o->precision > VGTB_BF16X3) {
+    msg = "unknown precision";
+    return VGTB_E_INVAL;
+  }
+  if (o->precision != VGTB_FP64) {
+    msg = "reduced-precision forms are not available in this build";
+    return VGTB_E_INVAL;
+  }
+  if (o->history_capacity < 1) { msg = "history_capacity must be >= 1"; return VGTB_E_INVAL; }
+  if (o->rescale_every < 0 || o->reserved != 0) { msg = "bad options"; return VGTB_E_INVAL; }
+  if (!(s->n_electrons >= 0.0) || s->n_electrons > 2.0 * n) {
+    msg = "n_electrons out of range";
+    return VGTB_E_INVAL;
+  }
+  if (s->gamma) {
+    const int na = s->n_atoms;
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < na; ++j)
+        if (std::fabs(s->gamma[(size_t)i * na + j] - s->gamma[(size_t)j * na + i]) > 1e-12) {
+          msg = "gamma must be symmetric";
+          return VGTB_E_INVAL;
+        }
+  }
+  return VGTB_OK;
+}
+
+// Arena carving: the same walk sizes the arena (base = 0) and assigns pointers.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = reinterpret_cast<T *>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Sizes {
+  int na, no, n, nk, np, ni, cap;
+  bool scc, deviation;
+};
+
+template <typename Ctx>
+void carve(Carver &cv, const Sizes &z, Ctx *c) {
+  const size_t n2 = (size_t)z.n * z.n * z.nk;
+  const size_t e2 = (size_t)z.no * z.no;
+  c->kpts_dev = cv.template take<double>(3 * (size_t)z.nk);
+  c->kw_dev = cv.template take<double>(z.nk);
+  c->g.row_ptr = cv.template take<int>(z.na + 1);
+  c->g.pair_col = cv.template take<int>(z.np);
+  c->g.img_ptr = cv.template take<int>(z.np + 1);
+  c->g.img_d = cv.template take<double>(3 * (size_t)z.ni);
+  c->g.img_h0 = cv.template take<double>(e2 * z.ni);
+  c->g.img_s = cv.template take<double>(e2 * z.ni);
+  c->spk = cv.template take<double2>(e2 * z.np * z.nk);
+  c->sinv = cv.template take<double2>(n2);
+  c->dlev[0] = cv.template take<double2>(n2);
+  c->dlev[1] = cv.template take<double2>(n2);
+  c->d0 = z.deviation ? cv.template take<double2>(n2) : nullptr;
+  c->w = cv.template take<double2>(n2);
+  c->y = cv.template take<double2>(n2);
+  c->part = cv.template take<double>((size_t)z.nk * z.na * 5);
+  c->v = cv.template take<double>(z.na);
+  c->z = cv.template take<double>(z.na);
+  c->qbuf = cv.template take<double>(z.na);
+  c->gamma = z.scc ? cv.template take<double>((size_t)z.na * z.na) : nullptr;
+  c->hist = cv.template take<double>((size_t)z.cap * (5 + z.na));
+  c->eig = cv.template take<double>((size_t)z.nk * z.n);
+  c->eig_e = cv.template take<double>((size_t)z.nk * z.n);
+  c->occ = cv.template take<double>((size_t)z.nk * z.n);
+  c->info = cv.template take<int>(z.nk);
+  c->flag = cv.template take<int>(1);
+}
+
+// Mutable stand-in used for the size query (PairGraph members are const).
+struct SizeProbe {
+  struct {
+    int *row_ptr, *pair_col, *img_ptr;
+    double *img_d, *img_h0, *img_s;
+  } g;
+  double *kpts_dev, *kw_dev, *part, *v, *z, *qbuf, *gamma, *hist, *eig, *eig_e, *occ;
+  double2 *spk, *sinv, *dlev[2], *d0, *w, *y;
+  int *info, *flag;
+};
+
+struct DevPtrs : SizeProbe {};
+
+Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg) {
+  Sizes z;
+  z.na = s->n_atoms;
+  z.no = s->orbs_per_atom;
+  z.n = z.na * z.no;
+  z.nk = s->n_k;
+  z.np = (int)hg.pair_col.size();
+  z.ni = (int)(hg.img_d.size() / 3);
+  z.cap = o->history_capacity;
+  z.scc = s->gamma != nullptr;
+  z.deviation = o->precision != VGTB_FP64;
+  return z;
+}
+
+// Aufbau with f = 2; a degenerate group (spread < tol) straddling the Fermi
+// level shares the remaining electrons equally.  eps ascending.
+void fill_states(const double *eps, int n, double n_el, double tol, double *f) {
+  double left = n_el;
+  int i = 0;
+  for (int t = 0; t < n; ++t) f[t] = 0.0;
+  while (i < n && left > 1e-12) {
+    int j = i + 1;
+    while (j < n && std::fabs(eps[j] - eps[i]) < tol) ++j;
+    const int g = j - i;
+    const double take = std::min(2.0 * g, left);
+    for (int t = i; t < j; ++t) f[t] = take / g;
+    left -= take;
+    i = j;
+  }
+}
+
+vgtb_status check_ready(vgtb_ctx *ctx) {
+  if (!ctx) return fail(nullptr, VGTB_E_INVAL, "null context");
+  if (ctx->poisoned) return VGTB_E_STATE;
+  return VGTB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vgtb_status vgtb_workspace_size(const vgtb_system *s, const vgtb_options *o, size_t *bytes) {
+  std::string msg;
+  vgtb_status st = validate(s, o, msg);
+  if (st != VGTB_OK) return fail(nullptr, st, msg);
+  if (!bytes) return fail(nullptr, VGTB_E_INVAL, "null bytes pointer");
+  HostGraph hg;
+  st = build_graph(s, hg, msg);
+  if (st != VGTB_OK) return fail(nullptr, st, msg);
+  Carver cv(nullptr);
+  SizeProbe probe;
+  carve(cv, sizes_of(s, o, hg), &probe);
+  *bytes = cv.off + 256;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena,
+                        size_t arena_bytes, void *hip_stream, vgtb_ctx **out) {
+  std::string msg;
+  vgtb_status st = validate(s, o, msg);
+  if (st != VGTB_OK) return fail(nullptr, st, msg);
+  if (!out || !arena) return fail(nullptr, VGTB_E_INVAL, "null arena or output pointer");
+  if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0)
+    return fail(nullptr, VGTB_E_INVAL, "arena must be 256-byte aligned");
+  HostGraph hg;
+  st = build_graph(s, hg, msg);
+  if (st != VGTB_OK) return fail(nullptr, st, msg);
+  const Sizes z = sizes_of(s, o, hg);
+  {
+    Carver probe_cv(nullptr);
+    SizeProbe probe;
+    carve(probe_cv, z, &probe);
+    if (probe_cv.off + 256 > arena_bytes)
+      return fail(nullptr, VGTB_E_NOMEM, "arena too small: need " + std::to_string(probe_cv.off + 256));
+  }
+
+  vgtb_ctx *c = new vgtb_ctx();
+  c->na = z.na;
+  c->no = z.no;
+  c->n = z.n;
+  c->nk = z.nk;
+  c->hist_cap = z.cap;
+  c->scc = z.scc;
+  c->precision = o->precision;
+  c->rescale_every = o->rescale_every;
+  c->dt = o->dt;
+  c->n_electrons = s->n_electrons;
+  {
+    const double *cl = s->cell;
+    c->volume = std::fabs(cl[0] * (cl[4] * cl[8] - cl[5] * cl[7]) - cl[1] * (cl[3] * cl[8] - cl[5] * cl[6]) +
+                          cl[2] * (cl[3] * cl[7] - cl[4] * cl[6]));
+  }
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->kpts.assign(s->kpts, s->kpts + 3 * (size_t)z.nk);
+  c->kw.assign(s->kw, s->kw + z.nk);
+  c->field.assign(3, 0.0);
+  c->z_host.assign(z.na, 0.0);
+  c->z_from_ground_state = (s->z_ref == nullptr);
+  if (s->z_ref) c->z_host.assign(s->z_ref, s->z_ref + z.na);
+
+  auto bail = [&](vgtb_status code, const std::string &m) {
+    g_global_err = m;
+    if (c->blas) rocblas_destroy_handle(c->blas);
+    delete c;
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(VGTB_E_DEVICE, "hipGetDevice failed");
+
+  Carver cv(arena);
+  DevPtrs dp;
+  carve(cv, z, &dp);
+  c->kpts_dev = dp.kpts_dev;
+  c->kw_dev = dp.kw_dev;
+  c->g.n_atoms = z.na;
+  c->g.norb = z.no;
+  c->g.n_pairs = z.np;
+  c->g.n_images = z.ni;
+  c->g.row_ptr = dp.g.row_ptr;
+  c->g.pair_col = dp.g.pair_col;
+  c->g.img_ptr = dp.g.img_ptr;
+  c->g.img_d = dp.g.img_d;
+  c->g.img_h0 = dp.g.img_h0;
+  c->g.img_s = dp.g.img_s;
+  c->spk = dp.spk;
+  c->sinv = dp.sinv;
+  c->dlev[0] = dp.dlev[0];
+  c->dlev[1] = dp.dlev[1];
+  c->d0 = dp.d0;
+  c->w = dp.w;
+  c->y = dp.y;
+  c->part = dp.part;
+  c->v = dp.v;
+  c->z = dp.z;
+  c->qbuf = dp.qbuf;
+  c->gamma = dp.gamma;
+  c->hist = dp.hist;
+  c->eig = dp.eig;
+  c->eig_e = dp.eig_e;
+  c->occ = dp.occ;
+  c->info = dp.info;
+  c->flag = dp.flag;
+
+  hipStream_t st_ = c->stream;
+#define CREATE_HIP(expr)                                                              \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) return bail(VGTB_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+  } while (0)
+  CREATE_HIP(hipMemcpyAsync(dp.kpts_dev, s->kpts, 3 * sizeof(double) * z.nk, hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.kw_dev, s->kw, sizeof(double) * z.nk, hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.row_ptr, hg.row_ptr.data(), sizeof(int) * hg.row_ptr.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.pair_col, hg.pair_col.data(), sizeof(int) * hg.pair_col.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.img_ptr, hg.img_ptr.data(), sizeof(int) * hg.img_ptr.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.img_d, hg.img_d.data(), sizeof(double) * hg.img_d.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.img_h0, hg.img_h0.data(), sizeof(double) * hg.img_h0.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.img_s, hg.img_s.data(), sizeof(double) * hg.img_s.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.z, c->z_host.data(), sizeof(double) * z.na, hipMemcpyHostToDevice, st_));
+  if (z.scc)
+    CREATE_HIP(hipMemcpyAsync(dp.gamma, s->gamma, sizeof(double) * z.na * z.na, hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemsetAsync(dp.v, 0, sizeof(double) * z.na, st_));
+  CREATE_HIP(hipMemsetAsync(dp.flag, 0, sizeof(int), st_));
+
+  // S_k on the pair graph (Eq. 7), dense S_k, then S_k^-1 by Cholesky.
+  vgtb::launch_pair_bloch_s(c->g, dp.kpts_dev, z.nk, dp.spk, st_);
+  const size_t n2 = (size_t)z.n * z.n * z.nk;
+  vgtb::launch_fill_zero(dp.sinv, n2, st_);
+  vgtb::launch_scatter_pairs(c->g, dp.kpts_dev, z.nk, dp.spk, 0, dp.sinv, z.n, st_);
+  CREATE_HIP(hipGetLastError());
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return bail(VGTB_E_DEVICE, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(c->blas, st_) != rocblas_status_success)
+    return bail(VGTB_E_DEVICE, "rocblas_set_stream failed");
+  // Row-major Hermitian storage read column-major is conj(S); the factor /
+  // inverse of its column-major upper triangle is S^-1's row-major lower one.
+  if (rocsolver_zpotrf_strided_batched(c->blas, rocblas_fill_upper, z.n,
+                                       reinterpret_cast<rocblas_double_complex *>(dp.sinv), z.n,
+                                       (rocblas_stride)z.n * z.n, dp.info, z.nk) != rocblas_status_success)
+    return bail(VGTB_E_DEVICE, "rocsolver_zpotrf_strided_batched failed");
+  std::vector<int> info(z.nk);
+  CREATE_HIP(hipMemcpyAsync(info.data(), dp.info, sizeof(int) * z.nk, hipMemcpyDeviceToHost, st_));
+  CREATE_HIP(hipStreamSynchronize(st_));
+  for (int k = 0; k < z.nk; ++k)
+    if (info[k] != 0)
+      return bail(VGTB_E_NOT_PD, "S_k is not positive definite at k-point " + std::to_string(k) +
+                                     " (leading minor " + std::to_string(info[k]) + ")");
+  if (rocsolver_zpotri_strided_batched(c->blas, rocblas_fill_upper, z.n,
+                                       reinterpret_cast<rocblas_double_complex *>(dp.sinv), z.n,
+                                       (rocblas_stride)z.n * z.n, dp.info, z.nk) != rocblas_status_success)
+    return bail(VGTB_E_DEVICE, "rocsolver_zpotri_strided_batched failed");
+  vgtb::launch_hermitian_from_lower(dp.sinv, z.n, z.nk, st_);
+  CREATE_HIP(hipGetLastError());
+  CREATE_HIP(hipMemcpyAsync(info.data(), dp.info, sizeof(int) * z.nk, hipMemcpyDeviceToHost, st_));
+  CREATE_HIP(hipStreamSynchronize(st_));
+  for (int k = 0; k < z.nk; ++k)
+    if (info[k] != 0) return bail(VGTB_E_NOT_PD, "S_k is singular at k-point " + std::to_string(k));
+#undef CREATE_HIP
+  *out = c;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  const int n = c->n, nk = c->nk;
+  const size_t n2 = (size_t)n * n * nk;
+  hipStream_t s = c->stream;
+  vgtb::launch_fill_zero(c->w, n2, s);
+  vgtb::launch_scatter_pairs(c->g, c->kpts_dev, nk, c->spk, 0, c->w, n, s);
+  vgtb::launch_fill_zero(c->y, n2, s);
+  vgtb::launch_scatter_pairs(c->g, c->kpts_dev, nk, c->spk, 1, c->y, n, s);
+  HIP_TRY(c, hipGetLastError());
+  BLAS_TRY(c, rocsolver_zhegvd_strided_batched(
+                  c->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n,
+                  reinterpret_cast<rocblas_double_complex *>(c->y), n, (rocblas_stride)n * n,
+                  reinterpret_cast<rocblas_double_complex *>(c->w), n, (rocblas_stride)n * n, c->eig,
+                  n, c->eig_e, n, c->info, nk));
+  std::vector<int> info(nk);
+  std::vector<double> eps((size_t)nk * n), occ((size_t)nk * n);
+  HIP_TRY(c, hipMemcpyAsync(info.data(), c->info, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(eps.data(), c->eig, sizeof(double) * eps.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  for (int k = 0; k < nk; ++k) {
+    if (info[k] > n) return fail(c, VGTB_E_NOT_PD, "S_k not positive definite at k-point " + std::to_string(k));
+    if (info[k] != 0) return fail(c, VGTB_E_DEVICE, "eigensolver did not converge at k-point " + std::to_string(k));
+  }
+  double gap = INFINITY, width = 0.0;
+  const int n_occ = (int)std::lround(c->n_electrons / 2.0);
+  for (int k = 0; k < nk; ++k) {
+    const double *e = eps.data() + (size_t)k * n;
+    fill_states(e, n, c->n_electrons, 1e-8, occ.data() + (size_t)k * n);
+    if (n_occ > 0 && n_occ < n) gap = std::min(gap, e[n_occ] - e[n_occ - 1]);
+    width = std::max(width, e[n - 1] - e[0]);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->occ, occ.data(), sizeof(double) * occ.size(), hipMemcpyHostToDevice, s));
+  double2 *dtarget = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
+  vgtb::launch_density_from_vectors(c->y, c->occ, dtarget, n, nk, s);
+  HIP_TRY(c, hipGetLastError());
+  if (c->precision != VGTB_FP64) vgtb::launch_fill_zero(c->dlev[0], n2, s);
+  c->cur = 0;
+  c->have_density = true;
+  c->have_prev = false;
+  c->step = 0;
+  if (c->z_from_ground_state) {
+    // Reference charges = Mulliken charges of the ground state (dq = 0 at t = 0).
+    vgtb::StepField f0{0.0, 0.0, 0.0};
+    vgtb::launch_observe(c->g, dtarget, nullptr, n, c->kpts_dev, nk, f0, c->spk, c->part, s);
+    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, 0.0, nullptr, c->z, c->v, c->qbuf, c->hist,
+                        c->flag, s);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(c->z, c->qbuf, sizeof(double) * c->na, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->z_host.data(), c->qbuf, sizeof(double) * c->na, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(c, hipMemsetAsync(c->v, 0, sizeof(double) * c->na, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (min_gap) *min_gap = (n_occ > 0 && n_occ < n) ? gap : 0.0;
+  if (std::fabs(c->dt) * width >= 1.0)
+    return fail(c, VGTB_E_UNSTABLE, "|dt| * spectral width = " + std::to_string(std::fabs(c->dt) * width) + " >= 1");
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (!d) return fail(c, VGTB_E_INVAL, "null density");
+  const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
+  double2 *target = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
+  HIP_TRY(c, hipMemcpyAsync(target, d, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (c->precision != VGTB_FP64) vgtb::launch_fill_zero(c->dlev[0], (size_t)c->n * c->n * c->nk, c->stream);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->have_density = true;
+  c->have_prev = false;
+  c->step = 0;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_set_field_table(vgtb_ctx *c, int64_t n, const double *a) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (n < 1 || !a) return fail(c, VGTB_E_INVAL, "field table needs n >= 1 entries");
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(a[i])) return fail(c, VGTB_E_INVAL, "non-finite vector potential");
+  c->field.assign(a, a + 3 * n);
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_set_field(vgtb_ctx *c, const double a[3]) { return vgtb_set_field_table(c, 1, a); }
+
+vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (!c->have_density) return fail(c, VGTB_E_STATE, "vgtb_step before a density was set");
+  if (n_steps < 0) return fail(c, VGTB_E_INVAL, "negative step count");
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int n = c->n, nk = c->nk;
+  const bool dev = c->precision != VGTB_FP64;
+  const int64_t nf = (int64_t)(c->field.size() / 3);
+  const double jscale = -1.0 / (c->volume * nk);
+  hipStream_t s = c->stream;
+  for (int64_t it = 0; it < n_steps; ++it) {
+    const int64_t idx = std::min<int64_t>(c->step, nf - 1);
+    const double *a = c->field.data() + 3 * idx;
+    const vgtb::StepField f{a[0] / vgtb::kLightSpeed, a[1] / vgtb::kLightSpeed, a[2] / vgtb::kLightSpeed};
+    double2 *dcur = c->dlev[c->cur];
+    double2 *doth = c->dlev[c->cur ^ 1];
+    const double2 *ref = dev ? c->d0 : nullptr;
+    double *hrow = c->hist + (size_t)(c->step % c->hist_cap) * (5 + c->na);
+    vgtb::launch_observe(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk, c->part, s);
+    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr, c->z,
+                        c->v, c->qbuf, hrow, c->flag, s);
+    vgtb::launch_spmm(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk, c->scc ? c->v : nullptr,
+                      c->w, s);
+    vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s);
+    if (c->have_prev)
+      vgtb::launch_update(c->y, doth, doth, n, nk, 2.0 * c->dt, s);
+    else
+      vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
+    c->cur ^= 1;
+    c->have_prev = true;
+    c->step += 1;
+  }
+  HIP_TRY(c, hipGetLastError());
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_synchronize(vgtb_ctx *c) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (flag) return fail(c, VGTB_E_NONFINITE, "non-finite trace or energy observed");
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_read_observables(vgtb_ctx *c, int64_t first, int64_t count, double *j,
+                                  double *e, double *tr, double *q) {
+  vgtb_status st = vgtb_synchronize(c);
+  if (st != VGTB_OK) return st;
+  if (first < 0 || count < 0 || first + count > c->step || first < c->step - c->hist_cap)
+    return fail(c, VGTB_E_INVAL, "requested steps are not in the history ring");
+  const int row = 5 + c->na;
+  std::vector<double> ring((size_t)c->hist_cap * row);
+  HIP_TRY(c, hipMemcpy(ring.data(), c->hist, sizeof(double) * ring.size(), hipMemcpyDeviceToHost));
+  for (int64_t t = 0; t < count; ++t) {
+    const double *r = ring.data() + (size_t)((first + t) % c->hist_cap) * row;
+    if (j) for (int a = 0; a < 3; ++a) j[3 * t + a] = r[a];
+    if (e) e[t] = r[3];
+    if (tr) tr[t] = r[4];
+    if (q) std::memcpy(q + (size_t)t * c->na, r + 5, sizeof(double) * c->na);
+  }
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_get_density(vgtb_ctx *c, int32_t level, void *out, int on_device) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (!c->have_density) return fail(c, VGTB_E_STATE, "no density set");
+  if (level != 0 && level != 1) return fail(c, VGTB_E_INVAL, "level must be 0 or 1");
+  if (level == 1 && !c->have_prev) return fail(c, VGTB_E_STATE, "no previous level yet");
+  if (!out) return fail(c, VGTB_E_INVAL, "null output");
+  const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
+  const double2 *src = c->dlev[level == 0 ? c->cur : (c->cur ^ 1)];
+  HIP_TRY(c, hipMemcpyAsync(out, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_get_reference_charges(vgtb_ctx *c, double *zh) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (!zh) return fail(c, VGTB_E_INVAL, "null output");
+  std::memcpy(zh, c->z_host.data(), sizeof(double) * c->na);
+  return VGTB_OK;
+}
+
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int64_t step;
+  int32_t n, nk, na, precision, have_prev, pad;
+};
+constexpr uint64_t kStateMagic = 0x7667746273743031ull;
+}  // namespace
+
+vgtb_status vgtb_state_size(const vgtb_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return fail(nullptr, VGTB_E_INVAL, "null argument");
+  const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
+  *bytes = sizeof(StateHeader) + 3 * n2 + sizeof(double) * c->na;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_save_state(vgtb_ctx *c, void *buf, size_t bytes) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  size_t need = 0;
+  vgtb_state_size(c, &need);
+  if (!buf || bytes < need) return fail(c, VGTB_E_INVAL, "state buffer too small");
+  if (!c->have_density) return fail(c, VGTB_E_STATE, "no density set");
+  const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
+  char *p = static_cast<char *>(buf);
+  StateHeader h{kStateMagic, c->step, c->n, c->nk, c->na, c->precision, c->have_prev ? 1 : 0, 0};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  HIP_TRY(c, hipMemcpyAsync(p, c->dlev[c->cur], n2, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p + n2, c->dlev[c->cur ^ 1], n2, hipMemcpyDeviceToHost, c->stream));
+  if (c->d0) HIP_TRY(c, hipMemcpyAsync(p + 2 * n2, c->d0, n2, hipMemcpyDeviceToHost, c->stream));
+  else std::memset(p + 2 * n2, 0, n2);
+  std::memcpy(p + 3 * n2, c->z_host.data(), sizeof(double) * c->na);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_load_state(vgtb_ctx *c, const void *buf, size_t bytes) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  size_t need = 0;
+  vgtb_state_size(c, &need);
+  if (!buf || bytes < need) return fail(c, VGTB_E_INVAL, "state buffer too small");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kStateMagic || h.n != c->n || h.nk != c->nk || h.na != c->na || h.precision != c->precision)
+    return fail(c, VGTB_E_INVAL, "state does not match this context");
+  const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
+  const char *p = static_cast<const char *>(buf) + sizeof(h);
+  c->cur = 0;
+  HIP_TRY(c, hipMemcpyAsync(c->dlev[0], p, n2, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->dlev[1], p + n2, n2, hipMemcpyHostToDevice, c->stream));
+  if (c->d0) HIP_TRY(c, hipMemcpyAsync(c->d0, p + 2 * n2, n2, hipMemcpyHostToDevice, c->stream));
+  std::memcpy(c->z_host.data(), p + 3 * n2, sizeof(double) * c->na);
+  HIP_TRY(c, hipMemcpyAsync(c->z, c->z_host.data(), sizeof(double) * c->na, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->step = h.step;
+  c->have_prev = h.have_prev != 0;
+  c->have_density = true;
+  return VGTB_OK;
+}
+
+int64_t vgtb_step_index(const vgtb_ctx *c) { return c ? c->step : -1; }
+
+const char *vgtb_last_error(const vgtb_ctx *c) { return c ? c->err.c_str() : g_global_err.c_str(); }
+
+void vgtb_destroy(vgtb_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->blas) rocblas_destroy_handle(c->blas);
+  delete c;
+}
+
+vgtb_status vgtb_zgemm(const void *a, const void *b, void *cc, int32_t n, int32_t batch,
+                       void *stream) {
+  if (!a || !b || !cc || n <= 0 || batch <= 0) return fail(nullptr, VGTB_E_INVAL, "bad zgemm arguments");
+  vgtb::launch_zgemm_f64(static_cast<const double2 *>(a), static_cast<const double2 *>(b),
+                         static_cast<double2 *>(cc), n, batch, static_cast<hipStream_t>(stream));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, VGTB_E_DEVICE, hipGetErrorString(e));
+  return VGTB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal declarations of the gfx950 propagator: context layout and the
+// host-side launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vgtb.h"
+
+namespace vgtb {
+
+constexpr double kLightSpeed = 137.035999084;
+
+// Device view of the real-space blocks, grouped by atom pair (I, J): pairs
+// of row atom I are row_ptr[I] .. row_ptr[I+1]-1, sorted by J; the periodic
+// images of pair p are img_ptr[p] .. img_ptr[p+1]-1.
+struct PairGraph {
+  int n_atoms = 0, norb = 0, n_pairs = 0, n_images = 0;
+  const int *row_ptr = nullptr;   // n_atoms + 1
+  const int *pair_col = nullptr;  // n_pairs
+  const int *img_ptr = nullptr;   // n_pairs + 1
+  const double *img_d = nullptr;  // n_images * 3
+  const double *img_h0 = nullptr; // n_images * norb^2
+  const double *img_s = nullptr;  // n_images * norb^2
+};
+
+// Per-step scalar inputs shared by the assembly / observable kernels.
+struct StepField {
+  double ax, ay, az;   // A(t_n) / c
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+void launch_fill_zero(double2 *p, size_t n, hipStream_t s);
+void launch_pair_bloch_s(const PairGraph &g, const double *kpts, int nk, double2 *spk,
+                         hipStream_t s);
+void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                          int which, double2 *dense, int n, hipStream_t s);
+void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int n,
+                    const double *kpts, int nk, StepField f, const double2 *spk, double *part,
+                    hipStream_t s);
+void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
+                   const double *gamma, const double *z, double *v, double *qbuf,
+                   double *hist_row, int *flag, hipStream_t s);
+void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
+                 const double *kpts, int nk, StepField f, const double2 *spk, const double *v,
+                 double2 *w, hipStream_t s);
+void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
+                   double fac, hipStream_t s);
+void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s);
+void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
+                                 int nk, hipStream_t s);
+
+// ---- launchers (gemm_f64.hip) ----------------------------------------------
+void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int batch,
+                      hipStream_t s);
+
+}  // namespace vgtb
+
+struct vgtb_ctx {
+  // sizes
+  int na = 0, no = 0, n = 0, nk = 0;
+  double volume = 0.0, n_electrons = 0.0, dt = 0.0;
+  int precision = 0, rescale_every = 0, hist_cap = 1;
+  bool scc = false, z_from_ground_state = false;
+
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  int device = 0;
+
+  // host copies
+  std::vector<double> kpts, kw, field;  // field: n_field * 3 (A, not A/c)
+  std::vector<double> z_host;
+
+  // device memory (carved from the caller's arena)
+  vgtb::PairGraph g;
+  double *kpts_dev = nullptr, *kw_dev = nullptr;
+  double2 *spk = nullptr;      // nk * n_pairs * norb^2
+  double2 *sinv = nullptr;     // nk * n * n
+  double2 *dlev[2] = {nullptr, nullptr};
+  double2 *d0 = nullptr;       // reference density (deviation forms)
+  double2 *w = nullptr;        // nk * n * n
+  double2 *y = nullptr;        // nk * n * n
+  double *part = nullptr;      // nk * na * 5
+  double *v = nullptr;         // na
+  double *z = nullptr;         // na
+  double *qbuf = nullptr;      // na
+  double *gamma = nullptr;     // na * na
+  double *hist = nullptr;      // hist_cap * (5 + na)
+  double *eig = nullptr;       // nk * n
+  double *eig_e = nullptr;     // nk * n
+  double *occ = nullptr;       // nk * n
+  int *info = nullptr;         // nk
+  int *flag = nullptr;         // 1
+
+  // propagation state
+  int cur = 0;                 // dlev[cur] = D_n
+  bool have_density = false, have_prev = false, poisoned = false;
+  int64_t step = 0;
+  std::string err;
+};

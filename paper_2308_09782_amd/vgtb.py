@@ -1,0 +1,299 @@
+"""ctypes binding of libvgtb.so (the C ABI declared in include/vgtb.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch provides the device arena, output tensors and the stream.
+The binding refuses to run without the built library and a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvgtb.so")
+
+VGTB_OK, VGTB_E_INVAL, VGTB_E_STATE, VGTB_E_NOT_PD, VGTB_E_UNSTABLE, VGTB_E_NOMEM, \
+    VGTB_E_DEVICE, VGTB_E_NONFINITE = range(8)
+STATUS_NAMES = {0: "VGTB_OK", 1: "VGTB_E_INVAL", 2: "VGTB_E_STATE", 3: "VGTB_E_NOT_PD",
+                4: "VGTB_E_UNSTABLE", 5: "VGTB_E_NOMEM", 6: "VGTB_E_DEVICE", 7: "VGTB_E_NONFINITE"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTED = [
+    "vgtb_workspace_size", "vgtb_create", "vgtb_ground_state", "vgtb_set_density",
+    "vgtb_set_field_table", "vgtb_set_field", "vgtb_step", "vgtb_synchronize",
+    "vgtb_read_observables", "vgtb_get_density", "vgtb_get_reference_charges",
+    "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
+    "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm",
+]
+
+
+class VgtbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class VgtbSystem(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int32), ("orbs_per_atom", ctypes.c_int32),
+        ("cell", ctypes.c_double * 9), ("n_blocks", ctypes.c_int32),
+        ("blk_i", ctypes.c_void_p), ("blk_j", ctypes.c_void_p), ("blk_d", ctypes.c_void_p),
+        ("blk_h0", ctypes.c_void_p), ("blk_s", ctypes.c_void_p), ("n_k", ctypes.c_int32),
+        ("kpts", ctypes.c_void_p), ("kw", ctypes.c_void_p), ("n_electrons", ctypes.c_double),
+        ("z_ref", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+    ]
+
+
+class VgtbOptions(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("rescale_every", ctypes.c_int32), ("history_capacity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libvgtb.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2308_09782_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "vgtb_workspace_size": [vp, vp, ctypes.POINTER(sz)],
+        "vgtb_create": [vp, vp, vp, sz, vp, ctypes.POINTER(vp)],
+        "vgtb_ground_state": [vp, ctypes.POINTER(ctypes.c_double)],
+        "vgtb_set_density": [vp, vp, ctypes.c_int],
+        "vgtb_set_field_table": [vp, i64, vp],
+        "vgtb_set_field": [vp, vp],
+        "vgtb_step": [vp, i64],
+        "vgtb_synchronize": [vp],
+        "vgtb_read_observables": [vp, i64, i64, vp, vp, vp, vp],
+        "vgtb_get_density": [vp, i32, vp, ctypes.c_int],
+        "vgtb_get_reference_charges": [vp, vp],
+        "vgtb_state_size": [vp, ctypes.POINTER(sz)],
+        "vgtb_save_state": [vp, vp, sz],
+        "vgtb_load_state": [vp, vp, sz],
+        "vgtb_zgemm": [vp, vp, vp, i32, i32, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.vgtb_step_index.argtypes = [vp]
+    lib.vgtb_step_index.restype = i64
+    lib.vgtb_last_error.argtypes = [vp]
+    lib.vgtb_last_error.restype = ctypes.c_char_p
+    lib.vgtb_destroy.argtypes = [vp]
+    lib.vgtb_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status != VGTB_OK:
+        msg = load_library().vgtb_last_error(ctx)
+        raise VgtbError(status, msg.decode() if msg else "")
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the vgtb library needs a ROCm GPU; none is visible")
+    return torch
+
+
+def make_system_struct(system):
+    """Pack a tight-binding system (vgtb_synth.TBSystem or alike) into the C struct.
+
+    Returns (struct, keepalive) - keep the second object alive during the call.
+    """
+    arrs = {
+        "blk_i": np.ascontiguousarray(system.blk_i, dtype=np.int32),
+        "blk_j": np.ascontiguousarray(system.blk_j, dtype=np.int32),
+        "blk_d": np.ascontiguousarray(system.blk_d, dtype=np.float64),
+        "blk_h0": np.ascontiguousarray(system.blk_h0, dtype=np.float64),
+        "blk_s": np.ascontiguousarray(system.blk_s, dtype=np.float64),
+        "kpts": np.ascontiguousarray(system.kpts, dtype=np.float64),
+        "kw": np.ascontiguousarray(system.kw, dtype=np.float64),
+        "z_ref": None if system.z_ref is None else np.ascontiguousarray(system.z_ref, np.float64),
+        "gamma": None if system.gamma is None else np.ascontiguousarray(system.gamma, np.float64),
+    }
+    s = VgtbSystem()
+    s.n_atoms = int(system.pos.shape[0])
+    s.orbs_per_atom = int(system.norb)
+    cell = np.ascontiguousarray(system.cell, dtype=np.float64).reshape(9)
+    for i in range(9):
+        s.cell[i] = float(cell[i])
+    s.n_blocks = int(arrs["blk_i"].shape[0])
+    s.n_k = int(arrs["kpts"].shape[0])
+    s.n_electrons = float(system.n_electrons)
+    for name in ("blk_i", "blk_j", "blk_d", "blk_h0", "blk_s", "kpts", "kw", "z_ref", "gamma"):
+        setattr(s, name, _ptr(arrs[name]))
+    return s, arrs
+
+
+def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
+                 history_capacity: int = 1024) -> VgtbOptions:
+    o = VgtbOptions()
+    o.dt = float(dt)
+    o.precision = PRECISIONS[precision]
+    o.rescale_every = int(rescale_every)
+    o.history_capacity = int(history_capacity)
+    o.reserved = 0
+    return o
+
+
+def vgtb_workspace_size(system, options: VgtbOptions) -> int:
+    lib = load_library()
+    s, keep = make_system_struct(system)
+    out = ctypes.c_size_t(0)
+    _check(lib.vgtb_workspace_size(ctypes.byref(s), ctypes.byref(options), ctypes.byref(out)))
+    del keep
+    return int(out.value)
+
+
+def vgtb_zgemm(a, b, c, stream=None):
+    """c[k] = a[k] @ b[k] for complex128 CUDA tensors of shape (batch, n, n)."""
+    torch = _torch()
+    lib = load_library()
+    for t in (a, b, c):
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("vgtb_zgemm needs contiguous complex128 device tensors")
+    if not (a.shape == b.shape == c.shape and a.dim() == 3 and a.shape[1] == a.shape[2]):
+        raise ValueError("vgtb_zgemm needs three (batch, n, n) tensors of one shape")
+    st = torch.cuda.current_stream(a.device).cuda_stream if stream is None else stream
+    _check(lib.vgtb_zgemm(a.data_ptr(), b.data_ptr(), c.data_ptr(), int(a.shape[1]),
+                          int(a.shape[0]), st))
+
+
+class Propagator:
+    """One propagation context: device arena, stream and the C handle."""
+
+    def __init__(self, system, dt: float, precision: str = "fp64", rescale_every: int = 50,
+                 history_capacity: int = 1024, device: str = "cuda:0"):
+        torch = _torch()
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.n_atoms = int(system.pos.shape[0])
+        self.norb = int(system.norb)
+        self.n = self.n_atoms * self.norb
+        self.n_k = int(np.asarray(system.kpts).shape[0])
+        self.precision = precision
+        self.options = make_options(dt, precision, rescale_every, history_capacity)
+        s, keep = make_system_struct(system)
+        with torch.cuda.device(self.device):
+            size = ctypes.c_size_t(0)
+            _check(self.lib.vgtb_workspace_size(ctypes.byref(s), ctypes.byref(self.options),
+                                                ctypes.byref(size)))
+            self.arena = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=self.device)
+            base = self.arena.data_ptr()
+            aligned = (base + 255) & ~255
+            self.stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _check(self.lib.vgtb_create(ctypes.byref(s), ctypes.byref(self.options), aligned,
+                                        int(size.value), self.stream.cuda_stream, ctypes.byref(h)))
+        del keep
+        self.ctx = h
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.vgtb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls ---------------------------------------------------------------
+    def ground_state(self) -> float:
+        gap = ctypes.c_double(0.0)
+        _check(self.lib.vgtb_ground_state(self.ctx, ctypes.byref(gap)), self.ctx)
+        return float(gap.value)
+
+    def set_density(self, d):
+        torch = self._torch
+        if isinstance(d, torch.Tensor):
+            t = d.to(device=self.device, dtype=torch.complex128).contiguous()
+            self._check_shape(t.shape)
+            _check(self.lib.vgtb_set_density(self.ctx, t.data_ptr(), 1), self.ctx)
+        else:
+            a = np.ascontiguousarray(d, dtype=np.complex128)
+            self._check_shape(a.shape)
+            _check(self.lib.vgtb_set_density(self.ctx, a.ctypes.data, 0), self.ctx)
+
+    def _check_shape(self, shape):
+        if tuple(shape) != (self.n_k, self.n, self.n):
+            raise ValueError(f"density must have shape {(self.n_k, self.n, self.n)}, got {tuple(shape)}")
+
+    def set_field_table(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 3)
+        _check(self.lib.vgtb_set_field_table(self.ctx, a.shape[0], a.ctypes.data), self.ctx)
+
+    def set_field(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64).reshape(3)
+        _check(self.lib.vgtb_set_field(self.ctx, a.ctypes.data), self.ctx)
+
+    def step(self, n_steps: int):
+        _check(self.lib.vgtb_step(self.ctx, int(n_steps)), self.ctx)
+
+    def synchronize(self):
+        _check(self.lib.vgtb_synchronize(self.ctx), self.ctx)
+
+    @property
+    def step_index(self) -> int:
+        return int(self.lib.vgtb_step_index(self.ctx))
+
+    def read_observables(self, first: int = 0, count: Optional[int] = None) -> dict:
+        if count is None:
+            count = self.step_index - first
+        j = np.zeros((count, 3))
+        e = np.zeros(count)
+        tr = np.zeros(count)
+        q = np.zeros((count, self.n_atoms))
+        _check(self.lib.vgtb_read_observables(self.ctx, first, count, j.ctypes.data, e.ctypes.data,
+                                              tr.ctypes.data, q.ctypes.data), self.ctx)
+        return {"J": j, "E": e, "trace": tr, "q": q}
+
+    def get_density(self, level: int = 0):
+        torch = self._torch
+        out = torch.empty((self.n_k, self.n, self.n), dtype=torch.complex128, device=self.device)
+        _check(self.lib.vgtb_get_density(self.ctx, int(level), out.data_ptr(), 1), self.ctx)
+        return out
+
+    def reference_charges(self) -> np.ndarray:
+        z = np.zeros(self.n_atoms)
+        _check(self.lib.vgtb_get_reference_charges(self.ctx, z.ctypes.data), self.ctx)
+        return z
+
+    def save_state(self) -> bytes:
+        size = ctypes.c_size_t(0)
+        _check(self.lib.vgtb_state_size(self.ctx, ctypes.byref(size)), self.ctx)
+        buf = ctypes.create_string_buffer(int(size.value))
+        _check(self.lib.vgtb_save_state(self.ctx, buf, size.value), self.ctx)
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self.lib.vgtb_load_state(self.ctx, buf, len(blob)), self.ctx)

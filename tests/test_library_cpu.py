@@ -1,0 +1,100 @@
+"""Host-side checks of the C-ABI library (no GPU calls).
+
+The library must load, export every function include/vgtb.h declares, size
+its arena, and reject inconsistent system descriptions before touching a
+device.
+"""
+import dataclasses
+import os
+import re
+
+import numpy as np
+import pytest
+
+import vgtb_synth as vs
+
+pkg = pytest.importorskip("paper_2308_09782_amd")
+
+
+def _lib():
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libvgtb.so not built")
+    return pkg.load_library()
+
+
+def test_header_symbols_exported(repo_root):
+    lib = _lib()
+    header = open(os.path.join(repo_root, "include", "vgtb.h")).read()
+    declared = set(re.findall(r"^\s*(?:vgtb_status|int64_t|const char \*|void)\s*\*?\s*(vgtb_\w+)\s*\(",
+                              header, flags=re.M))
+    assert declared == set(pkg.EXPORTED), declared ^ set(pkg.EXPORTED)
+    for name in declared:
+        assert getattr(lib, name) is not None
+
+
+def test_workspace_size_scales():
+    _lib()
+    opts = pkg.make_options(0.2)
+    small = pkg.vgtb_workspace_size(vs.config_system("si8_k64"), opts)
+    mid = pkg.vgtb_workspace_size(vs.config_system("asi64_k8_scc"), opts)
+    n1, n2 = 32, 256
+    assert small >= 5 * 16 * n1 * n1 * 64
+    assert mid >= 5 * 16 * n2 * n2 * 8
+    assert pkg.vgtb_workspace_size(vs.config_system("asi64_k8_scc"), pkg.make_options(0.2, history_capacity=10)) < mid
+
+
+def _expect_inval(sysm, opts=None, match=None):
+    opts = opts or pkg.make_options(0.2)
+    with pytest.raises(pkg.VgtbError) as ei:
+        pkg.vgtb_workspace_size(sysm, opts)
+    assert ei.value.status == 1
+    if match:
+        assert match in str(ei.value)
+
+
+def test_rejects_missing_hermitian_partner():
+    _lib()
+    s = vs.config_system("si8_k64")
+    keep = np.ones(s.n_blocks, bool)
+    keep[np.nonzero(np.linalg.norm(s.blk_d, axis=1) > 0)[0][0]] = False
+    bad = dataclasses.replace(s, blk_i=s.blk_i[keep], blk_j=s.blk_j[keep], blk_d=s.blk_d[keep],
+                              blk_h0=s.blk_h0[keep], blk_s=s.blk_s[keep])
+    _expect_inval(bad, match="Hermitian partner")
+
+
+def test_rejects_non_transposed_partner():
+    _lib()
+    s = vs.config_system("si8_k64")
+    h0 = s.blk_h0.copy()
+    b = np.nonzero(np.linalg.norm(s.blk_d, axis=1) > 0)[0][0]
+    h0[b, 0, 1] += 1e-3
+    _expect_inval(dataclasses.replace(s, blk_h0=h0), match="transpose")
+
+
+def test_rejects_bad_weights_and_options():
+    _lib()
+    s = vs.config_system("si8_k64")
+    _expect_inval(dataclasses.replace(s, kw=s.kw * 1.01), match="weights")
+    _expect_inval(s, pkg.make_options(0.0), match="dt")
+    o = pkg.make_options(0.2)
+    o.history_capacity = 0
+    _expect_inval(s, o)
+    bad_atom = s.blk_j.copy()
+    bad_atom[3] = 99
+    _expect_inval(dataclasses.replace(s, blk_j=bad_atom), match="outside")
+
+
+def test_rejects_asymmetric_gamma():
+    _lib()
+    s = vs.random_cell(5, seed=4, gamma_u=0.25)
+    g = s.gamma.copy()
+    g[0, 1] += 0.1
+    _expect_inval(dataclasses.replace(s, gamma=g), match="symmetric")
+
+
+def test_product_path_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(RuntimeError):
+        pkg.Propagator(vs.config_system("si8_k64"), 0.2)

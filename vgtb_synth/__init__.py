@@ -17,6 +17,7 @@ from .systems import (  # noqa: F401
     diamond_supercell,
     amorphous_si,
     linear_chain,
+    random_cell,
     primitive_diamond,
     gamma_mesh,
     config_system,

@@ -331,3 +331,31 @@ def config_system(name: str) -> TBSystem:
     if c["kind"] == "crystal":
         return diamond_supercell(c["ncell"], c["kmesh"], c["n_electrons"], c["seed"], u, name)
     return amorphous_si(c["ncell"], c["kmesh"], 0.3, c["seed"], u, c["n_electrons"], name)
+
+
+def random_cell(n_atoms: int, kmesh=(1, 1, 1), seed: int = 7, gamma_u=None,
+                n_electrons=None, min_dist: float = 3.6, name=None) -> TBSystem:
+    """n_atoms at seeded random positions in a cubic cell of silicon density.
+
+    Used for ragged sizes (N not a multiple of any tile) and disordered tests.
+    """
+    ss = np.random.SeedSequence(seed).spawn(3)
+    rng = np.random.default_rng(ss[0])
+    side = (n_atoms * A_SI ** 3 / 8.0) ** (1.0 / 3.0)
+    cell = np.eye(3) * side
+    pos = []
+    imgs = _images(cell, 0.0)
+    while len(pos) < n_atoms:
+        p = rng.uniform(0.0, side, 3)
+        ok = True
+        for q in pos:
+            if np.min(np.linalg.norm(p - q + imgs, axis=1)) < min_dist:
+                ok = False
+                break
+        if ok:
+            pos.append(p)
+    pos = np.asarray(pos)
+    vh, vs = _sk_params(ss[1], ss[2])
+    if n_electrons is None:
+        n_electrons = 4 * n_atoms
+    return _sp_system(name or f"random{n_atoms}", cell, pos, vh, vs, kmesh, n_electrons, gamma_u)
