@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Throughput of the density-matrix propagation on one MI355X.
+
+Workload: the 512-atom amorphous-Si supercell (2048 sp3 orbitals) on the
+Gamma-centred 2x2x2 mesh (8 k-points), SCC shift on, 20 fs sin^2 pulse
+(omega = 0.1 Ha, peak A = 0.05 au), dt = 0.2 au.  One step = one pass of the
+whole hot path over all k-points: observables + Mulliken + SCC shift,
+fused Peierls assembly and block-sparse H D, dense S^-1 (H D) on the matrix
+cores, and the leapfrog update.  Inputs are seeded synthetic stand-ins of
+the paper's a-Si structure (no dataset is read).
+
+Prints one JSON line: k-steps/s over the timed steps, the roofline of the
+dominant kernel (event-timed inside the library on the stream it runs on),
+and the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "asi512_k8_scc"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-k", type=int, default=2)
+    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    return ap.parse_args()
+
+
+def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    import oracle
+    from threadpoolctl import threadpool_info
+
+    sub = sysm.with_kpts(sysm.kpts[:n_k_sample])
+    rng = np.random.default_rng(0)
+    n = sysm.n_orb
+    d0 = []
+    for _ in range(n_k_sample):
+        a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        d0.append(1e-3 * 0.5 * (a + a.conj().T))
+    z = np.full(sysm.n_atoms, 4.0)
+    state = oracle.make_state(sub, d0, z)
+    t0 = time.perf_counter()
+    oracle.propagate(sub, None, atab, dt, n_steps, state=state)
+    el = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {
+        "value": n_k_sample * n_steps / el,
+        "unit": "k*steps/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{n_steps} steps x {n_k_sample} of {sysm.n_k} k-points of the same "
+                  f"{sysm.n_orb}-orbital system (numpy/BLAS FP64, {el:.1f} s)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(k-point sharding across GPUs is not part of this build)", file=sys.stderr)
+        return 2
+    import torch
+    import vgtb_synth as vs
+    import paper_2308_09782_amd as vg
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    cfg = vs.CONFIGS[args.workload]
+    sysm = vs.config_system(args.workload)
+    dt = cfg["dt"]
+    if cfg["drive"] == "pulse":
+        atab = vs.sin2_pulse_table(cfg["n_steps"], dt, cfg["omega"], cfg["t_fs"] * vs.FS_AU, cfg["a_peak"])
+    else:
+        atab = vs.kick_table(1, cfg["a0"])
+    total = args.warmup + args.steps
+    prop = vg.Propagator(sysm, dt, args.precision, history_capacity=max(total, 1))
+    t_init = time.perf_counter()
+    gap = prop.ground_state()
+    t_init = time.perf_counter() - t_init
+    # Run the warmup and the timed steps in the middle of the pulse, where A is large.
+    offset = min(2000, max(0, atab.shape[0] - total))
+    prop.set_field_table(atab[offset:])
+    prop.step(args.warmup)
+    prop.synchronize()
+
+    prop.profile(True)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        events[i].record()
+        prop.step(1)
+    events[-1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prop.synchronize()
+    prof = prop.profile_read()
+    step_ms = np.array([events[i].elapsed_time(events[i + 1]) for i in range(args.steps)])
+    obs = prop.read_observables(args.warmup, args.steps)
+
+    n, nk = sysm.n_orb, sysm.n_k
+    value = nk * args.steps / elapsed
+    gemm_ms, gemm_n = prof["gemm"]
+    gemm_avg_s = gemm_ms / max(gemm_n, 1) / 1e3
+    flops_per_launch = 8.0 * n ** 3 * nk
+    achieved = flops_per_launch / gemm_avg_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    kernels = {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1],
+                   "share": (v[0] / max(sum(x[0] for x in prof.values()), 1e-30))}
+               for k, v in prof.items() if v[1]}
+    out = {
+        "metric": "k*steps/s (512-atom a-Si, 2048 orbitals, 8 k-points)",
+        "value": value,
+        "unit": "k*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32 products, f64 state", "bf16x3": "bf16x3 products, f64 state"}[args.precision],
+        "data": "synthetic (seeded a-Si supercell, sp3 Slater-Koster blocks, sin^2 pulse)",
+        "config": {"workload": f"{args.workload}: {sysm.n_atoms}-atom a-Si, {n} orbitals, "
+                               f"{nk} k-points (2x2x2), SCC, sin^2 pulse, dt={dt}",
+                   "n_orb": n, "n_k": nk, "n_atoms": sysm.n_atoms, "precision": args.precision,
+                   "parallelism": "single GPU, all k-points batched"},
+        "roofline": {"bound": "mfma", "kernel": "zgemm (S^-1 W, all k)", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "flops_per_launch": flops_per_launch, "avg_launch_ms": gemm_avg_s * 1e3},
+        "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                            "max": float(step_ms.max())},
+        "kernels": kernels,
+        "init_s": t_init,
+        "min_gap_ha": gap,
+        "trace_drift": float(np.abs(obs["trace"] - sysm.n_electrons).max()),
+        "cpu_baseline": None,
+    }
+    prop.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysm, atab[offset:], dt, args.cpu_sample_k, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -192,6 +192,27 @@ const char *vgtb_last_error(const vgtb_ctx *ctx);
 
 void vgtb_destroy(vgtb_ctx *ctx);
 
+/* Kernel classes of one step, for vgtb_profile_read. */
+typedef enum {
+  VGTB_K_OBSERVE = 0,   /* Mulliken / energy / current sweep of D_n            */
+  VGTB_K_REDUCE = 1,    /* k-sum, SCC shift, history row                       */
+  VGTB_K_SPMM = 2,      /* fused Peierls assembly + block-sparse W = H D       */
+  VGTB_K_GEMM = 3,      /* dense Y = S^-1 W on the matrix cores (all k)        */
+  VGTB_K_UPDATE = 4,    /* leapfrog D_{n+1} = D_{n-1} - 2 i dt (Y - Y^dag)     */
+  VGTB_K_RESCALE = 5,   /* deviation forms: re-Hermitise + trace rescale       */
+  VGTB_K_COUNT = 6
+} vgtb_kernel;
+
+/*
+ * Per-kernel timing with HIP events recorded on the context stream around
+ * every launch of vgtb_step while enabled (enable != 0).  Enabling clears
+ * the totals.  vgtb_profile_read synchronises the stream and returns the
+ * summed device time (ms) and the number of launches of one kernel class.
+ */
+vgtb_status vgtb_profile_enable(vgtb_ctx *ctx, int enable);
+vgtb_status vgtb_profile_read(vgtb_ctx *ctx, int32_t kernel, double *total_ms_host,
+                              int64_t *launches_host);
+
 /*
  * Stand-alone kernel entry: C = A * B for `batch` row-major N x N complex128
  * matrices (strides N*N), on the FP64 matrix cores - the dense product

@@ -29,5 +29,6 @@ from .tddftb import (  # noqa: F401
     observables,
     propagate,
     OracleState,
+    make_state,
 )
 from .spectrum import conductivity, dielectric, absorption  # noqa: F401

@@ -185,7 +185,8 @@ class OracleState:
     z: np.ndarray
 
 
-def _init_state(sysm, d0, z) -> OracleState:
+def make_state(sysm, d0, z) -> OracleState:
+    """S_k (Eq. 7), S_k^-1 and the first time level, before any step."""
     s = [overlap_k(sysm, k) for k in sysm.kpts]
     s_inv = [overlap_inverse(x) for x in s]
     return OracleState(d_prev=None, d_cur=[np.array(x, dtype=np.complex128) for x in d0],
@@ -204,7 +205,7 @@ def propagate(sysm, d0, a_table: np.ndarray, dt: float, n_steps: int, z=None,
     if state is None:
         if z is None:
             z = np.zeros(sysm.n_atoms) if sysm.z_ref is None else sysm.z_ref
-        state = _init_state(sysm, d0, z)
+        state = make_state(sysm, d0, z)
     hist = {"J": [], "E": [], "trace": [], "q": []}
     a_table = np.asarray(a_table, float).reshape(-1, 3)
     for _ in range(n_steps):

@@ -285,6 +285,27 @@ void fill_states(const double *eps, int n, double n_el, double tol, double *f) {
   }
 }
 
+// Run one launch, bracketed by timing events when profiling is on.
+template <typename F>
+void timed(vgtb_ctx *c, int id, F &&launch) {
+  if (!c->profiling) {
+    launch();
+    return;
+  }
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (!c->ev_free.empty()) {
+    ev = c->ev_free.back();
+    c->ev_free.pop_back();
+  } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+    launch();
+    return;
+  }
+  (void)hipEventRecord(ev.first, c->stream);
+  launch();
+  (void)hipEventRecord(ev.second, c->stream);
+  c->ev_pending.push_back({id, ev.first, ev.second});
+}
+
 vgtb_status check_ready(vgtb_ctx *ctx) {
   if (!ctx) return fail(nullptr, VGTB_E_INVAL, "null context");
   if (ctx->poisoned) return VGTB_E_STATE;
@@ -563,16 +584,24 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     double2 *doth = c->dlev[c->cur ^ 1];
     const double2 *ref = dev ? c->d0 : nullptr;
     double *hrow = c->hist + (size_t)(c->step % c->hist_cap) * (5 + c->na);
-    vgtb::launch_observe(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk, c->part, s);
-    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr, c->z,
-                        c->v, c->qbuf, hrow, c->flag, s);
-    vgtb::launch_spmm(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk, c->scc ? c->v : nullptr,
-                      c->w, s);
-    vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s);
-    if (c->have_prev)
-      vgtb::launch_update(c->y, doth, doth, n, nk, 2.0 * c->dt, s);
-    else
-      vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
+    timed(c, VGTB_K_OBSERVE, [&] {
+      vgtb::launch_observe(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk, c->part, s);
+    });
+    timed(c, VGTB_K_REDUCE, [&] {
+      vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
+                          c->z, c->v, c->qbuf, hrow, c->flag, s);
+    });
+    timed(c, VGTB_K_SPMM, [&] {
+      vgtb::launch_spmm(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk,
+                        c->scc ? c->v : nullptr, c->w, s);
+    });
+    timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
+    timed(c, VGTB_K_UPDATE, [&] {
+      if (c->have_prev)
+        vgtb::launch_update(c->y, doth, doth, n, nk, 2.0 * c->dt, s);
+      else
+        vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
+    });
     c->cur ^= 1;
     c->have_prev = true;
     c->step += 1;
@@ -694,6 +723,38 @@ vgtb_status vgtb_load_state(vgtb_ctx *c, const void *buf, size_t bytes) {
   return VGTB_OK;
 }
 
+vgtb_status vgtb_profile_enable(vgtb_ctx *c, int enable) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto &e : c->ev_pending) c->ev_free.push_back({e.a, e.b});
+  c->ev_pending.clear();
+  for (int i = 0; i < VGTB_K_COUNT; ++i) {
+    c->prof_ms[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  c->profiling = enable != 0;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_profile_read(vgtb_ctx *c, int32_t kernel, double *ms, int64_t *launches) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (kernel < 0 || kernel >= VGTB_K_COUNT) return fail(c, VGTB_E_INVAL, "unknown kernel class");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto &e : c->ev_pending) {
+    float t = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&t, e.a, e.b));
+    c->prof_ms[e.id] += t;
+    c->prof_n[e.id] += 1;
+    c->ev_free.push_back({e.a, e.b});
+  }
+  c->ev_pending.clear();
+  if (ms) *ms = c->prof_ms[kernel];
+  if (launches) *launches = c->prof_n[kernel];
+  return VGTB_OK;
+}
+
 int64_t vgtb_step_index(const vgtb_ctx *c) { return c ? c->step : -1; }
 
 const char *vgtb_last_error(const vgtb_ctx *c) { return c ? c->err.c_str() : g_global_err.c_str(); }
@@ -701,6 +762,11 @@ const char *vgtb_last_error(const vgtb_ctx *c) { return c ? c->err.c_str() : g_g
 void vgtb_destroy(vgtb_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (auto &e : c->ev_pending) c->ev_free.push_back({e.a, e.b});
+  for (auto &e : c->ev_free) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
 }

@@ -96,6 +96,14 @@ struct vgtb_ctx {
   int *info = nullptr;         // nk
   int *flag = nullptr;         // 1
 
+  // per-kernel event timing (vgtb_profile_*)
+  struct EvPair { int id; hipEvent_t a, b; };
+  bool profiling = false;
+  std::vector<EvPair> ev_pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+  double prof_ms[VGTB_K_COUNT] = {0};
+  int64_t prof_n[VGTB_K_COUNT] = {0};
+
   // propagation state
   int cur = 0;                 // dlev[cur] = D_n
   bool have_density = false, have_prev = false, poisoned = false;

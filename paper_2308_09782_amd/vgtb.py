@@ -27,8 +27,9 @@ EXPORTED = [
     "vgtb_set_field_table", "vgtb_set_field", "vgtb_step", "vgtb_synchronize",
     "vgtb_read_observables", "vgtb_get_density", "vgtb_get_reference_charges",
     "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
-    "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm",
+    "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
 ]
+KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5}
 
 
 class VgtbError(RuntimeError):
@@ -82,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_save_state": [vp, vp, sz],
         "vgtb_load_state": [vp, vp, sz],
         "vgtb_zgemm": [vp, vp, vp, i32, i32, vp],
+        "vgtb_profile_enable": [vp, ctypes.c_int],
+        "vgtb_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -293,6 +296,20 @@ class Propagator:
         buf = ctypes.create_string_buffer(int(size.value))
         _check(self.lib.vgtb_save_state(self.ctx, buf, size.value), self.ctx)
         return buf.raw
+
+    def profile(self, enable: bool = True):
+        """Start (clearing totals) or stop per-kernel event timing inside vgtb_step."""
+        _check(self.lib.vgtb_profile_enable(self.ctx, 1 if enable else 0), self.ctx)
+
+    def profile_read(self) -> dict:
+        """{kernel: (total_ms, launches)} since profiling was enabled."""
+        out = {}
+        for name, kid in KERNELS.items():
+            ms = ctypes.c_double(0.0)
+            cnt = ctypes.c_int64(0)
+            _check(self.lib.vgtb_profile_read(self.ctx, kid, ctypes.byref(ms), ctypes.byref(cnt)), self.ctx)
+            out[name] = (float(ms.value), int(cnt.value))
+        return out
 
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
