@@ -1,8 +1,9 @@
-// Batched complex128 GEMM C = A * B (row-major N x N per batch entry) on the
-// gfx950 FP64 matrix cores: the dense product S_k^-1 (H_k D_k) of Eq. 6.
+// Batched complex GEMM C = A * B (row-major N x N per batch entry) on the
+// gfx950 matrix cores: the dense product S_k^-1 (H_k D_k) of Eq. 6, in
+// complex128 (v_mfma_f64_16x16x4f64) or complex64 (v_mfma_f32_16x16x4f32).
 //
-// Each complex multiply-accumulate is four real v_mfma_f64_16x16x4f64 on
-// interleaved (re, im) operands: Cr += ar br - ai bi, Ci += ar bi + ai br.
+// Each complex multiply-accumulate is four real MFMAs on interleaved
+// (re, im) operands: Cr += ar br - ai bi, Ci += ar bi + ai br.
 // A workgroup owns a BM x BN output tile; its WM x WN wavefronts each own a
 // (BM/WM) x (BN/WN) sub-tile made of 16 x 16 MFMA tiles.  Operand tiles of
 // depth BK are staged through LDS (A stored k-major so that the sixteen
@@ -16,20 +17,46 @@ namespace vgtb {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM *WN * 64) void k_zgemm_f64(const double2 *__restrict__ A,
-                                                          const double2 *__restrict__ B,
-                                                          double2 *__restrict__ C, int n,
-                                                          int tiles_m, int tiles_n) {
+// Element traits: complex type, accumulator, one 16x16x4 MFMA, and the row
+// of accumulator element j of a lane (the f64 and f32 forms differ).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using C2 = double2;
+  using Acc = v4d;
+  static __device__ inline Acc mac(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int j) { return lk + 4 * j; }
+  static __device__ inline C2 make(double x, double y) { return make_double2(x, y); }
+};
+template <> struct Mfma<float> {
+  using C2 = float2;
+  using Acc = v4f;
+  static __device__ inline Acc mac(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int j) { return 4 * lk + j; }
+  static __device__ inline C2 make(float x, float y) { return make_float2(x, y); }
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM *WN * 64) void k_zgemm(const typename Mfma<T>::C2 *__restrict__ A,
+                                                      const typename Mfma<T>::C2 *__restrict__ B,
+                                                      typename Mfma<T>::C2 *__restrict__ C, int n,
+                                                      int tiles_m, int tiles_n) {
+  using M = Mfma<T>;
+  using C2 = typename M::C2;
+  using Acc = typename M::Acc;
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   constexpr int LA = BM * BK / NT;   // complex elements of A per thread per stage
   constexpr int LB = BN * BK / NT;
   static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "tile / thread mismatch");
-  __shared__ double2 As[2][BK][BM + 1];
-  __shared__ double2 Bs[2][BK][BN + 1];
+  __shared__ C2 As[2][BK][BM + 1];
+  __shared__ C2 Bs[2][BK][BN + 1];
 
   // XCD-aware tile order: consecutive workgroup ids land on different XCDs,
   // so give each XCD a contiguous run of tiles (same A rows, same batch).
@@ -43,9 +70,9 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm_f64(const double2 *__rest
   const int bn = (tile % tiles_n) * BN;
 
   const size_t boff = (size_t)batch * n * n;
-  const double2 *Ab = A + boff;
-  const double2 *Bb = B + boff;
-  double2 *Cb = C + boff;
+  const C2 *Ab = A + boff;
+  const C2 *Bb = B + boff;
+  C2 *Cb = C + boff;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -53,30 +80,31 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm_f64(const double2 *__rest
   const int wm0 = (wave / WN) * (BM / WM);
   const int wn0 = (wave % WN) * (BN / WN);
 
-  v4d cr[TM][TN], ci[TM][TN];
+  Acc cr[TM][TN], ci[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
-      cr[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-      ci[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      cr[a][b] = Acc{0, 0, 0, 0};
+      ci[a][b] = Acc{0, 0, 0, 0};
     }
 
-  double2 ra[LA], rb[LB];
+  const C2 zero = M::make(0, 0);
+  C2 ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int L = tid + i * NT;
       const int m = L / BK, kk = L % BK;
       const int gm = bm + m, gk = k0 + kk;
-      ra[i] = (gm < n && gk < n) ? Ab[(size_t)gm * n + gk] : make_double2(0.0, 0.0);
+      ra[i] = (gm < n && gk < n) ? Ab[(size_t)gm * n + gk] : zero;
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int L = tid + i * NT;
       const int kk = L / BN, c = L % BN;
       const int gk = k0 + kk, gc = bn + c;
-      rb[i] = (gk < n && gc < n) ? Bb[(size_t)gk * n + gc] : make_double2(0.0, 0.0);
+      rb[i] = (gk < n && gc < n) ? Bb[(size_t)gk * n + gc] : zero;
     }
   };
   auto store = [&](int buf) {
@@ -102,7 +130,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm_f64(const double2 *__rest
     if (kt + 1 < nkt) load((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double2 fa[TM], fb[TN];
+      C2 fa[TM], fb[TN];
 #pragma unroll
       for (int a = 0; a < TM; ++a) fa[a] = As[buf][ks + lk][wm0 + a * 16 + lr];
 #pragma unroll
@@ -111,15 +139,15 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm_f64(const double2 *__rest
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].x, cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].y, ci[a][b], 0, 0, 0);
+          cr[a][b] = M::mac(fa[a].x, fb[b].x, cr[a][b]);
+          ci[a][b] = M::mac(fa[a].x, fb[b].y, ci[a][b]);
         }
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fa[a].y, fb[b].y, cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].y, fb[b].x, ci[a][b], 0, 0, 0);
+          cr[a][b] = M::mac(-fa[a].y, fb[b].y, cr[a][b]);
+          ci[a][b] = M::mac(fa[a].y, fb[b].x, ci[a][b]);
         }
     }
     if (kt + 1 < nkt) store(buf ^ 1);
@@ -127,24 +155,25 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm_f64(const double2 *__rest
     buf ^= 1;
   }
 
-  // Output layout of the 16x16 f64 MFMA: element j of a lane is row lane/16 + 4*j,
-  // column lane%16.
+  // Output layout: element j of a lane is row M::row(lane/16, j), column lane%16
+  // (f64: lane/16 + 4j; f32: 4 (lane/16) + j).
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = bm + wm0 + a * 16 + lk + 4 * j;
+        const int row = bm + wm0 + a * 16 + M::row(lk, j);
         const int col = bn + wn0 + b * 16 + lr;
-        if (row < n && col < n) Cb[(size_t)row * n + col] = make_double2(cr[a][b][j], ci[a][b][j]);
+        if (row < n && col < n) Cb[(size_t)row * n + col] = M::make(cr[a][b][j], ci[a][b][j]);
       }
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
-void run(const double2 *a, const double2 *b, double2 *c, int n, int batch, hipStream_t s) {
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+void run(const typename Mfma<T>::C2 *a, const typename Mfma<T>::C2 *b, typename Mfma<T>::C2 *c,
+         int n, int batch, hipStream_t s) {
   const int tm = (n + BM - 1) / BM, tn = (n + BN - 1) / BN;
-  hipLaunchKernelGGL((k_zgemm_f64<BM, BN, BK, WM, WN>), dim3(tm * tn, batch), dim3(WM * WN * 64),
+  hipLaunchKernelGGL((k_zgemm<T, BM, BN, BK, WM, WN>), dim3(tm * tn, batch), dim3(WM * WN * 64),
                      0, s, a, b, c, n, tm, tn);
 }
 
@@ -153,9 +182,17 @@ void run(const double2 *a, const double2 *b, double2 *c, int n, int batch, hipSt
 void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int batch,
                       hipStream_t s) {
   if (n >= 1024)
-    run<64, 64, 16, 2, 2>(a, b, c, n, batch, s);
+    run<double, 64, 64, 16, 2, 2>(a, b, c, n, batch, s);
   else
-    run<32, 32, 16, 2, 2>(a, b, c, n, batch, s);
+    run<double, 32, 32, 16, 2, 2>(a, b, c, n, batch, s);
+}
+
+void launch_cgemm_f32(const float2 *a, const float2 *b, float2 *c, int n, int batch,
+                      hipStream_t s) {
+  if (n >= 1024)
+    run<float, 64, 64, 16, 2, 2>(a, b, c, n, batch, s);
+  else
+    run<float, 32, 32, 16, 2, 2>(a, b, c, n, batch, s);
 }
 
 }  // namespace vgtb

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 
 #include "vgtb_internal.h"
 
@@ -205,21 +206,40 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
   }
 }
 
+// Round-to-nearest-even float -> bf16 bits, and back.
+__device__ inline uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi).
+__device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
+  const float xf = (float)x;
+  hi = to_bf16(xf);
+  lo = to_bf16(xf - from_bf16(hi));
+}
+
 // Fused assembly + block-sparse product.  Block (column chunk, atom I, k):
 //   W[rows of I, cols] = sum_{pairs (I,J)} H_k(I,J) D_k[rows of J, cols]
 // with H_k(I,J) = sum_images exp(i(k+A/c).d) H0 + 1/2 (V_I + V_J) S_k(I,J)
 // (Eqs. 8-10) built in LDS.  DELTA: the deviation form
 //   W = H_k dD + dH_k D0,  dH_k = H_k - H0_k(A=0)
 // with exp(i(k+A/c).d) - exp(i k.d) = 2 sin(a/2) i exp(i(k.d + a/2)), a = A.d/c.
+// OUT selects the operand format of the dense product that consumes W:
+//   0: complex128 row-major; 1: complex64 row-major;
+//   2: four bf16 planes (re_hi, re_lo, im_hi, im_lo), k-packed with padded
+//      size np: W[r][c] at ((r/8)*np + c)*8 + r%8 of each plane.
 constexpr int kPairChunk = 64;
 
-template <int NO, bool DELTA>
+template <int NO, bool DELTA, int OUT>
 __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d,
                                               const double2 *__restrict__ d0, int n,
                                               const double *kpts, StepField f,
                                               const double2 *__restrict__ spk,
                                               const double *__restrict__ v,
-                                              double2 *__restrict__ w) {
+                                              void *__restrict__ wout, int np, int nk,
+                                              float2 *__restrict__ w32) {
   constexpr int E2 = NO * NO;
   __shared__ double2 hs[kPairChunk * E2];
   __shared__ double2 dhs[DELTA ? kPairChunk * E2 : 1];
@@ -298,15 +318,57 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
     __syncthreads();
   }
   if (col < n) {
+    if (OUT == 0) {
+      double2 *w = static_cast<double2 *>(wout);
 #pragma unroll
-    for (int mu = 0; mu < NO; ++mu) w[base + (size_t)(I * NO + mu) * n + col] = acc[mu];
+      for (int mu = 0; mu < NO; ++mu) w[base + (size_t)(I * NO + mu) * n + col] = acc[mu];
+    } else if (OUT == 1) {
+      float2 *w = static_cast<float2 *>(wout);
+#pragma unroll
+      for (int mu = 0; mu < NO; ++mu)
+        w[base + (size_t)(I * NO + mu) * n + col] = make_float2((float)acc[mu].x, (float)acc[mu].y);
+    } else {
+      // complex64 copy of W for the identity part of S^-1 W = W + (S^-1 - I) W
+#pragma unroll
+      for (int mu = 0; mu < NO; ++mu)
+        w32[base + (size_t)(I * NO + mu) * n + col] = make_float2((float)acc[mu].x, (float)acc[mu].y);
+      uint16_t *w = static_cast<uint16_t *>(wout);
+      const size_t plane = (size_t)nk * np * np;
+      uint16_t h[4][NO];
+#pragma unroll
+      for (int mu = 0; mu < NO; ++mu) {
+        split_bf16(acc[mu].x, h[0][mu], h[1][mu]);
+        split_bf16(acc[mu].y, h[2][mu], h[3][mu]);
+      }
+      const int r0 = I * NO;
+      const size_t off = (size_t)k * np * np + ((size_t)(r0 >> 3) * np + col) * 8 + (r0 & 7);
+      if (NO == 4) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          uint2 pk = make_uint2((uint32_t)h[p][0] | ((uint32_t)h[p][NO > 1 ? 1 : 0] << 16),
+                                (uint32_t)h[p][NO > 2 ? 2 : 0] | ((uint32_t)h[p][NO > 3 ? 3 : 0] << 16));
+          *reinterpret_cast<uint2 *>(w + p * plane + off) = pk;
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) w[p * plane + off] = h[p][0];
+      }
+    }
   }
 }
 
 // Leapfrog (Eq. 13) in the form D_out = D_base - i fac (Y - Y^dag), Y = S^-1 H D,
 // so that dD/dt = -i (Y - Y^dag) is anti-Hermitian bit for bit.  32x32 tiles;
 // the transposed partner tile of Y is staged through LDS.
-__global__ __launch_bounds__(256) void k_update(const double2 *__restrict__ y,
+// SPLIT: the product is Y = W + G with G = (S^-1 - I) W computed separately;
+// both are complex64 and are summed in FP64 here.
+// m0 (may be null): a constant term -i X0 added as fac * m0, where
+// X0 = S^-1 H0 D0 - D0 H0 S^-1 is the part of dD/dt the deviation form leaves
+// out when the reference density D0 is not stationary.
+template <typename YT, bool SPLIT>
+__global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
+                                                const float2 *__restrict__ wsplit,
+                                                const double2 *__restrict__ m0,
                                                 const double2 *dbase, double2 *dout, int n,
                                                 double fac) {
   __shared__ double2 tt[32][33];
@@ -316,19 +378,41 @@ __global__ __launch_bounds__(256) void k_update(const double2 *__restrict__ y,
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r = ty; r < 32; r += 8) {
     const int row = bj + r, c = bi + tx;
-    tt[r][tx] = (row < n && c < n) ? y[base + (size_t)row * n + c] : make_double2(0.0, 0.0);
+    double2 t = make_double2(0.0, 0.0);
+    if (row < n && c < n) {
+      const YT v = y[base + (size_t)row * n + c];
+      t = make_double2((double)v.x, (double)v.y);
+      if (SPLIT) {
+        const float2 wv = wsplit[base + (size_t)row * n + c];
+        t.x += (double)wv.x;
+        t.y += (double)wv.y;
+      }
+    }
+    tt[r][tx] = t;
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int i = bi + r, j = bj + tx;
     if (i < n && j < n) {
       const size_t idx = base + (size_t)i * n + j;
-      const double2 yv = y[idx];
+      const YT yr = y[idx];
+      double2 yv = make_double2((double)yr.x, (double)yr.y);
+      if (SPLIT) {
+        const float2 wv = wsplit[idx];
+        yv.x += (double)wv.x;
+        yv.y += (double)wv.y;
+      }
       const double2 yt = tt[tx][r];            // Y[j][i]
       const double xr = yv.x - yt.x;           // X = Y - conj(Y^T)
       const double xi = yv.y + yt.y;
       const double2 b = dbase[idx];
-      dout[idx] = make_double2(b.x + fac * xi, b.y - fac * xr);
+      double2 o = make_double2(b.x + fac * xi, b.y - fac * xr);
+      if (m0 != nullptr) {
+        const double2 mv = m0[idx];
+        o.x += fac * mv.x;
+        o.y += fac * mv.y;
+      }
+      dout[idx] = o;
     }
   }
 }
@@ -393,6 +477,136 @@ __global__ __launch_bounds__(256) void k_density_from_vectors(const double2 *__r
   }
 }
 
+// S^-1 - I in the operand format of the reduced-precision product (the
+// identity part of S^-1 W is added back exactly in the update).
+// fmt 1: complex64 row-major (n); fmt 2: four bf16 planes row-major, padded np.
+__global__ void k_convert_operand(const double2 *__restrict__ src, void *__restrict__ dst, int n,
+                                  int np, int nk, int fmt) {
+  const int k = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (fmt == 1) {
+    if (j >= n) return;
+    double2 v = src[(size_t)k * n * n + (size_t)i * n + j];
+    if (i == j) v.x -= 1.0;
+    static_cast<float2 *>(dst)[(size_t)k * n * n + (size_t)i * n + j] = make_float2((float)v.x, (float)v.y);
+  } else {
+    if (j >= np) return;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n) v = src[(size_t)k * n * n + (size_t)i * n + j];
+    if (i == j && i < n) v.x -= 1.0;
+    uint16_t rh, rl, ih, il;
+    split_bf16(v.x, rh, rl);
+    split_bf16(v.y, ih, il);
+    uint16_t *o = static_cast<uint16_t *>(dst);
+    const size_t plane = (size_t)nk * np * np;
+    const size_t idx = (size_t)k * np * np + (size_t)i * np + j;
+    o[idx] = rh;
+    o[plane + idx] = rl;
+    o[2 * plane + idx] = ih;
+    o[3 * plane + idx] = il;
+  }
+}
+
+// Per-row partial traces Re sum_{pairs of I} (D0 + dD)_{mu nu} conj(S_{mu nu}) of one level.
+template <int NO>
+__global__ __launch_bounds__(64) void k_trace_rows(PairGraph g, const double2 *__restrict__ da,
+                                                   const double2 *__restrict__ db,
+                                                   const double2 *__restrict__ d0, int n,
+                                                   const double2 *__restrict__ spk, double *tpart) {
+  constexpr int E2 = NO * NO;
+  constexpr int P = 64 / E2;
+  const int I = blockIdx.x, k = blockIdx.y, lev = blockIdx.z;
+  const double2 *d = lev ? db : da;
+  const int lane = threadIdx.x, e = lane % E2, slot = lane / E2, mu = e / NO, nu = e % NO;
+  const size_t base = (size_t)k * n * n;
+  double q = 0.0;
+  for (int p = g.row_ptr[I] + slot; p < g.row_ptr[I + 1]; p += P) {
+    const size_t idx = base + (size_t)(I * NO + mu) * n + (g.pair_col[p] * NO + nu);
+    const double2 a = d[idx], r = d0[idx], sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+    q += (a.x + r.x) * sv.x + (a.y + r.y) * sv.y;
+  }
+  q = wave_sum(q);
+  if (lane == 0) tpart[((size_t)lev * gridDim.y + k) * g.n_atoms + I] = q;
+}
+
+// mode 0: fac[lev*nk+k] = target[k] / trace(lev, k);  mode 1: target[k] = trace(0, k).
+__global__ void k_trace_factors(const double *__restrict__ tpart, double *target, double *fac,
+                                int nk, int na, int mode) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nk) return;
+  double s = 0.0;
+  for (int I = 0; I < na; ++I) s += tpart[(size_t)t * na + I];
+  if (mode == 1) {
+    if (t < nk) target[t] = s;
+  } else {
+    fac[t] = target[t % nk] / s;
+  }
+}
+
+// Both levels: D <- c * 1/2 (D + D^dag) with D = D0 + dD, stored back as a
+// deviation from D0.  Tile pairs (bi <= bj) are handled by one block so the
+// in-place update never races with its mirror.
+__global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
+                                                 const double2 *__restrict__ d0,
+                                                 const double *__restrict__ fac, int n, int nt) {
+  __shared__ double2 t1[32][33], t2[32][33];
+  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
+  if (bi > bj) return;
+  const int k = blockIdx.y, lev = blockIdx.z;
+  double2 *d = lev ? db : da;
+  const double c = fac[lev * gridDim.y + k];
+  const size_t base = (size_t)k * n * n;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i1 = bi * 32 + r, j1 = bj * 32 + tx;
+    const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+    double2 z = make_double2(0.0, 0.0), a = z, b = z;
+    if (i1 < n && j1 < n) {
+      const size_t idx = base + (size_t)i1 * n + j1;
+      a = d[idx];
+      const double2 r0 = d0[idx];
+      a.x += r0.x;
+      a.y += r0.y;
+    }
+    if (i2 < n && j2 < n) {
+      const size_t idx = base + (size_t)i2 * n + j2;
+      b = d[idx];
+      const double2 r0 = d0[idx];
+      b.x += r0.x;
+      b.y += r0.y;
+    }
+    t1[r][tx] = a;   // full D, tile (bi, bj)
+    t2[r][tx] = b;   // full D, tile (bj, bi)
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i1 = bi * 32 + r, j1 = bj * 32 + tx;
+    if (i1 < n && j1 < n) {
+      const double2 a = t1[r][tx], m = t2[tx][r];        // D[i][j], D[j][i]
+      const size_t idx = base + (size_t)i1 * n + j1;
+      const double2 r0 = d0[idx];
+      d[idx] = make_double2(c * 0.5 * (a.x + m.x) - r0.x, c * 0.5 * (a.y - m.y) - r0.y);
+    }
+    if (bi != bj) {
+      const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
+      if (i2 < n && j2 < n) {
+        const double2 b = t2[r][tx], m = t1[tx][r];
+        const size_t idx = base + (size_t)i2 * n + j2;
+        const double2 r0 = d0[idx];
+        d[idx] = make_double2(c * 0.5 * (b.x + m.x) - r0.x, c * 0.5 * (b.y - m.y) - r0.y);
+      }
+    }
+  }
+}
+
+__global__ void k_add(const double2 *__restrict__ a, const double2 *__restrict__ b,
+                      double2 *__restrict__ out, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) out[i] = make_double2(a[i].x + b[i].x, a[i].y + b[i].y);
+}
+
 inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -438,24 +652,89 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
                      gamma, z, v, qbuf, hist_row, flag);
 }
 
+template <int NO, bool DELTA, int OUT>
+static void spmm_launch(dim3 grid, int threads, hipStream_t s, const PairGraph &g,
+                        const double2 *d, const double2 *d0, int n, const double *kpts,
+                        StepField f, const double2 *spk, const double *v, void *w, int np,
+                        int nk, float2 *w32) {
+  hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f,
+                     spk, v, w, np, nk, w32);
+}
+
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
                  const double *kpts, int nk, StepField f, const double2 *spk, const double *v,
-                 double2 *w, hipStream_t s) {
+                 void *w, int out_format, int np, float2 *w32, hipStream_t s) {
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
   dim3 grid(blocks_for(n, threads), g.n_atoms, nk);
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(grid, threads, s, g, d, d0, n, kpts, f, spk, v, w, np, nk, w32)
   if (g.norb == 4) {
-    if (d0) hipLaunchKernelGGL((k_spmm<4, true>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
-    else hipLaunchKernelGGL((k_spmm<4, false>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
+    if (!d0) VG_SPMM(4, false, 0);
+    else if (out_format == 0) VG_SPMM(4, true, 0);
+    else if (out_format == 1) VG_SPMM(4, true, 1);
+    else VG_SPMM(4, true, 2);
   } else {
-    if (d0) hipLaunchKernelGGL((k_spmm<1, true>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
-    else hipLaunchKernelGGL((k_spmm<1, false>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f, spk, v, w);
+    if (!d0) VG_SPMM(1, false, 0);
+    else if (out_format == 0) VG_SPMM(1, true, 0);
+    else if (out_format == 1) VG_SPMM(1, true, 1);
+    else VG_SPMM(1, true, 2);
   }
+#undef VG_SPMM
 }
 
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
-  hipLaunchKernelGGL(k_update, grid, dim3(256), 0, s, y, dbase, dout, n, fac);
+  hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
+                     (const double2 *)nullptr, dbase, dout, n, fac);
+}
+
+void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
+                         double2 *dout, int n, int nk, double fac, hipStream_t s) {
+  dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
+  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac);
+}
+
+void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
+                         hipStream_t s) {
+  dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
+  hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
+                     (const double2 *)nullptr, dbase, dout, n, 1.0);
+}
+
+void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,
+                            hipStream_t s) {
+  const int cols = fmt == 1 ? n : np;
+  const int rows = fmt == 1 ? n : np;
+  hipLaunchKernelGGL(k_convert_operand, dim3(blocks_for(cols, 256), rows, nk), dim3(256), 0, s, src,
+                     dst, n, np, nk, fmt);
+}
+
+void launch_trace_target(const PairGraph &g, const double2 *dd, const double2 *d0, int n, int nk,
+                         const double2 *spk, double *tpart, double *target, hipStream_t s) {
+  dim3 grid(g.n_atoms, nk, 2);
+  if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, dd, dd, d0, n, spk, tpart);
+  else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, dd, dd, d0, n, spk, tpart);
+  hipLaunchKernelGGL(k_trace_factors, dim3(blocks_for(2 * nk, 64)), dim3(64), 0, s, tpart, target,
+                     (double *)nullptr, nk, g.n_atoms, 1);
+}
+
+void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 *d0, int n, int nk,
+                    const double2 *spk, double *tpart, const double *target, double *fac,
+                    hipStream_t s) {
+  dim3 grid(g.n_atoms, nk, 2);
+  if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, da, db, d0, n, spk, tpart);
+  else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, da, db, d0, n, spk, tpart);
+  hipLaunchKernelGGL(k_trace_factors, dim3(blocks_for(2 * nk, 64)), dim3(64), 0, s, tpart,
+                     const_cast<double *>(target), fac, nk, g.n_atoms, 0);
+  const int nt = (int)blocks_for(n, 32);
+  hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, d0, fac, n, nt);
+}
+
+void launch_add(const double2 *a, const double2 *b, double2 *out, size_t count, hipStream_t s) {
+  unsigned blk = blocks_for(count, 256);
+  if (blk > 65536u) blk = 65536u;
+  if (blk == 0) return;
+  hipLaunchKernelGGL(k_add, dim3(blk), dim3(256), 0, s, a, b, out, count);
 }
 
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s) {

@@ -168,10 +168,6 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
     msg = "unknown precision";
     return VGTB_E_INVAL;
   }
-  if (o->precision != VGTB_FP64) {
-    msg = "reduced-precision forms are not available in this build";
-    return VGTB_E_INVAL;
-  }
   if (o->history_capacity < 1) { msg = "history_capacity must be >= 1"; return VGTB_E_INVAL; }
   if (o->rescale_every < 0 || o->reserved != 0) { msg = "bad options"; return VGTB_E_INVAL; }
   if (!(s->n_electrons >= 0.0) || s->n_electrons > 2.0 * n) {
@@ -205,7 +201,7 @@ struct Carver {
 };
 
 struct Sizes {
-  int na, no, n, nk, np, ni, cap;
+  int na, no, n, nk, np, ni, cap, precision, npad;
   bool scc, deviation;
 };
 
@@ -239,6 +235,23 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->occ = cv.template take<double>((size_t)z.nk * z.n);
   c->info = cv.template take<int>(z.nk);
   c->flag = cv.template take<int>(1);
+  if (z.deviation) {
+    const size_t lo = (z.precision == VGTB_FP32) ? n2 * sizeof(float2)
+                                                  : (size_t)4 * z.npad * z.npad * z.nk * sizeof(uint16_t);
+    c->sinv_lo = cv.template take<char>(lo);
+    c->w_lo = cv.template take<char>(lo);
+    c->y_lo = cv.template take<float2>(n2);
+    c->w32 = (z.precision == VGTB_BF16X3) ? cv.template take<float2>(n2) : nullptr;
+    c->tpart = cv.template take<double>((size_t)2 * z.nk * z.na);
+    c->tfac = cv.template take<double>((size_t)2 * z.nk);
+    c->trace0 = cv.template take<double>(z.nk);
+    c->m0 = cv.template take<double2>(n2);
+  } else {
+    c->m0 = nullptr;
+    c->sinv_lo = c->w_lo = nullptr;
+    c->y_lo = c->w32 = nullptr;
+    c->tpart = c->tfac = c->trace0 = nullptr;
+  }
 }
 
 // Mutable stand-in used for the size query (PairGraph members are const).
@@ -250,6 +263,10 @@ struct SizeProbe {
   double *kpts_dev, *kw_dev, *part, *v, *z, *qbuf, *gamma, *hist, *eig, *eig_e, *occ;
   double2 *spk, *sinv, *dlev[2], *d0, *w, *y;
   int *info, *flag;
+  void *sinv_lo, *w_lo;
+  float2 *y_lo, *w32;
+  double *tpart, *tfac, *trace0;
+  double2 *m0;
 };
 
 struct DevPtrs : SizeProbe {};
@@ -265,6 +282,8 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.cap = o->history_capacity;
   z.scc = s->gamma != nullptr;
   z.deviation = o->precision != VGTB_FP64;
+  z.precision = o->precision;
+  z.npad = (z.n + 63) / 64 * 64;
   return z;
 }
 
@@ -416,6 +435,15 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->occ = dp.occ;
   c->info = dp.info;
   c->flag = dp.flag;
+  c->np = z.npad;
+  c->sinv_lo = dp.sinv_lo;
+  c->w_lo = dp.w_lo;
+  c->y_lo = dp.y_lo;
+  c->w32 = dp.w32;
+  c->tpart = dp.tpart;
+  c->tfac = dp.tfac;
+  c->trace0 = dp.trace0;
+  c->m0 = dp.m0;
 
   hipStream_t st_ = c->stream;
 #define CREATE_HIP(expr)                                                              \
@@ -472,6 +500,17 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   CREATE_HIP(hipStreamSynchronize(st_));
   for (int k = 0; k < z.nk; ++k)
     if (info[k] != 0) return bail(VGTB_E_NOT_PD, "S_k is singular at k-point " + std::to_string(k));
+  if (z.deviation) {
+    // S^-1 in the reduced-precision operand format; W's padding stays zero.
+    const int fmt = z.precision == VGTB_FP32 ? 1 : 2;
+    vgtb::launch_convert_operand(dp.sinv, dp.sinv_lo, z.n, z.npad, z.nk, fmt, st_);
+    if (fmt == 2) {
+      const size_t bytes = (size_t)4 * z.npad * z.npad * z.nk * sizeof(uint16_t);
+      vgtb::launch_fill_zero(static_cast<double2 *>(dp.w_lo), bytes / sizeof(double2), st_);
+    }
+    CREATE_HIP(hipGetLastError());
+    CREATE_HIP(hipStreamSynchronize(st_));
+  }
 #undef CREATE_HIP
   *out = c;
   return VGTB_OK;
@@ -514,7 +553,11 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
   double2 *dtarget = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
   vgtb::launch_density_from_vectors(c->y, c->occ, dtarget, n, nk, s);
   HIP_TRY(c, hipGetLastError());
-  if (c->precision != VGTB_FP64) vgtb::launch_fill_zero(c->dlev[0], n2, s);
+  if (c->precision != VGTB_FP64) {
+    vgtb::launch_fill_zero(c->dlev[0], n2, s);
+    vgtb::launch_trace_target(c->g, c->dlev[0], c->d0, n, nk, c->spk, c->tpart, c->trace0, s);
+    c->m0_active = false;   // the ground state commutes with S^-1 H0: no constant term
+  }
   c->cur = 0;
   c->have_density = true;
   c->have_prev = false;
@@ -544,7 +587,21 @@ vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   double2 *target = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
   HIP_TRY(c, hipMemcpyAsync(target, d, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-  if (c->precision != VGTB_FP64) vgtb::launch_fill_zero(c->dlev[0], (size_t)c->n * c->n * c->nk, c->stream);
+  if (c->precision != VGTB_FP64) {
+    const size_t n2 = (size_t)c->n * c->n * c->nk;
+    vgtb::launch_fill_zero(c->dlev[0], n2, c->stream);
+    vgtb::launch_trace_target(c->g, c->dlev[0], c->d0, c->n, c->nk, c->spk, c->tpart, c->trace0,
+                              c->stream);
+    // A density given by the caller need not be stationary: keep the constant
+    // part of dD/dt, m0 = -i (S^-1 H0 D0 - D0 H0 S^-1), in FP64.
+    const vgtb::StepField f0{0.0, 0.0, 0.0};
+    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->w, 0,
+                      0, nullptr, c->stream);
+    vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, c->n, c->nk, c->stream);
+    vgtb::launch_update_const(c->y, c->dlev[0], c->m0, c->n, c->nk, c->stream);
+    c->m0_active = true;
+  }
+  HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->cur = 0;
   c->have_density = true;
@@ -591,20 +648,52 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
                           c->z, c->v, c->qbuf, hrow, c->flag, s);
     });
-    timed(c, VGTB_K_SPMM, [&] {
-      vgtb::launch_spmm(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk,
-                        c->scc ? c->v : nullptr, c->w, s);
-    });
-    timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
-    timed(c, VGTB_K_UPDATE, [&] {
-      if (c->have_prev)
-        vgtb::launch_update(c->y, doth, doth, n, nk, 2.0 * c->dt, s);
-      else
-        vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
-    });
+    if (!dev) {
+      timed(c, VGTB_K_SPMM, [&] {
+        vgtb::launch_spmm(c->g, dcur, nullptr, n, c->kpts_dev, nk, f, c->spk,
+                          c->scc ? c->v : nullptr, c->w, 0, 0, nullptr, s);
+      });
+      timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
+      timed(c, VGTB_K_UPDATE, [&] {
+        if (c->have_prev)
+          vgtb::launch_update(c->y, doth, doth, n, nk, 2.0 * c->dt, s);
+        else
+          vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
+      });
+    } else {
+      // Deviation form: W = H dD + dH D0 in FP64, rounded to the product's format;
+      // S^-1 W = W + (S^-1 - I) W with only the second term in reduced precision.
+      const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
+      timed(c, VGTB_K_SPMM, [&] {
+        vgtb::launch_spmm(c->g, dcur, c->d0, n, c->kpts_dev, nk, f, c->spk,
+                          c->scc ? c->v : nullptr, c->w_lo, fmt, c->np, c->w32, s);
+      });
+      timed(c, VGTB_K_GEMM, [&] {
+        if (fmt == 1)
+          vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
+                                 static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s);
+        else
+          vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
+                                    static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s);
+      });
+      const float2 *wid = fmt == 1 ? static_cast<const float2 *>(c->w_lo) : c->w32;
+      const double2 *m0 = c->m0_active ? c->m0 : nullptr;
+      timed(c, VGTB_K_UPDATE, [&] {
+        if (c->have_prev)
+          vgtb::launch_update_split(c->y_lo, wid, m0, doth, doth, n, nk, 2.0 * c->dt, s);
+        else
+          vgtb::launch_update_split(c->y_lo, wid, m0, dcur, doth, n, nk, c->dt, s);
+      });
+    }
     c->cur ^= 1;
     c->have_prev = true;
     c->step += 1;
+    if (dev && c->rescale_every > 0 && c->step % c->rescale_every == 0) {
+      timed(c, VGTB_K_RESCALE, [&] {
+        vgtb::launch_rescale(c->g, c->dlev[c->cur], c->dlev[c->cur ^ 1], c->d0, n, nk, c->spk,
+                             c->tpart, c->trace0, c->tfac, s);
+      });
+    }
   }
   HIP_TRY(c, hipGetLastError());
   return VGTB_OK;
@@ -648,6 +737,12 @@ vgtb_status vgtb_get_density(vgtb_ctx *c, int32_t level, void *out, int on_devic
   if (!out) return fail(c, VGTB_E_INVAL, "null output");
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   const double2 *src = c->dlev[level == 0 ? c->cur : (c->cur ^ 1)];
+  if (c->precision != VGTB_FP64) {
+    // D = D0 + dD, formed in the FP64 scratch product buffer.
+    vgtb::launch_add(c->d0, src, c->y, (size_t)c->n * c->n * c->nk, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    src = c->y;
+  }
   HIP_TRY(c, hipMemcpyAsync(out, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VGTB_OK;
@@ -665,7 +760,7 @@ namespace {
 struct StateHeader {
   uint64_t magic;
   int64_t step;
-  int32_t n, nk, na, precision, have_prev, pad;
+  int32_t n, nk, na, precision, have_prev, pad;   // pad: reference carries a constant term
 };
 constexpr uint64_t kStateMagic = 0x7667746273743031ull;
 }  // namespace
@@ -686,7 +781,8 @@ vgtb_status vgtb_save_state(vgtb_ctx *c, void *buf, size_t bytes) {
   if (!c->have_density) return fail(c, VGTB_E_STATE, "no density set");
   const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   char *p = static_cast<char *>(buf);
-  StateHeader h{kStateMagic, c->step, c->n, c->nk, c->na, c->precision, c->have_prev ? 1 : 0, 0};
+  StateHeader h{kStateMagic, c->step, c->n, c->nk, c->na, c->precision, c->have_prev ? 1 : 0,
+                c->m0_active ? 1 : 0};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
   HIP_TRY(c, hipMemcpyAsync(p, c->dlev[c->cur], n2, hipMemcpyDeviceToHost, c->stream));
@@ -720,6 +816,19 @@ vgtb_status vgtb_load_state(vgtb_ctx *c, const void *buf, size_t bytes) {
   c->step = h.step;
   c->have_prev = h.have_prev != 0;
   c->have_density = true;
+  c->m0_active = false;
+  if (c->d0 && h.pad != 0) {
+    // Rebuild the constant term of a non-stationary reference (same kernels, same bits).
+    const vgtb::StepField f0{0.0, 0.0, 0.0};
+    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->w, 0,
+                      0, nullptr, c->stream);
+    vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, c->n, c->nk, c->stream);
+    vgtb::launch_fill_zero(c->w, (size_t)c->n * c->n * c->nk, c->stream);
+    vgtb::launch_update_const(c->y, c->w, c->m0, c->n, c->nk, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->m0_active = true;
+  }
   return VGTB_OK;
 }
 

@@ -45,18 +45,38 @@ void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
                    double *hist_row, int *flag, hipStream_t s);
+// out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np).
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
                  const double *kpts, int nk, StepField f, const double2 *spk, const double *v,
-                 double2 *w, hipStream_t s);
+                 void *w, int out_format, int np, float2 *w32, hipStream_t s);
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, hipStream_t s);
+// D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each);
+// m0 may be null.
+void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
+                         double2 *dout, int n, int nk, double fac, hipStream_t s);
+// D_out = D_base - i (Y - Y^dag) (used to form the constant term m0 = -i X0).
+void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
+                         hipStream_t s);
+void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,
+                            hipStream_t s);
+void launch_trace_target(const PairGraph &g, const double2 *dd, const double2 *d0, int n, int nk,
+                         const double2 *spk, double *tpart, double *target, hipStream_t s);
+void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 *d0, int n, int nk,
+                    const double2 *spk, double *tpart, const double *target, double *fac,
+                    hipStream_t s);
+void launch_add(const double2 *a, const double2 *b, double2 *out, size_t count, hipStream_t s);
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s);
 void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
                                  int nk, hipStream_t s);
 
-// ---- launchers (gemm_f64.hip) ----------------------------------------------
+// ---- launchers (gemm_mfma.hip, gemm_bf16x3.hip) ------------------------------
 void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int batch,
                       hipStream_t s);
+void launch_cgemm_f32(const float2 *a, const float2 *b, float2 *c, int n, int batch,
+                      hipStream_t s);
+void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
+                         hipStream_t s);
 
 }  // namespace vgtb
 
@@ -95,6 +115,17 @@ struct vgtb_ctx {
   double *occ = nullptr;       // nk * n
   int *info = nullptr;         // nk
   int *flag = nullptr;         // 1
+  // deviation (reduced-precision) forms
+  int np = 0;                  // padded N of the bf16 planes
+  void *sinv_lo = nullptr;     // S^-1 as complex64 (n) or 4 bf16 planes (np)
+  void *w_lo = nullptr;        // W in the same format
+  float2 *y_lo = nullptr;      // nk * n * n, G = (S^-1 - I) W
+  float2 *w32 = nullptr;       // nk * n * n, W as complex64 (bf16 form; the fp32 form uses w_lo)
+  double *tpart = nullptr;     // 2 * nk * na
+  double *tfac = nullptr;      // 2 * nk
+  double *trace0 = nullptr;    // nk
+  double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density
+  bool m0_active = false;
 
   // per-kernel event timing (vgtb_profile_*)
   struct EvPair { int id; hipEvent_t a, b; };

@@ -1,0 +1,140 @@
+"""Reduced-precision (deviation-form) GPU propagation against the FP64 oracle.
+
+Bar: the current within 1e-5 of max |J| of the FP64 oracle trajectory; the
+density Hermitian bit for bit; Tr(D S) held at N_el by the periodic rescale.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import vgtb_synth as vs
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2308_09782_amd")
+
+pytestmark = pytest.mark.gpu
+
+J_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.load_library()
+
+
+def run_gpu(sysm, atab, dt, n_steps, precision, rescale_every=50, d0=None):
+    with pkg.Propagator(sysm, dt, precision, rescale_every=rescale_every,
+                        history_capacity=max(n_steps, 1)) as p:
+        if d0 is None:
+            p.ground_state()
+        else:
+            p.set_density(np.asarray(d0))
+        p.set_field_table(atab)
+        p.step(n_steps)
+        p.synchronize()
+        hist = p.read_observables(0, n_steps)
+        cur = p.get_density(0).cpu().numpy()
+        prev = p.get_density(1).cpu().numpy()
+    return hist, cur, prev
+
+
+def j_err(h, ref):
+    return np.abs(h["J"] - ref["J"]).max() / np.abs(ref["J"]).max()
+
+
+def rho_err(cur, dref):
+    return max(np.linalg.norm(cur[k] - dref[k]) / np.linalg.norm(dref[k]) for k in range(len(dref)))
+
+
+@pytest.fixture(scope="module")
+def c1_reference():
+    c = vs.CONFIGS["si8_k64"]
+    sysm = vs.config_system("si8_k64")
+    d0, z, _ = oracle.ground_state(sysm)
+    atab = vs.kick_table(1, c["a0"])
+    ref, st = oracle.propagate(sysm, d0, atab, c["dt"], c["n_steps"], z=z)
+    return sysm, atab, c["dt"], c["n_steps"], ref, st
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_c1_mixed_current_within_tolerance(c1_reference, precision):
+    sysm, atab, dt, n, ref, st = c1_reference
+    h, cur, prev = run_gpu(sysm, atab, dt, n, precision)
+    err = j_err(h, ref)
+    print(f"{precision}: J err {err:.2e}, rho err {rho_err(cur, st.d_cur):.2e}")
+    assert err < J_TOL
+    assert rho_err(cur, st.d_cur) < 1e-4
+    for k in range(sysm.n_k):
+        assert np.array_equal(cur[k], cur[k].conj().T)
+        assert np.array_equal(prev[k], prev[k].conj().T)
+    assert np.abs(h["trace"] - sysm.n_electrons).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_c2_mixed_scc_pulse(precision):
+    c = vs.CONFIGS["asi64_k8_scc"]
+    sysm = vs.config_system("asi64_k8_scc")
+    n = 1000
+    full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
+    atab = full[1500:1500 + n]
+    d0, z, _ = oracle.ground_state(sysm)
+    ref, st = oracle.propagate(sysm, d0, atab, c["dt"], n, z=z)
+    h, cur, _ = run_gpu(sysm, atab, c["dt"], n, precision)
+    err = j_err(h, ref)
+    print(f"{precision}: J err {err:.2e}, rho err {rho_err(cur, st.d_cur):.2e}")
+    assert err < J_TOL
+    assert np.abs(h["q"] - ref["q"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_ragged_padding_and_arbitrary_start(precision):
+    """N = 52 (bf16 planes padded to 64), non-stationary start."""
+    sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
+    d0, z, _ = oracle.ground_state(sysm)
+    rng = np.random.default_rng(1)
+    start = []
+    for d in d0:
+        a = rng.normal(size=d.shape) + 1j * rng.normal(size=d.shape)
+        start.append(d + 0.002 * (a + a.conj().T))
+    sysm = dataclasses.replace(sysm, z_ref=z)
+    atab = vs.kick_table(1, 0.02)
+    ref, st = oracle.propagate(sysm, start, atab, 0.2, 400, z=z)
+    h, cur, _ = run_gpu(sysm, atab, 0.2, 400, precision, d0=np.stack(start))
+    assert j_err(h, ref) < J_TOL
+    assert rho_err(cur, st.d_cur) < 1e-4
+
+
+def test_rescale_holds_trace():
+    sysm = vs.config_system("asi64_k8_scc")
+    c = vs.CONFIGS["asi64_k8_scc"]
+    full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
+    atab = full[1500:1900]
+    h_on, _, _ = run_gpu(sysm, atab, 0.2, 400, "bf16x3", rescale_every=50)
+    h_off, _, _ = run_gpu(sysm, atab, 0.2, 400, "bf16x3", rescale_every=0)
+    drift_on = np.abs(h_on["trace"] - sysm.n_electrons)
+    drift_off = np.abs(h_off["trace"] - sysm.n_electrons)
+    # Right after each rescale the trace is back at N_el to FP64 rounding.
+    assert drift_on[50::50].max() < 1e-10
+    assert drift_off.max() >= drift_on[50::50].max()
+
+
+def test_mixed_checkpoint_resume_bitwise():
+    sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
+    atab = vs.sin2_pulse_table(400, 0.2, 0.1, 60.0, 0.3)
+    h, full, _ = run_gpu(sysm, atab, 0.2, 300, "bf16x3", rescale_every=50)
+    with pkg.Propagator(sysm, 0.2, "bf16x3", rescale_every=50, history_capacity=300) as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.step(130)
+        blob = p.save_state()
+    with pkg.Propagator(sysm, 0.2, "bf16x3", rescale_every=50, history_capacity=300) as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.load_state(blob)
+        p.step(170)
+        cur = p.get_density(0).cpu().numpy()
+    assert np.array_equal(cur, full)
