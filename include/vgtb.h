@@ -196,11 +196,12 @@ void vgtb_destroy(vgtb_ctx *ctx);
 typedef enum {
   VGTB_K_OBSERVE = 0,   /* Mulliken / energy / current sweep of D_n            */
   VGTB_K_REDUCE = 1,    /* k-sum, SCC shift, history row                       */
-  VGTB_K_SPMM = 2,      /* fused Peierls assembly + block-sparse W = H D       */
+  VGTB_K_SPMM = 2,      /* block-sparse W = H D (deviation: H dD + dH D0)      */
   VGTB_K_GEMM = 3,      /* dense Y = S^-1 W on the matrix cores (all k)        */
   VGTB_K_UPDATE = 4,    /* leapfrog D_{n+1} = D_{n-1} - 2 i dt (Y - Y^dag)     */
   VGTB_K_RESCALE = 5,   /* deviation forms: re-Hermitise + trace rescale       */
-  VGTB_K_COUNT = 6
+  VGTB_K_ASSEMBLE = 6,  /* Peierls assembly of the pair blocks of H_k(t)       */
+  VGTB_K_COUNT = 7
 } vgtb_kernel;
 
 /*

@@ -22,13 +22,12 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 packed bf16
 
-__device__ inline bf16x8 as_bf16x8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
-__device__ inline uint4 negate8(uint4 u) {
-  return make_uint4(u.x ^ 0x80008000u, u.y ^ 0x80008000u, u.z ^ 0x80008000u, u.w ^ 0x80008000u);
-}
-__device__ inline v4f mma(uint4 a, uint4 b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+__device__ inline u32x4 negate8(u32x4 u) { return u ^ 0x80008000u; }
+__device__ inline v4f mma(u32x4 a, u32x4 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
 constexpr int BM = 64, BN = 64, BK = 32;   // workgroup tile; 4 wavefronts of 32x32
@@ -40,8 +39,8 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
                                                      float2 *__restrict__ Y, int n, int np,
                                                      int batch_count, int tiles_m, int tiles_n) {
   // LDS: A [plane][row][k] (padded rows), B [plane][k/8][col][8].
-  __shared__ uint4 As[4][BM][APAD / 8];
-  __shared__ uint4 Bs[4][BK / 8][BN];
+  __shared__ u32x4 As[4][BM][APAD / 8];
+  __shared__ u32x4 Bs[4][BK / 8][BN];
 
   const int tiles = tiles_m * tiles_n;
   const int nwg = tiles * batch_count;
@@ -67,35 +66,32 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
       ci[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
-  // Per stage each thread moves 4 uint4 of A and 4 of B (4 planes x 64 x 32 bf16 each).
-  uint4 ra[4], rb[4];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int L = tid + i * NT;          // 0 .. 1023
-      const int p = L >> 8, r = (L >> 2) & 63, c = L & 3;
-      ra[i] = *reinterpret_cast<const uint4 *>(A + p * plane + boff + (size_t)(bm + r) * np + k0 + c * 8);
-      const int kb = (L >> 6) & 3, col = L & 63;
-      rb[i] = *reinterpret_cast<const uint4 *>(B + p * plane + boff + ((size_t)(k0 / 8 + kb) * np + bn + col) * 8);
-    }
-  };
-  auto store = [&]() {
+  // Per stage each thread moves 4 u32x4 of A and 4 of B (4 planes x 64 x 32 bf16 each).
+  u32x4 ra[4], rb[4];
+#define VG_LOAD64(k0)                                                                          \
+  do {                                                                                         \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                            \
+      const int L = tid + i * NT;                                                              \
+      ra[i] = *reinterpret_cast<const u32x4 *>(A + (L >> 8) * plane + boff +                   \
+                                               (size_t)(bm + ((L >> 2) & 63)) * np + (k0) + (L & 3) * 8); \
+      rb[i] = *reinterpret_cast<const u32x4 *>(B + (L >> 8) * plane + boff +                   \
+                                               ((size_t)((k0) / 8 + ((L >> 6) & 3)) * np + bn + (L & 63)) * 8); \
+    }                                                                                          \
+  } while (0)
+
+  const int nkt = np / BK;
+  VG_LOAD64(0);
+  for (int kt = 0; kt < nkt; ++kt) {
+    __syncthreads();                 // previous stage fully consumed
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int L = tid + i * NT;
       As[L >> 8][(L >> 2) & 63][L & 3] = ra[i];
       Bs[L >> 8][(L >> 6) & 3][L & 63] = rb[i];
     }
-  };
-
-  const int nkt = np / BK;
-  load(0);
-  for (int kt = 0; kt < nkt; ++kt) {
-    __syncthreads();                 // previous stage fully consumed
-    store();
     __syncthreads();
-    if (kt + 1 < nkt) load((kt + 1) * BK);
-    uint4 fa[2][4], fb[2][4];
+    if (kt + 1 < nkt) VG_LOAD64((kt + 1) * BK);
+    u32x4 fa[2][4], fb[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -107,7 +103,7 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
     // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const uint4 nih = negate8(fa[a][2]), nil = negate8(fa[a][3]);
+      const u32x4 nih = negate8(fa[a][2]), nil = negate8(fa[a][3]);
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         v4f r = cr[a][b], m = ci[a][b];
@@ -142,15 +138,141 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
         const int col = bn + wn0 + b * 16 + lr;
         if (row < n && col < n) Yb[(size_t)row * n + col] = make_float2(cr[a][b][j], ci[a][b][j]);
       }
+#undef VG_LOAD64
+}
+
+// Large tiles for np a multiple of 128: 128 x 128 per workgroup, 64 x 64 per
+// wavefront (16 MFMA tiles, 32 independent accumulators, so consecutive MFMAs
+// never wait on each other).  The twelve partial products are grouped by the
+// B plane they read, so only one B plane's fragments are live at a time.
+constexpr int BM2 = 128, BN2 = 128;
+
+__global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restrict__ A,
+                                                         const uint16_t *__restrict__ B,
+                                                         float2 *__restrict__ Y, int n, int np,
+                                                         int batch_count, int tiles_m,
+                                                         int tiles_n) {
+  __shared__ u32x4 As[4][BM2][APAD / 8];
+  __shared__ u32x4 Bs[4][BK / 8][BN2];
+
+  const int tiles = tiles_m * tiles_n;
+  const int nwg = tiles * batch_count;
+  int lin = blockIdx.x + blockIdx.y * tiles;
+  if ((nwg & 7) == 0) lin = (lin & 7) * (nwg >> 3) + (lin >> 3);
+  const int batch = lin / tiles;
+  const int tile = lin % tiles;
+  const int bm = (tile / tiles_n) * BM2;
+  const int bn = (tile % tiles_n) * BN2;
+
+  const size_t plane = (size_t)batch_count * np * np;
+  const size_t boff = (size_t)batch * np * np;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  v4f cr[4][4], ci[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      cr[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+      ci[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+
+  // Per stage: 2048 u32x4 of A (4 planes x 128 rows x 4) and 2048 of B (4 x 4 x 128).
+  u32x4 ra[8], rb[8];
+#define VG_LOAD128(k0)                                                                         \
+  do {                                                                                         \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                            \
+      const int L = tid + i * NT;                                                              \
+      ra[i] = *reinterpret_cast<const u32x4 *>(A + (L >> 9) * plane + boff +                   \
+                                               (size_t)(bm + ((L >> 2) & 127)) * np + (k0) + (L & 3) * 8); \
+      rb[i] = *reinterpret_cast<const u32x4 *>(B + (L >> 9) * plane + boff +                   \
+                                               ((size_t)((k0) / 8 + ((L >> 7) & 3)) * np + bn + (L & 127)) * 8); \
+    }                                                                                          \
+  } while (0)
+
+  const int nkt = np / BK;
+  VG_LOAD128(0);
+  for (int kt = 0; kt < nkt; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int L = tid + i * NT;
+      As[L >> 9][(L >> 2) & 127][L & 3] = ra[i];
+      Bs[L >> 9][(L >> 7) & 3][L & 127] = rb[i];
+    }
+    __syncthreads();
+    if (kt + 1 < nkt) VG_LOAD128((kt + 1) * BK);
+    u32x4 fa[4][4], nf2[4], nf3[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) fa[a][p] = As[p][wm0 + a * 16 + lr][lg];
+      nf2[a] = negate8(fa[a][2]);
+      nf3[a] = negate8(fa[a][3]);
+    }
+    // B plane 0 (re_hi): Re += Ar_hi Br_hi + Ar_lo Br_hi;  Im += Ai_hi Br_hi + Ai_lo Br_hi
+    // B plane 1 (re_lo): Re += Ar_hi Br_lo;                  Im += Ai_hi Br_lo
+    // B plane 2 (im_hi): Re -= Ai_hi Bi_hi + Ai_lo Bi_hi;  Im += Ar_hi Bi_hi + Ar_lo Bi_hi
+    // B plane 3 (im_lo): Re -= Ai_hi Bi_lo;                  Im += Ar_hi Bi_lo
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+      u32x4 fb[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fb[b] = Bs[pb][lg][wn0 + b * 16 + lr];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (pb == 0) {
+            cr[a][b] = mma(fa[a][0], fb[b], cr[a][b]);
+            ci[a][b] = mma(fa[a][2], fb[b], ci[a][b]);
+            cr[a][b] = mma(fa[a][1], fb[b], cr[a][b]);
+            ci[a][b] = mma(fa[a][3], fb[b], ci[a][b]);
+          } else if (pb == 1) {
+            cr[a][b] = mma(fa[a][0], fb[b], cr[a][b]);
+            ci[a][b] = mma(fa[a][2], fb[b], ci[a][b]);
+          } else if (pb == 2) {
+            cr[a][b] = mma(nf2[a], fb[b], cr[a][b]);
+            ci[a][b] = mma(fa[a][0], fb[b], ci[a][b]);
+            cr[a][b] = mma(nf3[a], fb[b], cr[a][b]);
+            ci[a][b] = mma(fa[a][1], fb[b], ci[a][b]);
+          } else {
+            cr[a][b] = mma(nf2[a], fb[b], cr[a][b]);
+            ci[a][b] = mma(fa[a][0], fb[b], ci[a][b]);
+          }
+        }
+    }
+  }
+
+  float2 *Yb = Y + (size_t)batch * n * n;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = bm + wm0 + a * 16 + 4 * lg + j;
+        const int col = bn + wn0 + b * 16 + lr;
+        if (row < n && col < n) Yb[(size_t)row * n + col] = make_float2(cr[a][b][j], ci[a][b][j]);
+      }
+#undef VG_LOAD128
 }
 
 }  // namespace
 
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                          hipStream_t s) {
-  const int tm = np / BM, tn = np / BN;
-  hipLaunchKernelGGL(k_cgemm_bf16x3, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
-                     tm, tn);
+  if (np % BM2 == 0 && np >= 512) {
+    const int tm = np / BM2, tn = np / BN2;
+    hipLaunchKernelGGL(k_cgemm_bf16x3_128, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np,
+                       batch, tm, tn);
+  } else {
+    const int tm = np / BM, tn = np / BN;
+    hipLaunchKernelGGL(k_cgemm_bf16x3, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
+                       tm, tn);
+  }
 }
 
 }  // namespace vgtb

@@ -89,45 +89,44 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm(const typename Mfma<T>::C
       ci[a][b] = Acc{0, 0, 0, 0};
     }
 
-  const C2 zero = M::make(0, 0);
   C2 ra[LA], rb[LB];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < LA; ++i) {
-      const int L = tid + i * NT;
-      const int m = L / BK, kk = L % BK;
-      const int gm = bm + m, gk = k0 + kk;
-      ra[i] = (gm < n && gk < n) ? Ab[(size_t)gm * n + gk] : zero;
-    }
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      const int L = tid + i * NT;
-      const int kk = L / BN, c = L % BN;
-      const int gk = k0 + kk, gc = bn + c;
-      rb[i] = (gk < n && gc < n) ? Bb[(size_t)gk * n + gc] : zero;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < LA; ++i) {
-      const int L = tid + i * NT;
-      As[buf][L % BK][L / BK] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      const int L = tid + i * NT;
-      Bs[buf][L / BN][L % BN] = rb[i];
-    }
-  };
+  // Global -> registers for the stage at depth k0 (zero outside the matrix).
+#define VG_LOAD(k0)                                                                   \
+  do {                                                                                \
+    _Pragma("unroll") for (int i = 0; i < LA; ++i) {                                  \
+      const int L = tid + i * NT;                                                     \
+      const int gm = bm + L / BK, gk = (k0) + L % BK;                                 \
+      if (gm < n && gk < n) ra[i] = Ab[(size_t)gm * n + gk];                          \
+      else ra[i] = M::make(0, 0);                                                     \
+    }                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < LB; ++i) {                                  \
+      const int L = tid + i * NT;                                                     \
+      const int gk = (k0) + L / BN, gc = bn + L % BN;                                 \
+      if (gk < n && gc < n) rb[i] = Bb[(size_t)gk * n + gc];                          \
+      else rb[i] = M::make(0, 0);                                                     \
+    }                                                                                 \
+  } while (0)
+  // Registers -> LDS buffer buf (A stored k-major).
+#define VG_STORE(buf)                                                                 \
+  do {                                                                                \
+    _Pragma("unroll") for (int i = 0; i < LA; ++i) {                                  \
+      const int L = tid + i * NT;                                                     \
+      As[buf][L % BK][L / BK] = ra[i];                                                \
+    }                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < LB; ++i) {                                  \
+      const int L = tid + i * NT;                                                     \
+      Bs[buf][L / BN][L % BN] = rb[i];                                                \
+    }                                                                                 \
+  } while (0)
 
   const int nkt = (n + BK - 1) / BK;
-  load(0);
-  store(0);
+  VG_LOAD(0);
+  VG_STORE(0);
   __syncthreads();
   int buf = 0;
   const int lr = lane & 15, lk = lane >> 4;
   for (int kt = 0; kt < nkt; ++kt) {
-    if (kt + 1 < nkt) load((kt + 1) * BK);
+    if (kt + 1 < nkt) VG_LOAD((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       C2 fa[TM], fb[TN];
@@ -150,7 +149,7 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm(const typename Mfma<T>::C
           ci[a][b] = M::mac(fa[a].y, fb[b].x, ci[a][b]);
         }
     }
-    if (kt + 1 < nkt) store(buf ^ 1);
+    if (kt + 1 < nkt) VG_STORE(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
@@ -167,6 +166,8 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm(const typename Mfma<T>::C
         const int col = bn + wn0 + b * 16 + lr;
         if (row < n && col < n) Cb[(size_t)row * n + col] = M::make(cr[a][b][j], ci[a][b][j]);
       }
+#undef VG_LOAD
+#undef VG_STORE
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>

@@ -141,9 +141,11 @@ __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__re
 }
 
 // Single workgroup: k-sums of the partials, Mulliken charges, SCC potential
-// V = gamma (q - Z) (Eq. 10), energy, current (Eq. 14) and trace; one history
-// row [Jx Jy Jz E Tr q_0 .. q_{na-1}].  Fixed summation order (deterministic).
-constexpr int kReduceThreads = 256;
+// V = gamma (q - Z) (Eq. 10, one matrix row per wavefront), energy, current
+// (Eq. 14) and trace; one history row [Jx Jy Jz E Tr q_0 .. q_{na-1}].
+// Fixed summation order throughout, so repeated runs agree bit for bit.
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceWaves = kReduceThreads / 64;
 
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ part, int nk,
                                                            int na, const double *__restrict__ kw,
@@ -154,8 +156,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
                                                            double *__restrict__ qbuf,
                                                            double *__restrict__ hist_row,
                                                            int *flag) {
-  __shared__ double red[6][kReduceThreads];
-  const int t = threadIdx.x;
+  __shared__ double red[6][kReduceWaves];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   for (int I = t; I < na; I += kReduceThreads) {
     double q = 0.0;
     for (int k = 0; k < nk; ++k) q += kw[k] * part[((size_t)k * na + I) * 5];
@@ -165,12 +167,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
   __syncthreads();
   double escc = 0.0;
   if (gamma != nullptr) {
-    for (int I = t; I < na; I += kReduceThreads) {
-      double acc = 0.0;
+    for (int I = wave; I < na; I += kReduceWaves) {
       const double *gr = gamma + (size_t)I * na;
-      for (int K = 0; K < na; ++K) acc += gr[K] * (qbuf[K] - z[K]);
-      v[I] = acc;
-      escc += 0.5 * (qbuf[I] - z[I]) * acc;
+      double acc = 0.0;
+      for (int K = lane; K < na; K += 64) acc += gr[K] * (qbuf[K] - z[K]);
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        v[I] = acc;
+        escc += 0.5 * (qbuf[I] - z[I]) * acc;
+      }
     }
   }
   double en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, tr = 0.0;
@@ -183,26 +188,31 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restr
     jy += o[3];
     jz += o[4];
   }
-  red[0][t] = en;
-  red[1][t] = jx;
-  red[2][t] = jy;
-  red[3][t] = jz;
-  red[4][t] = tr;
-  red[5][t] = escc;
-  __syncthreads();
-  for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + s];
-    }
-    __syncthreads();
+  en = wave_sum(en);
+  jx = wave_sum(jx);
+  jy = wave_sum(jy);
+  jz = wave_sum(jz);
+  tr = wave_sum(tr);
+  escc = wave_sum(escc);
+  if (lane == 0) {
+    red[0][wave] = en;
+    red[1][wave] = jx;
+    red[2][wave] = jy;
+    red[3][wave] = jz;
+    red[4][wave] = tr;
+    red[5][wave] = escc;
   }
+  __syncthreads();
   if (t == 0) {
-    hist_row[0] = red[1][0] * jscale;
-    hist_row[1] = red[2][0] * jscale;
-    hist_row[2] = red[3][0] * jscale;
-    hist_row[3] = red[0][0] + red[5][0];
-    hist_row[4] = red[4][0];
-    if (!isfinite(red[4][0]) || !isfinite(red[0][0])) *flag = 1;
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < kReduceWaves; ++w)
+      for (int c = 0; c < 6; ++c) o[c] += red[c][w];
+    hist_row[0] = o[1] * jscale;
+    hist_row[1] = o[2] * jscale;
+    hist_row[2] = o[3] * jscale;
+    hist_row[3] = o[0] + o[5];
+    hist_row[4] = o[4];
+    if (!isfinite(o[4]) || !isfinite(o[0])) *flag = 1;
   }
 }
 
@@ -220,140 +230,208 @@ __device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
   lo = to_bf16(xf - from_bf16(hi));
 }
 
-// Fused assembly + block-sparse product.  Block (column chunk, atom I, k):
-//   W[rows of I, cols] = sum_{pairs (I,J)} H_k(I,J) D_k[rows of J, cols]
-// with H_k(I,J) = sum_images exp(i(k+A/c).d) H0 + 1/2 (V_I + V_J) S_k(I,J)
-// (Eqs. 8-10) built in LDS.  DELTA: the deviation form
-//   W = H_k dD + dH_k D0,  dH_k = H_k - H0_k(A=0)
-// with exp(i(k+A/c).d) - exp(i k.d) = 2 sin(a/2) i exp(i(k.d + a/2)), a = A.d/c.
+// Fused assembly + block-sparse product W = H_k D_k (Eqs. 8-10).
+//   H_k(I,J) = sum_images exp(i(k+A/c).d) H0 + 1/2 (V_I + V_J) S_k(I,J)
+// DELTA: the deviation form W = H_k dD + dH_k D0, dH_k = H_k - H0_k(A=0), with
+// exp(i(k+A/c).d) - exp(i k.d) = 2 sin(a/2) i exp(i(k.d + a/2)), a = A.d/c.
+//
+// A workgroup owns the rows of kGroup consecutive atoms and one chunk of
+// columns (one column per thread).  It walks the union of those atoms'
+// neighbours once: each neighbour's D rows are loaded a single time and
+// applied to every group atom that pairs with it (mask bits, uniform
+// branches, accumulators indexed at compile time).  Pair blocks of H are
+// built in LDS kEntChunk neighbours at a time.
+//
 // OUT selects the operand format of the dense product that consumes W:
 //   0: complex128 row-major; 1: complex64 row-major;
 //   2: four bf16 planes (re_hi, re_lo, im_hi, im_lo), k-packed with padded
-//      size np: W[r][c] at ((r/8)*np + c)*8 + r%8 of each plane.
-constexpr int kPairChunk = 64;
+//      size np: W[r][c] at ((r/8)*np + c)*8 + r%8 of each plane; plus a
+//      complex64 copy (w32) for the identity part of S^-1 W.
+constexpr int kEntChunk = 8;
+
+template <int NO, int OUT>
+__device__ inline void store_rows(const double2 (&acc)[NO], int r0, int col, int k, int n, int np,
+                                  int nk, void *wout, float2 *w32) {
+  const size_t base = (size_t)k * n * n;
+  if (OUT == 0) {
+    double2 *w = static_cast<double2 *>(wout);
+#pragma unroll
+    for (int mu = 0; mu < NO; ++mu) w[base + (size_t)(r0 + mu) * n + col] = acc[mu];
+  } else if (OUT == 1) {
+    float2 *w = static_cast<float2 *>(wout);
+#pragma unroll
+    for (int mu = 0; mu < NO; ++mu)
+      w[base + (size_t)(r0 + mu) * n + col] = make_float2((float)acc[mu].x, (float)acc[mu].y);
+  } else {
+#pragma unroll
+    for (int mu = 0; mu < NO; ++mu)
+      w32[base + (size_t)(r0 + mu) * n + col] = make_float2((float)acc[mu].x, (float)acc[mu].y);
+    uint16_t *w = static_cast<uint16_t *>(wout);
+    const size_t plane = (size_t)nk * np * np;
+    uint16_t h[4][NO];
+#pragma unroll
+    for (int mu = 0; mu < NO; ++mu) {
+      split_bf16(acc[mu].x, h[0][mu], h[1][mu]);
+      split_bf16(acc[mu].y, h[2][mu], h[3][mu]);
+    }
+    const size_t off = (size_t)k * np * np + ((size_t)(r0 >> 3) * np + col) * 8 + (r0 & 7);
+    if (NO == 4) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        uint2 pk = make_uint2((uint32_t)h[p][0] | ((uint32_t)h[p][NO > 1 ? 1 : 0] << 16),
+                              (uint32_t)h[p][NO > 2 ? 2 : 0] | ((uint32_t)h[p][NO > 3 ? 3 : 0] << 16));
+        *reinterpret_cast<uint2 *>(w + p * plane + off) = pk;
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) w[p * plane + off] = h[p][0];
+    }
+  }
+}
+
+// Peierls assembly of the pair blocks of H_k(t) (and dH_k for DELTA) in the
+// grouped pair order q of the sparse product: hq[k][q][e].
+template <int NO, bool DELTA>
+__global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpts, StepField f,
+                                                  const double2 *__restrict__ spk,
+                                                  const double *__restrict__ v,
+                                                  double2 *__restrict__ hq,
+                                                  double2 *__restrict__ dhq) {
+  constexpr int E2 = NO * NO;
+  const int k = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n_pairs * E2) return;
+  const int q = t / E2, e = t % E2;
+  const int p = g.gp_pair[q];
+  const double k0x = kpts[3 * k], k0y = kpts[3 * k + 1], k0z = kpts[3 * k + 2];
+  double2 h = make_double2(0.0, 0.0), dh = make_double2(0.0, 0.0);
+  for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+    const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
+    const double hv = g.img_h0[(size_t)m * E2 + e];
+    const double a = f.ax * dx + f.ay * dy + f.az * dz;
+    const double kd = k0x * dx + k0y * dy + k0z * dz;
+    double sn, cs;
+    sincos(kd + a, &sn, &cs);
+    h.x += cs * hv;
+    h.y += sn * hv;
+    if (DELTA) {
+      double sh, ch;
+      sincos(kd + 0.5 * a, &sh, &ch);
+      const double amp = 2.0 * sin(0.5 * a) * hv;
+      dh.x -= amp * sh;
+      dh.y += amp * ch;
+    }
+  }
+  if (v != nullptr) {
+    const double vs = 0.5 * (v[g.pair_row[p]] + v[g.pair_col[p]]);
+    const double2 sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+    h.x += vs * sv.x;
+    h.y += vs * sv.y;
+    if (DELTA) {
+      dh.x += vs * sv.x;
+      dh.y += vs * sv.y;
+    }
+  }
+  const size_t o = ((size_t)k * g.n_pairs + q) * E2 + e;
+  hq[o] = h;
+  if (DELTA) dhq[o] = dh;
+}
 
 template <int NO, bool DELTA, int OUT>
 __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d,
                                               const double2 *__restrict__ d0, int n,
-                                              const double *kpts, StepField f,
-                                              const double2 *__restrict__ spk,
-                                              const double *__restrict__ v,
+                                              const double2 *__restrict__ hq,
+                                              const double2 *__restrict__ dhq,
                                               void *__restrict__ wout, int np, int nk,
                                               float2 *__restrict__ w32) {
   constexpr int E2 = NO * NO;
-  __shared__ double2 hs[kPairChunk * E2];
-  __shared__ double2 dhs[DELTA ? kPairChunk * E2 : 1];
-  __shared__ int cols[kPairChunk];
-  const int I = blockIdx.y, k = blockIdx.z;
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  const double k0x = kpts[3 * k], k0y = kpts[3 * k + 1], k0z = kpts[3 * k + 2];
+  constexpr int CP = kEntChunk * kGroup;       // pair blocks per chunk, at most
+  __shared__ double2 hs[CP * E2];
+  __shared__ double2 dhs[DELTA ? CP * E2 : 1];
+  __shared__ int s_j[kEntChunk], s_mask[kEntChunk], s_pp[kEntChunk];
+  const int grp = blockIdx.y, k = blockIdx.z;
+  const int I0 = grp * kGroup;
+  const int tid = threadIdx.x;
+  const int col = blockIdx.x * blockDim.x + tid;
+  const int cl = col < n ? col : n - 1;        // clamped column for loads
   const size_t base = (size_t)k * n * n;
-  const double vi = v ? v[I] : 0.0;
-  double2 acc[NO];
+  double2 acc[kGroup][NO];
 #pragma unroll
-  for (int mu = 0; mu < NO; ++mu) acc[mu] = make_double2(0.0, 0.0);
-  const int p0 = g.row_ptr[I], p1 = g.row_ptr[I + 1];
-  for (int pc = p0; pc < p1; pc += kPairChunk) {
-    const int npc = min(kPairChunk, p1 - pc);
-    for (int t = threadIdx.x; t < npc * E2; t += blockDim.x) {
-      const int pl = t / E2, e = t % E2, p = pc + pl;
-      double2 h = make_double2(0.0, 0.0), dh = make_double2(0.0, 0.0);
-      for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
-        const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
-        const double hv = g.img_h0[(size_t)m * E2 + e];
-        const double a = f.ax * dx + f.ay * dy + f.az * dz;
-        const double kd = k0x * dx + k0y * dy + k0z * dz;
-        double sn, cs;
-        sincos(kd + a, &sn, &cs);
-        h.x += cs * hv;
-        h.y += sn * hv;
-        if (DELTA) {
-          double sh, ch;
-          sincos(kd + 0.5 * a, &sh, &ch);
-          const double amp = 2.0 * sin(0.5 * a) * hv;
-          dh.x -= amp * sh;
-          dh.y += amp * ch;
-        }
-      }
-      if (v != nullptr) {
-        const double vs = 0.5 * (vi + v[g.pair_col[p]]);
-        const double2 s = spk[((size_t)k * g.n_pairs + p) * E2 + e];
-        h.x += vs * s.x;
-        h.y += vs * s.y;
-        if (DELTA) {
-          dh.x += vs * s.x;
-          dh.y += vs * s.y;
-        }
-      }
-      hs[t] = h;
-      if (DELTA) dhs[t] = dh;
-      if (e == 0) cols[pl] = g.pair_col[p];
+  for (int il = 0; il < kGroup; ++il)
+#pragma unroll
+    for (int mu = 0; mu < NO; ++mu) acc[il][mu] = make_double2(0.0, 0.0);
+  const int e0 = g.grp_ptr[grp], e1 = g.grp_ptr[grp + 1];
+  for (int ec = e0; ec < e1; ec += kEntChunk) {
+    const int ne = min(kEntChunk, e1 - ec);
+    const int q0 = g.ent_pp[ec];
+    const int nq = g.ent_pp[ec + ne] - q0;     // <= ne * kGroup
+    const size_t hoff = ((size_t)k * g.n_pairs + q0) * E2;
+    for (int t = tid; t < nq * E2; t += blockDim.x) {
+      hs[t] = hq[hoff + t];
+      if (DELTA) dhs[t] = dhq[hoff + t];
+    }
+    if (tid < ne) {
+      s_j[tid] = g.ent_j[ec + tid];
+      s_mask[tid] = g.ent_mask[ec + tid];
+      s_pp[tid] = g.ent_pp[ec + tid] - q0;
     }
     __syncthreads();
-    if (col < n) {
-      for (int pl = 0; pl < npc; ++pl) {
-        const int J = cols[pl];
+    // Software pipeline: the D rows of neighbour el+1 load while el is applied.
+    double2 dv[NO], rv[NO], dn[NO], rn[NO];
+    {
+      const int J = s_j[0];
+#pragma unroll
+      for (int nu = 0; nu < NO; ++nu) {
+        const size_t idx = base + (size_t)(J * NO + nu) * n + cl;
+        dn[nu] = d[idx];
+        if (DELTA) rn[nu] = d0[idx];
+      }
+    }
+    for (int el = 0; el < ne; ++el) {
+#pragma unroll
+      for (int nu = 0; nu < NO; ++nu) {
+        dv[nu] = dn[nu];
+        if (DELTA) rv[nu] = rn[nu];
+      }
+      if (el + 1 < ne) {
+        const int J = s_j[el + 1];
 #pragma unroll
         for (int nu = 0; nu < NO; ++nu) {
-          const size_t idx = base + (size_t)(J * NO + nu) * n + col;
-          const double2 dv = d[idx];
+          const size_t idx = base + (size_t)(J * NO + nu) * n + cl;
+          dn[nu] = d[idx];
+          if (DELTA) rn[nu] = d0[idx];
+        }
+      }
+      const int mask = s_mask[el];
+      int slot = s_pp[el];
 #pragma unroll
-          for (int mu = 0; mu < NO; ++mu) {
-            const double2 h = hs[pl * E2 + mu * NO + nu];
-            acc[mu].x += h.x * dv.x - h.y * dv.y;
-            acc[mu].y += h.x * dv.y + h.y * dv.x;
-          }
-          if (DELTA) {
-            const double2 rv = d0[idx];
+      for (int il = 0; il < kGroup; ++il) {
+        if (mask & (1 << il)) {
+          const double2 *h = hs + slot * E2;
+          const double2 *dh = dhs + (DELTA ? slot * E2 : 0);
 #pragma unroll
-            for (int mu = 0; mu < NO; ++mu) {
-              const double2 h = dhs[pl * E2 + mu * NO + nu];
-              acc[mu].x += h.x * rv.x - h.y * rv.y;
-              acc[mu].y += h.x * rv.y + h.y * rv.x;
+          for (int mu = 0; mu < NO; ++mu)
+#pragma unroll
+            for (int nu = 0; nu < NO; ++nu) {
+              const double2 hv = h[mu * NO + nu];
+              acc[il][mu].x += hv.x * dv[nu].x - hv.y * dv[nu].y;
+              acc[il][mu].y += hv.x * dv[nu].y + hv.y * dv[nu].x;
+              if (DELTA) {
+                const double2 gv = dh[mu * NO + nu];
+                acc[il][mu].x += gv.x * rv[nu].x - gv.y * rv[nu].y;
+                acc[il][mu].y += gv.x * rv[nu].y + gv.y * rv[nu].x;
+              }
             }
-          }
+          ++slot;
         }
       }
     }
     __syncthreads();
   }
   if (col < n) {
-    if (OUT == 0) {
-      double2 *w = static_cast<double2 *>(wout);
 #pragma unroll
-      for (int mu = 0; mu < NO; ++mu) w[base + (size_t)(I * NO + mu) * n + col] = acc[mu];
-    } else if (OUT == 1) {
-      float2 *w = static_cast<float2 *>(wout);
-#pragma unroll
-      for (int mu = 0; mu < NO; ++mu)
-        w[base + (size_t)(I * NO + mu) * n + col] = make_float2((float)acc[mu].x, (float)acc[mu].y);
-    } else {
-      // complex64 copy of W for the identity part of S^-1 W = W + (S^-1 - I) W
-#pragma unroll
-      for (int mu = 0; mu < NO; ++mu)
-        w32[base + (size_t)(I * NO + mu) * n + col] = make_float2((float)acc[mu].x, (float)acc[mu].y);
-      uint16_t *w = static_cast<uint16_t *>(wout);
-      const size_t plane = (size_t)nk * np * np;
-      uint16_t h[4][NO];
-#pragma unroll
-      for (int mu = 0; mu < NO; ++mu) {
-        split_bf16(acc[mu].x, h[0][mu], h[1][mu]);
-        split_bf16(acc[mu].y, h[2][mu], h[3][mu]);
-      }
-      const int r0 = I * NO;
-      const size_t off = (size_t)k * np * np + ((size_t)(r0 >> 3) * np + col) * 8 + (r0 & 7);
-      if (NO == 4) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          uint2 pk = make_uint2((uint32_t)h[p][0] | ((uint32_t)h[p][NO > 1 ? 1 : 0] << 16),
-                                (uint32_t)h[p][NO > 2 ? 2 : 0] | ((uint32_t)h[p][NO > 3 ? 3 : 0] << 16));
-          *reinterpret_cast<uint2 *>(w + p * plane + off) = pk;
-        }
-      } else {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) w[p * plane + off] = h[p][0];
-      }
-    }
+    for (int il = 0; il < kGroup; ++il)
+      if (I0 + il < g.n_atoms) store_rows<NO, OUT>(acc[il], (I0 + il) * NO, col, k, n, np, nk, wout, w32);
   }
 }
 
@@ -654,19 +732,32 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
 
 template <int NO, bool DELTA, int OUT>
 static void spmm_launch(dim3 grid, int threads, hipStream_t s, const PairGraph &g,
-                        const double2 *d, const double2 *d0, int n, const double *kpts,
-                        StepField f, const double2 *spk, const double *v, void *w, int np,
-                        int nk, float2 *w32) {
-  hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT>), grid, dim3(threads), 0, s, g, d, d0, n, kpts, f,
-                     spk, v, w, np, nk, w32);
+                        const double2 *d, const double2 *d0, int n, const double2 *hq,
+                        const double2 *dhq, void *w, int np, int nk, float2 *w32) {
+  hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT>), grid, dim3(threads), 0, s, g, d, d0, n, hq, dhq, w,
+                     np, nk, w32);
 }
 
-void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
-                 const double *kpts, int nk, StepField f, const double2 *spk, const double *v,
-                 void *w, int out_format, int np, float2 *w32, hipStream_t s) {
+void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
+                     const double2 *spk, const double *v, double2 *hq, double2 *dhq,
+                     hipStream_t s) {
+  const size_t tot = (size_t)g.n_pairs * g.norb * g.norb;
+  dim3 grid(blocks_for(tot, 256), nk);
+  if (g.norb == 4) {
+    if (dhq) hipLaunchKernelGGL((k_assemble<4, true>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
+    else hipLaunchKernelGGL((k_assemble<4, false>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
+  } else {
+    if (dhq) hipLaunchKernelGGL((k_assemble<1, true>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
+    else hipLaunchKernelGGL((k_assemble<1, false>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
+  }
+}
+
+void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
+                 const double2 *hq, const double2 *dhq, void *w, int out_format, int np,
+                 float2 *w32, hipStream_t s) {
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
-  dim3 grid(blocks_for(n, threads), g.n_atoms, nk);
-#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(grid, threads, s, g, d, d0, n, kpts, f, spk, v, w, np, nk, w32)
+  dim3 grid(blocks_for(n, threads), g.n_groups, nk);
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(grid, threads, s, g, d, d0, n, hq, dhq, w, np, nk, w32)
   if (g.norb == 4) {
     if (!d0) VG_SPMM(4, false, 0);
     else if (out_format == 0) VG_SPMM(4, true, 0);

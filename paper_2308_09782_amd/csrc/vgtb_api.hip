@@ -51,9 +51,37 @@ vgtb_status fail(vgtb_ctx *ctx, vgtb_status st, const std::string &msg) {
 // ---------------------------------------------------------------------------
 struct HostGraph {
   int na = 0, norb = 0;
-  std::vector<int> row_ptr, pair_col, img_ptr;
+  std::vector<int> row_ptr, pair_col, pair_row, img_ptr;
   std::vector<double> img_d, img_h0, img_s;
+  std::vector<int> grp_ptr, ent_j, ent_mask, ent_pp, gp_pair, gp_il;
 };
+
+// Row groups of kGroup consecutive atoms and the union of their neighbours.
+void build_groups(HostGraph &hg) {
+  const int G = vgtb::kGroup;
+  const int ng = (hg.na + G - 1) / G;
+  hg.grp_ptr.assign(1, 0);
+  hg.ent_pp.assign(1, 0);
+  for (int g = 0; g < ng; ++g) {
+    std::map<int, std::vector<std::pair<int, int>>> by_j;   // J -> (il, pair)
+    for (int il = 0; il < G && g * G + il < hg.na; ++il) {
+      const int I = g * G + il;
+      for (int p = hg.row_ptr[I]; p < hg.row_ptr[I + 1]; ++p) by_j[hg.pair_col[p]].push_back({il, p});
+    }
+    for (auto &kv : by_j) {
+      int mask = 0;
+      for (auto &ip : kv.second) {
+        mask |= 1 << ip.first;
+        hg.gp_pair.push_back(ip.second);
+        hg.gp_il.push_back(ip.first);
+      }
+      hg.ent_j.push_back(kv.first);
+      hg.ent_mask.push_back(mask);
+      hg.ent_pp.push_back((int)hg.gp_pair.size());
+    }
+    hg.grp_ptr.push_back((int)hg.ent_j.size());
+  }
+}
 
 vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
   const int na = s->n_atoms, no = s->orbs_per_atom, nb = s->n_blocks;
@@ -118,6 +146,7 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
     const int i = s->blk_i[b], j = s->blk_j[b];
     if (i != prev_i || j != prev_j) {
       hg.pair_col.push_back(j);
+      hg.pair_row.push_back(i);
       hg.img_ptr.push_back((int)(hg.img_d.size() / 3));
       hg.row_ptr[i + 1] += 1;
       prev_i = i;
@@ -136,6 +165,7 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
       msg = "atom " + std::to_string(i) + " has no blocks (an on-site block is required)";
       return VGTB_E_INVAL;
     }
+  build_groups(hg);
   return VGTB_OK;
 }
 
@@ -201,7 +231,7 @@ struct Carver {
 };
 
 struct Sizes {
-  int na, no, n, nk, np, ni, cap, precision, npad;
+  int na, no, n, nk, np, ni, cap, precision, npad, ng, ne;
   bool scc, deviation;
 };
 
@@ -213,11 +243,20 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->kw_dev = cv.template take<double>(z.nk);
   c->g.row_ptr = cv.template take<int>(z.na + 1);
   c->g.pair_col = cv.template take<int>(z.np);
+  c->g.pair_row = cv.template take<int>(z.np);
   c->g.img_ptr = cv.template take<int>(z.np + 1);
   c->g.img_d = cv.template take<double>(3 * (size_t)z.ni);
   c->g.img_h0 = cv.template take<double>(e2 * z.ni);
   c->g.img_s = cv.template take<double>(e2 * z.ni);
+  c->g.grp_ptr = cv.template take<int>(z.ng + 1);
+  c->g.ent_j = cv.template take<int>(z.ne);
+  c->g.ent_mask = cv.template take<int>(z.ne);
+  c->g.ent_pp = cv.template take<int>(z.ne + 1);
+  c->g.gp_pair = cv.template take<int>(z.np);
+  c->g.gp_il = cv.template take<int>(z.np);
   c->spk = cv.template take<double2>(e2 * z.np * z.nk);
+  c->hq = cv.template take<double2>(e2 * z.np * z.nk);
+  c->dhq = z.deviation ? cv.template take<double2>(e2 * z.np * z.nk) : nullptr;
   c->sinv = cv.template take<double2>(n2);
   c->dlev[0] = cv.template take<double2>(n2);
   c->dlev[1] = cv.template take<double2>(n2);
@@ -257,11 +296,12 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
 // Mutable stand-in used for the size query (PairGraph members are const).
 struct SizeProbe {
   struct {
-    int *row_ptr, *pair_col, *img_ptr;
+    int *row_ptr, *pair_col, *pair_row, *img_ptr;
     double *img_d, *img_h0, *img_s;
+    int *grp_ptr, *ent_j, *ent_mask, *ent_pp, *gp_pair, *gp_il;
   } g;
   double *kpts_dev, *kw_dev, *part, *v, *z, *qbuf, *gamma, *hist, *eig, *eig_e, *occ;
-  double2 *spk, *sinv, *dlev[2], *d0, *w, *y;
+  double2 *spk, *hq, *dhq, *sinv, *dlev[2], *d0, *w, *y;
   int *info, *flag;
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
@@ -279,6 +319,8 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.nk = s->n_k;
   z.np = (int)hg.pair_col.size();
   z.ni = (int)(hg.img_d.size() / 3);
+  z.ng = (int)hg.grp_ptr.size() - 1;
+  z.ne = (int)hg.ent_j.size();
   z.cap = o->history_capacity;
   z.scc = s->gamma != nullptr;
   z.deviation = o->precision != VGTB_FP64;
@@ -413,11 +455,22 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.n_images = z.ni;
   c->g.row_ptr = dp.g.row_ptr;
   c->g.pair_col = dp.g.pair_col;
+  c->g.pair_row = dp.g.pair_row;
   c->g.img_ptr = dp.g.img_ptr;
   c->g.img_d = dp.g.img_d;
   c->g.img_h0 = dp.g.img_h0;
   c->g.img_s = dp.g.img_s;
+  c->g.n_groups = z.ng;
+  c->g.n_entries = z.ne;
+  c->g.grp_ptr = dp.g.grp_ptr;
+  c->g.ent_j = dp.g.ent_j;
+  c->g.ent_mask = dp.g.ent_mask;
+  c->g.ent_pp = dp.g.ent_pp;
+  c->g.gp_pair = dp.g.gp_pair;
+  c->g.gp_il = dp.g.gp_il;
   c->spk = dp.spk;
+  c->hq = dp.hq;
+  c->dhq = dp.dhq;
   c->sinv = dp.sinv;
   c->dlev[0] = dp.dlev[0];
   c->dlev[1] = dp.dlev[1];
@@ -455,10 +508,17 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   CREATE_HIP(hipMemcpyAsync(dp.kw_dev, s->kw, sizeof(double) * z.nk, hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.row_ptr, hg.row_ptr.data(), sizeof(int) * hg.row_ptr.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.pair_col, hg.pair_col.data(), sizeof(int) * hg.pair_col.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.pair_row, hg.pair_row.data(), sizeof(int) * hg.pair_row.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.img_ptr, hg.img_ptr.data(), sizeof(int) * hg.img_ptr.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.img_d, hg.img_d.data(), sizeof(double) * hg.img_d.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.img_h0, hg.img_h0.data(), sizeof(double) * hg.img_h0.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.img_s, hg.img_s.data(), sizeof(double) * hg.img_s.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.grp_ptr, hg.grp_ptr.data(), sizeof(int) * hg.grp_ptr.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.ent_j, hg.ent_j.data(), sizeof(int) * hg.ent_j.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.ent_mask, hg.ent_mask.data(), sizeof(int) * hg.ent_mask.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.ent_pp, hg.ent_pp.data(), sizeof(int) * hg.ent_pp.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.gp_pair, hg.gp_pair.data(), sizeof(int) * hg.gp_pair.size(), hipMemcpyHostToDevice, st_));
+  CREATE_HIP(hipMemcpyAsync(dp.g.gp_il, hg.gp_il.data(), sizeof(int) * hg.gp_il.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.z, c->z_host.data(), sizeof(double) * z.na, hipMemcpyHostToDevice, st_));
   if (z.scc)
     CREATE_HIP(hipMemcpyAsync(dp.gamma, s->gamma, sizeof(double) * z.na * z.na, hipMemcpyHostToDevice, st_));
@@ -595,8 +655,9 @@ vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
     // A density given by the caller need not be stationary: keep the constant
     // part of dD/dt, m0 = -i (S^-1 H0 D0 - D0 H0 S^-1), in FP64.
     const vgtb::StepField f0{0.0, 0.0, 0.0};
-    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->w, 0,
-                      0, nullptr, c->stream);
+    vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, nullptr, c->stream);
+    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->w, 0, 0, nullptr,
+                      c->stream);
     vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, c->n, c->nk, c->stream);
     vgtb::launch_update_const(c->y, c->dlev[0], c->m0, c->n, c->nk, c->stream);
     c->m0_active = true;
@@ -648,10 +709,13 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
                           c->z, c->v, c->qbuf, hrow, c->flag, s);
     });
+    timed(c, VGTB_K_ASSEMBLE, [&] {
+      vgtb::launch_assemble(c->g, c->kpts_dev, nk, f, c->spk, c->scc ? c->v : nullptr, c->hq,
+                            dev ? c->dhq : nullptr, s);
+    });
     if (!dev) {
       timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, nullptr, n, c->kpts_dev, nk, f, c->spk,
-                          c->scc ? c->v : nullptr, c->w, 0, 0, nullptr, s);
+        vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr, s);
       });
       timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
       timed(c, VGTB_K_UPDATE, [&] {
@@ -665,8 +729,7 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       // S^-1 W = W + (S^-1 - I) W with only the second term in reduced precision.
       const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
       timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, c->d0, n, c->kpts_dev, nk, f, c->spk,
-                          c->scc ? c->v : nullptr, c->w_lo, fmt, c->np, c->w32, s);
+        vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->dhq, c->w_lo, fmt, c->np, c->w32, s);
       });
       timed(c, VGTB_K_GEMM, [&] {
         if (fmt == 1)
@@ -820,8 +883,9 @@ vgtb_status vgtb_load_state(vgtb_ctx *c, const void *buf, size_t bytes) {
   if (c->d0 && h.pad != 0) {
     // Rebuild the constant term of a non-stationary reference (same kernels, same bits).
     const vgtb::StepField f0{0.0, 0.0, 0.0};
-    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->w, 0,
-                      0, nullptr, c->stream);
+    vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, nullptr, c->stream);
+    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->w, 0, 0, nullptr,
+                      c->stream);
     vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, c->n, c->nk, c->stream);
     vgtb::launch_fill_zero(c->w, (size_t)c->n * c->n * c->nk, c->stream);
     vgtb::launch_update_const(c->y, c->w, c->m0, c->n, c->nk, c->stream);

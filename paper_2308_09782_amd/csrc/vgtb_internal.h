@@ -15,13 +15,29 @@ namespace vgtb {
 
 constexpr double kLightSpeed = 137.035999084;
 
+// Atoms per row group of the sparse product (consecutive atom indices).
+constexpr int kGroup = 8;
+
 // Device view of the real-space blocks, grouped by atom pair (I, J): pairs
 // of row atom I are row_ptr[I] .. row_ptr[I+1]-1, sorted by J; the periodic
 // images of pair p are img_ptr[p] .. img_ptr[p+1]-1.
+//
+// Row groups of kGroup atoms: group g's neighbour union is entries
+// grp_ptr[g] .. grp_ptr[g+1]-1; entry e is atom ent_j[e] with bit il of
+// ent_mask[e] set when atom g*kGroup + il pairs with it; its pairs, in il
+// order, are gp_pair[ent_pp[e] .. ent_pp[e+1]-1] (local atom gp_il[...]).
 struct PairGraph {
   int n_atoms = 0, norb = 0, n_pairs = 0, n_images = 0;
+  int n_groups = 0, n_entries = 0;
+  const int *grp_ptr = nullptr;   // n_groups + 1
+  const int *ent_j = nullptr;     // n_entries
+  const int *ent_mask = nullptr;  // n_entries
+  const int *ent_pp = nullptr;    // n_entries + 1
+  const int *gp_pair = nullptr;   // n_pairs
+  const int *gp_il = nullptr;     // n_pairs
   const int *row_ptr = nullptr;   // n_atoms + 1
   const int *pair_col = nullptr;  // n_pairs
+  const int *pair_row = nullptr;  // n_pairs (row atom I of pair p)
   const int *img_ptr = nullptr;   // n_pairs + 1
   const double *img_d = nullptr;  // n_images * 3
   const double *img_h0 = nullptr; // n_images * norb^2
@@ -45,10 +61,15 @@ void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
                    double *hist_row, int *flag, hipStream_t s);
-// out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np).
-void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
-                 const double *kpts, int nk, StepField f, const double2 *spk, const double *v,
-                 void *w, int out_format, int np, float2 *w32, hipStream_t s);
+// Pair blocks of H_k(t) (and dH_k when dhq != null) in grouped pair order.
+void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
+                     const double2 *spk, const double *v, double2 *hq, double2 *dhq,
+                     hipStream_t s);
+// W = H D (d0 == null) or W = H dD + dH D0; out_format: 0 complex128,
+// 1 complex64, 2 bf16 planes (k-packed, padded np) + complex64 copy w32.
+void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
+                 const double2 *hq, const double2 *dhq, void *w, int out_format, int np,
+                 float2 *w32, hipStream_t s);
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, hipStream_t s);
 // D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each);
@@ -99,6 +120,8 @@ struct vgtb_ctx {
   vgtb::PairGraph g;
   double *kpts_dev = nullptr, *kw_dev = nullptr;
   double2 *spk = nullptr;      // nk * n_pairs * norb^2
+  double2 *hq = nullptr;       // nk * n_pairs * norb^2, H_k pair blocks (grouped order)
+  double2 *dhq = nullptr;      // same, dH_k (deviation forms)
   double2 *sinv = nullptr;     // nk * n * n
   double2 *dlev[2] = {nullptr, nullptr};
   double2 *d0 = nullptr;       // reference density (deviation forms)

@@ -29,7 +29,8 @@ EXPORTED = [
     "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
 ]
-KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5}
+KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
+           "assemble": 6}
 
 
 class VgtbError(RuntimeError):
