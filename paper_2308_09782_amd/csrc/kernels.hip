@@ -140,79 +140,94 @@ __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__re
   }
 }
 
-// Single workgroup: k-sums of the partials, Mulliken charges, SCC potential
-// V = gamma (q - Z) (Eq. 10, one matrix row per wavefront), energy, current
-// (Eq. 14) and trace; one history row [Jx Jy Jz E Tr q_0 .. q_{na-1}].
-// Fixed summation order throughout, so repeated runs agree bit for bit.
-constexpr int kReduceThreads = 1024;
-constexpr int kReduceWaves = kReduceThreads / 64;
-
-__global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ part, int nk,
-                                                           int na, const double *__restrict__ kw,
-                                                           double jscale,
-                                                           const double *__restrict__ gamma,
-                                                           const double *__restrict__ z,
-                                                           double *__restrict__ v,
-                                                           double *__restrict__ qbuf,
-                                                           double *__restrict__ hist_row,
-                                                           int *flag) {
-  __shared__ double red[6][kReduceWaves];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int I = t; I < na; I += kReduceThreads) {
-    double q = 0.0;
-    for (int k = 0; k < nk; ++k) q += kw[k] * part[((size_t)k * na + I) * 5];
-    qbuf[I] = q;
-    hist_row[5 + I] = q;
-  }
-  __syncthreads();
-  double escc = 0.0;
-  if (gamma != nullptr) {
-    for (int I = wave; I < na; I += kReduceWaves) {
-      const double *gr = gamma + (size_t)I * na;
-      double acc = 0.0;
-      for (int K = lane; K < na; K += 64) acc += gr[K] * (qbuf[K] - z[K]);
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        v[I] = acc;
-        escc += 0.5 * (qbuf[I] - z[I]) * acc;
-      }
-    }
-  }
-  double en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, tr = 0.0;
-  for (int idx = t; idx < nk * na; idx += kReduceThreads) {
-    const int k = idx / na;
-    const double *o = part + (size_t)idx * 5;
-    tr += kw[k] * o[0];
+// Reduction of the per-(k, atom) partials, in three short kernels with a
+// fixed summation order (repeated runs agree bit for bit):
+//  1. per atom I: q_I = sum_k w_k q(k,I) (Mulliken), and the atom's shares
+//     of the band energy and the current summed over k;
+//  2. SCC only, one wavefront per row: V_I = sum_K gamma_IK (q_K - Z_K)
+//     (Eq. 10) and the atom's share 1/2 dq_I V_I of the SCC energy;
+//  3. one workgroup: sums over atoms into the history row
+//     [Jx Jy Jz E Tr q_0 .. q_{na-1}] (current of Eq. 14, Tr = sum_I q_I).
+__global__ __launch_bounds__(256) void k_reduce_atoms(const double *__restrict__ part, int nk,
+                                                      int na, const double *__restrict__ kw,
+                                                      double *__restrict__ qbuf,
+                                                      double *__restrict__ rowpart,
+                                                      double *__restrict__ hist_row) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= na) return;
+  double q = 0.0, en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int k = 0; k < nk; ++k) {
+    const double *o = part + ((size_t)k * na + I) * 5;
+    q += kw[k] * o[0];
     en += kw[k] * o[1];
     jx += o[2];
     jy += o[3];
     jz += o[4];
   }
-  en = wave_sum(en);
-  jx = wave_sum(jx);
-  jy = wave_sum(jy);
-  jz = wave_sum(jz);
-  tr = wave_sum(tr);
-  escc = wave_sum(escc);
+  qbuf[I] = q;
+  hist_row[5 + I] = q;
+  double *r = rowpart + (size_t)I * 5;
+  r[0] = en;
+  r[1] = jx;
+  r[2] = jy;
+  r[3] = jz;
+  r[4] = 0.0;
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_scc(int na, const double *__restrict__ gamma,
+                                                     const double *__restrict__ z,
+                                                     const double *__restrict__ qbuf,
+                                                     double *__restrict__ v,
+                                                     double *__restrict__ rowpart) {
+  const int lane = threadIdx.x & 63;
+  const int I = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (I >= na) return;
+  const double *gr = gamma + (size_t)I * na;
+  double acc = 0.0;
+  for (int K = lane; K < na; K += 64) acc += gr[K] * (qbuf[K] - z[K]);
+  acc = wave_sum(acc);
   if (lane == 0) {
-    red[0][wave] = en;
-    red[1][wave] = jx;
-    red[2][wave] = jy;
-    red[3][wave] = jz;
-    red[4][wave] = tr;
-    red[5][wave] = escc;
+    v[I] = acc;
+    rowpart[(size_t)I * 5 + 4] = 0.5 * (qbuf[I] - z[I]) * acc;
+  }
+}
+
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceWaves = kReduceThreads / 64;
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(int na, double jscale,
+                                                                 const double *__restrict__ qbuf,
+                                                                 const double *__restrict__ rowpart,
+                                                                 double *__restrict__ hist_row,
+                                                                 int *flag) {
+  __shared__ double red[6][kReduceWaves];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double c[6] = {0, 0, 0, 0, 0, 0};
+  for (int I = t; I < na; I += kReduceThreads) {
+    const double *r = rowpart + (size_t)I * 5;
+    c[0] += r[0];
+    c[1] += r[1];
+    c[2] += r[2];
+    c[3] += r[3];
+    c[4] += r[4];
+    c[5] += qbuf[I];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    c[i] = wave_sum(c[i]);
+    if (lane == 0) red[i][wave] = c[i];
   }
   __syncthreads();
   if (t == 0) {
     double o[6] = {0, 0, 0, 0, 0, 0};
     for (int w = 0; w < kReduceWaves; ++w)
-      for (int c = 0; c < 6; ++c) o[c] += red[c][w];
+      for (int i = 0; i < 6; ++i) o[i] += red[i][w];
     hist_row[0] = o[1] * jscale;
     hist_row[1] = o[2] * jscale;
     hist_row[2] = o[3] * jscale;
-    hist_row[3] = o[0] + o[5];
-    hist_row[4] = o[4];
-    if (!isfinite(o[4]) || !isfinite(o[0])) *flag = 1;
+    hist_row[3] = o[0] + o[4];
+    hist_row[4] = o[5];
+    if (!isfinite(o[5]) || !isfinite(o[0])) *flag = 1;
   }
 }
 
@@ -289,14 +304,13 @@ __device__ inline void store_rows(const double2 (&acc)[NO], int r0, int col, int
   }
 }
 
-// Peierls assembly of the pair blocks of H_k(t) (and dH_k for DELTA) in the
-// grouped pair order q of the sparse product: hq[k][q][e].
-template <int NO, bool DELTA>
+// Peierls assembly of the pair blocks of H_k(t) in the grouped pair order q
+// of the sparse product: hq[k][q][e].
+template <int NO>
 __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpts, StepField f,
                                                   const double2 *__restrict__ spk,
                                                   const double *__restrict__ v,
-                                                  double2 *__restrict__ hq,
-                                                  double2 *__restrict__ dhq) {
+                                                  double2 *__restrict__ hq) {
   constexpr int E2 = NO * NO;
   const int k = blockIdx.y;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,50 +318,36 @@ __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpt
   const int q = t / E2, e = t % E2;
   const int p = g.gp_pair[q];
   const double k0x = kpts[3 * k], k0y = kpts[3 * k + 1], k0z = kpts[3 * k + 2];
-  double2 h = make_double2(0.0, 0.0), dh = make_double2(0.0, 0.0);
+  double2 h = make_double2(0.0, 0.0);
   for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
     const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
     const double hv = g.img_h0[(size_t)m * E2 + e];
-    const double a = f.ax * dx + f.ay * dy + f.az * dz;
-    const double kd = k0x * dx + k0y * dy + k0z * dz;
     double sn, cs;
-    sincos(kd + a, &sn, &cs);
+    sincos((k0x + f.ax) * dx + (k0y + f.ay) * dy + (k0z + f.az) * dz, &sn, &cs);
     h.x += cs * hv;
     h.y += sn * hv;
-    if (DELTA) {
-      double sh, ch;
-      sincos(kd + 0.5 * a, &sh, &ch);
-      const double amp = 2.0 * sin(0.5 * a) * hv;
-      dh.x -= amp * sh;
-      dh.y += amp * ch;
-    }
   }
   if (v != nullptr) {
     const double vs = 0.5 * (v[g.pair_row[p]] + v[g.pair_col[p]]);
     const double2 sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
     h.x += vs * sv.x;
     h.y += vs * sv.y;
-    if (DELTA) {
-      dh.x += vs * sv.x;
-      dh.y += vs * sv.y;
-    }
   }
-  const size_t o = ((size_t)k * g.n_pairs + q) * E2 + e;
-  hq[o] = h;
-  if (DELTA) dhq[o] = dh;
+  hq[((size_t)k * g.n_pairs + q) * E2 + e] = h;
 }
 
+// DELTA: W = H_k (D0 + dD) - C0 with the constant C0 = H0_k(A=0) D0, i.e.
+// H dD + (H - H0) D0 in one product; FP64 keeps the cancellation harmless.
 template <int NO, bool DELTA, int OUT>
 __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d,
                                               const double2 *__restrict__ d0, int n,
                                               const double2 *__restrict__ hq,
-                                              const double2 *__restrict__ dhq,
+                                              const double2 *__restrict__ c0,
                                               void *__restrict__ wout, int np, int nk,
                                               float2 *__restrict__ w32) {
   constexpr int E2 = NO * NO;
   constexpr int CP = kEntChunk * kGroup;       // pair blocks per chunk, at most
   __shared__ double2 hs[CP * E2];
-  __shared__ double2 dhs[DELTA ? CP * E2 : 1];
   __shared__ int s_j[kEntChunk], s_mask[kEntChunk], s_pp[kEntChunk];
   const int grp = blockIdx.y, k = blockIdx.z;
   const int I0 = grp * kGroup;
@@ -366,10 +366,7 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
     const int q0 = g.ent_pp[ec];
     const int nq = g.ent_pp[ec + ne] - q0;     // <= ne * kGroup
     const size_t hoff = ((size_t)k * g.n_pairs + q0) * E2;
-    for (int t = tid; t < nq * E2; t += blockDim.x) {
-      hs[t] = hq[hoff + t];
-      if (DELTA) dhs[t] = dhq[hoff + t];
-    }
+    for (int t = tid; t < nq * E2; t += blockDim.x) hs[t] = hq[hoff + t];
     if (tid < ne) {
       s_j[tid] = g.ent_j[ec + tid];
       s_mask[tid] = g.ent_mask[ec + tid];
@@ -377,7 +374,7 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
     }
     __syncthreads();
     // Software pipeline: the D rows of neighbour el+1 load while el is applied.
-    double2 dv[NO], rv[NO], dn[NO], rn[NO];
+    double2 dv[NO], dn[NO], rn[NO];
     {
       const int J = s_j[0];
 #pragma unroll
@@ -391,7 +388,10 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
 #pragma unroll
       for (int nu = 0; nu < NO; ++nu) {
         dv[nu] = dn[nu];
-        if (DELTA) rv[nu] = rn[nu];
+        if (DELTA) {
+          dv[nu].x += rn[nu].x;
+          dv[nu].y += rn[nu].y;
+        }
       }
       if (el + 1 < ne) {
         const int J = s_j[el + 1];
@@ -408,19 +408,15 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
       for (int il = 0; il < kGroup; ++il) {
         if (mask & (1 << il)) {
           const double2 *h = hs + slot * E2;
-          const double2 *dh = dhs + (DELTA ? slot * E2 : 0);
 #pragma unroll
           for (int mu = 0; mu < NO; ++mu)
 #pragma unroll
             for (int nu = 0; nu < NO; ++nu) {
               const double2 hv = h[mu * NO + nu];
-              acc[il][mu].x += hv.x * dv[nu].x - hv.y * dv[nu].y;
-              acc[il][mu].y += hv.x * dv[nu].y + hv.y * dv[nu].x;
-              if (DELTA) {
-                const double2 gv = dh[mu * NO + nu];
-                acc[il][mu].x += gv.x * rv[nu].x - gv.y * rv[nu].y;
-                acc[il][mu].y += gv.x * rv[nu].y + gv.y * rv[nu].x;
-              }
+              acc[il][mu].x = fma(hv.x, dv[nu].x, acc[il][mu].x);
+              acc[il][mu].x = fma(-hv.y, dv[nu].y, acc[il][mu].x);
+              acc[il][mu].y = fma(hv.x, dv[nu].y, acc[il][mu].y);
+              acc[il][mu].y = fma(hv.y, dv[nu].x, acc[il][mu].y);
             }
           ++slot;
         }
@@ -430,8 +426,19 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
   }
   if (col < n) {
 #pragma unroll
-    for (int il = 0; il < kGroup; ++il)
-      if (I0 + il < g.n_atoms) store_rows<NO, OUT>(acc[il], (I0 + il) * NO, col, k, n, np, nk, wout, w32);
+    for (int il = 0; il < kGroup; ++il) {
+      if (I0 + il < g.n_atoms) {
+        if (DELTA) {
+#pragma unroll
+          for (int mu = 0; mu < NO; ++mu) {
+            const double2 cv = c0[base + (size_t)((I0 + il) * NO + mu) * n + col];
+            acc[il][mu].x -= cv.x;
+            acc[il][mu].y -= cv.y;
+          }
+        }
+        store_rows<NO, OUT>(acc[il], (I0 + il) * NO, col, k, n, np, nk, wout, w32);
+      }
+    }
   }
 }
 
@@ -725,39 +732,38 @@ void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int
 
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
-                   double *hist_row, int *flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, s, part, nk, na, kw, jscale,
-                     gamma, z, v, qbuf, hist_row, flag);
+                   double *rowpart, double *hist_row, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_atoms, dim3(blocks_for(na, 256)), dim3(256), 0, s, part, nk, na, kw,
+                     qbuf, rowpart, hist_row);
+  if (gamma != nullptr)
+    hipLaunchKernelGGL(k_reduce_scc, dim3(blocks_for(na, 16)), dim3(1024), 0, s, na, gamma, z, qbuf,
+                       v, rowpart);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, s, na, jscale, qbuf, rowpart,
+                     hist_row, flag);
 }
 
 template <int NO, bool DELTA, int OUT>
 static void spmm_launch(dim3 grid, int threads, hipStream_t s, const PairGraph &g,
                         const double2 *d, const double2 *d0, int n, const double2 *hq,
-                        const double2 *dhq, void *w, int np, int nk, float2 *w32) {
-  hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT>), grid, dim3(threads), 0, s, g, d, d0, n, hq, dhq, w,
+                        const double2 *c0, void *w, int np, int nk, float2 *w32) {
+  hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT>), grid, dim3(threads), 0, s, g, d, d0, n, hq, c0, w,
                      np, nk, w32);
 }
 
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
-                     const double2 *spk, const double *v, double2 *hq, double2 *dhq,
-                     hipStream_t s) {
+                     const double2 *spk, const double *v, double2 *hq, hipStream_t s) {
   const size_t tot = (size_t)g.n_pairs * g.norb * g.norb;
   dim3 grid(blocks_for(tot, 256), nk);
-  if (g.norb == 4) {
-    if (dhq) hipLaunchKernelGGL((k_assemble<4, true>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
-    else hipLaunchKernelGGL((k_assemble<4, false>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
-  } else {
-    if (dhq) hipLaunchKernelGGL((k_assemble<1, true>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
-    else hipLaunchKernelGGL((k_assemble<1, false>), grid, dim3(256), 0, s, g, kpts, f, spk, v, hq, dhq);
-  }
+  if (g.norb == 4) hipLaunchKernelGGL(k_assemble<4>, grid, dim3(256), 0, s, g, kpts, f, spk, v, hq);
+  else hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, f, spk, v, hq);
 }
 
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
-                 const double2 *hq, const double2 *dhq, void *w, int out_format, int np,
+                 const double2 *hq, const double2 *c0, void *w, int out_format, int np,
                  float2 *w32, hipStream_t s) {
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
   dim3 grid(blocks_for(n, threads), g.n_groups, nk);
-#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(grid, threads, s, g, d, d0, n, hq, dhq, w, np, nk, w32)
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(grid, threads, s, g, d, d0, n, hq, c0, w, np, nk, w32)
   if (g.norb == 4) {
     if (!d0) VG_SPMM(4, false, 0);
     else if (out_format == 0) VG_SPMM(4, true, 0);

@@ -256,7 +256,7 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->g.gp_il = cv.template take<int>(z.np);
   c->spk = cv.template take<double2>(e2 * z.np * z.nk);
   c->hq = cv.template take<double2>(e2 * z.np * z.nk);
-  c->dhq = z.deviation ? cv.template take<double2>(e2 * z.np * z.nk) : nullptr;
+  c->c0 = z.deviation ? cv.template take<double2>(n2) : nullptr;
   c->sinv = cv.template take<double2>(n2);
   c->dlev[0] = cv.template take<double2>(n2);
   c->dlev[1] = cv.template take<double2>(n2);
@@ -267,6 +267,7 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->v = cv.template take<double>(z.na);
   c->z = cv.template take<double>(z.na);
   c->qbuf = cv.template take<double>(z.na);
+  c->rowpart = cv.template take<double>((size_t)z.na * 5);
   c->gamma = z.scc ? cv.template take<double>((size_t)z.na * z.na) : nullptr;
   c->hist = cv.template take<double>((size_t)z.cap * (5 + z.na));
   c->eig = cv.template take<double>((size_t)z.nk * z.n);
@@ -300,8 +301,8 @@ struct SizeProbe {
     double *img_d, *img_h0, *img_s;
     int *grp_ptr, *ent_j, *ent_mask, *ent_pp, *gp_pair, *gp_il;
   } g;
-  double *kpts_dev, *kw_dev, *part, *v, *z, *qbuf, *gamma, *hist, *eig, *eig_e, *occ;
-  double2 *spk, *hq, *dhq, *sinv, *dlev[2], *d0, *w, *y;
+  double *kpts_dev, *kw_dev, *part, *v, *z, *qbuf, *rowpart, *gamma, *hist, *eig, *eig_e, *occ;
+  double2 *spk, *hq, *c0, *sinv, *dlev[2], *d0, *w, *y;
   int *info, *flag;
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
@@ -365,6 +366,20 @@ void timed(vgtb_ctx *c, int id, F &&launch) {
   launch();
   (void)hipEventRecord(ev.second, c->stream);
   c->ev_pending.push_back({id, ev.first, ev.second});
+}
+
+// Deviation forms: C0 = H0_k(A=0) D0 (constant part of the sparse product)
+// and, for a reference that is not stationary, m0 = -i (S^-1 C0 - C0^dag S^-1).
+void prepare_reference(vgtb_ctx *c, bool with_m0) {
+  const vgtb::StepField f0{0.0, 0.0, 0.0};
+  vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, c->stream);
+  vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
+                    c->stream);
+  c->m0_active = with_m0;
+  if (!with_m0) return;
+  vgtb::launch_zgemm_f64(c->sinv, c->c0, c->y, c->n, c->nk, c->stream);
+  vgtb::launch_fill_zero(c->w, (size_t)c->n * c->n * c->nk, c->stream);
+  vgtb::launch_update_const(c->y, c->w, c->m0, c->n, c->nk, c->stream);
 }
 
 vgtb_status check_ready(vgtb_ctx *ctx) {
@@ -470,7 +485,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.gp_il = dp.g.gp_il;
   c->spk = dp.spk;
   c->hq = dp.hq;
-  c->dhq = dp.dhq;
+  c->c0 = dp.c0;
   c->sinv = dp.sinv;
   c->dlev[0] = dp.dlev[0];
   c->dlev[1] = dp.dlev[1];
@@ -481,6 +496,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->v = dp.v;
   c->z = dp.z;
   c->qbuf = dp.qbuf;
+  c->rowpart = dp.rowpart;
   c->gamma = dp.gamma;
   c->hist = dp.hist;
   c->eig = dp.eig;
@@ -616,7 +632,7 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
   if (c->precision != VGTB_FP64) {
     vgtb::launch_fill_zero(c->dlev[0], n2, s);
     vgtb::launch_trace_target(c->g, c->dlev[0], c->d0, n, nk, c->spk, c->tpart, c->trace0, s);
-    c->m0_active = false;   // the ground state commutes with S^-1 H0: no constant term
+    prepare_reference(c, false);   // the ground state commutes with S^-1 H0: no m0 term
   }
   c->cur = 0;
   c->have_density = true;
@@ -626,8 +642,8 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
     // Reference charges = Mulliken charges of the ground state (dq = 0 at t = 0).
     vgtb::StepField f0{0.0, 0.0, 0.0};
     vgtb::launch_observe(c->g, dtarget, nullptr, n, c->kpts_dev, nk, f0, c->spk, c->part, s);
-    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, 0.0, nullptr, c->z, c->v, c->qbuf, c->hist,
-                        c->flag, s);
+    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, 0.0, nullptr, c->z, c->v, c->qbuf,
+                        c->rowpart, c->hist, c->flag, s);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(c->z, c->qbuf, sizeof(double) * c->na, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->z_host.data(), c->qbuf, sizeof(double) * c->na, hipMemcpyDeviceToHost, s));
@@ -654,13 +670,7 @@ vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
                               c->stream);
     // A density given by the caller need not be stationary: keep the constant
     // part of dD/dt, m0 = -i (S^-1 H0 D0 - D0 H0 S^-1), in FP64.
-    const vgtb::StepField f0{0.0, 0.0, 0.0};
-    vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, nullptr, c->stream);
-    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->w, 0, 0, nullptr,
-                      c->stream);
-    vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, c->n, c->nk, c->stream);
-    vgtb::launch_update_const(c->y, c->dlev[0], c->m0, c->n, c->nk, c->stream);
-    c->m0_active = true;
+    prepare_reference(c, true);
   }
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -707,11 +717,10 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     });
     timed(c, VGTB_K_REDUCE, [&] {
       vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
-                          c->z, c->v, c->qbuf, hrow, c->flag, s);
+                          c->z, c->v, c->qbuf, c->rowpart, hrow, c->flag, s);
     });
     timed(c, VGTB_K_ASSEMBLE, [&] {
-      vgtb::launch_assemble(c->g, c->kpts_dev, nk, f, c->spk, c->scc ? c->v : nullptr, c->hq,
-                            dev ? c->dhq : nullptr, s);
+      vgtb::launch_assemble(c->g, c->kpts_dev, nk, f, c->spk, c->scc ? c->v : nullptr, c->hq, s);
     });
     if (!dev) {
       timed(c, VGTB_K_SPMM, [&] {
@@ -725,11 +734,12 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
           vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
       });
     } else {
-      // Deviation form: W = H dD + dH D0 in FP64, rounded to the product's format;
+      // Deviation form: W = H dD + dH D0 = H (D0 + dD) - H0 D0 in FP64, rounded to
+      // the product's format;
       // S^-1 W = W + (S^-1 - I) W with only the second term in reduced precision.
       const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
       timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->dhq, c->w_lo, fmt, c->np, c->w32, s);
+        vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32, s);
       });
       timed(c, VGTB_K_GEMM, [&] {
         if (fmt == 1)
@@ -880,18 +890,11 @@ vgtb_status vgtb_load_state(vgtb_ctx *c, const void *buf, size_t bytes) {
   c->have_prev = h.have_prev != 0;
   c->have_density = true;
   c->m0_active = false;
-  if (c->d0 && h.pad != 0) {
-    // Rebuild the constant term of a non-stationary reference (same kernels, same bits).
-    const vgtb::StepField f0{0.0, 0.0, 0.0};
-    vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, nullptr, c->stream);
-    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->w, 0, 0, nullptr,
-                      c->stream);
-    vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, c->n, c->nk, c->stream);
-    vgtb::launch_fill_zero(c->w, (size_t)c->n * c->n * c->nk, c->stream);
-    vgtb::launch_update_const(c->y, c->w, c->m0, c->n, c->nk, c->stream);
+  if (c->d0) {
+    // Rebuild C0 (and m0 for a non-stationary reference): same kernels, same bits.
+    prepare_reference(c, h.pad != 0);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->m0_active = true;
   }
   return VGTB_OK;
 }

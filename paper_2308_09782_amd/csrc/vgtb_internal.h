@@ -60,15 +60,14 @@ void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int
                     hipStream_t s);
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
-                   double *hist_row, int *flag, hipStream_t s);
-// Pair blocks of H_k(t) (and dH_k when dhq != null) in grouped pair order.
+                   double *rowpart, double *hist_row, int *flag, hipStream_t s);
+// Pair blocks of H_k(t) in grouped pair order.
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
-                     const double2 *spk, const double *v, double2 *hq, double2 *dhq,
-                     hipStream_t s);
-// W = H D (d0 == null) or W = H dD + dH D0; out_format: 0 complex128,
+                     const double2 *spk, const double *v, double2 *hq, hipStream_t s);
+// W = H D (d0 == null) or W = H (D0 + dD) - C0; out_format: 0 complex128,
 // 1 complex64, 2 bf16 planes (k-packed, padded np) + complex64 copy w32.
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
-                 const double2 *hq, const double2 *dhq, void *w, int out_format, int np,
+                 const double2 *hq, const double2 *c0, void *w, int out_format, int np,
                  float2 *w32, hipStream_t s);
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, hipStream_t s);
@@ -121,7 +120,7 @@ struct vgtb_ctx {
   double *kpts_dev = nullptr, *kw_dev = nullptr;
   double2 *spk = nullptr;      // nk * n_pairs * norb^2
   double2 *hq = nullptr;       // nk * n_pairs * norb^2, H_k pair blocks (grouped order)
-  double2 *dhq = nullptr;      // same, dH_k (deviation forms)
+  double2 *c0 = nullptr;       // nk * n * n, H0_k(A=0) D0 (deviation forms)
   double2 *sinv = nullptr;     // nk * n * n
   double2 *dlev[2] = {nullptr, nullptr};
   double2 *d0 = nullptr;       // reference density (deviation forms)
@@ -131,6 +130,7 @@ struct vgtb_ctx {
   double *v = nullptr;         // na
   double *z = nullptr;         // na
   double *qbuf = nullptr;      // na
+  double *rowpart = nullptr;   // na * 5 (per-atom shares of E, J, SCC energy)
   double *gamma = nullptr;     // na * na
   double *hist = nullptr;      // hist_cap * (5 + na)
   double *eig = nullptr;       // nk * n
