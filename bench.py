@@ -39,8 +39,11 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-k", type=int, default=2)
-    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    ap.add_argument("--cpu-sample-k", type=int, default=4)
+    ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed steps, run one plain device copy of this many MiB "
+                         "(read N, write N): the reference kernel for hardware byte counters")
     return ap.parse_args()
 
 
@@ -92,6 +95,12 @@ def main():
         atab = vs.sin2_pulse_table(cfg["n_steps"], dt, cfg["omega"], cfg["t_fs"] * vs.FS_AU, cfg["a_peak"])
     else:
         atab = vs.kick_table(1, cfg["a0"])
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     total = args.warmup + args.steps
     prop = vg.Propagator(sysm, dt, args.precision, history_capacity=max(total, 1))
     t_init = time.perf_counter()

@@ -43,13 +43,12 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
   __shared__ u32x4 Bs[4][BK / 8][BN];
 
   const int tiles = tiles_m * tiles_n;
-  const int nwg = tiles * batch_count;
-  int lin = blockIdx.x + blockIdx.y * tiles;
-  if ((nwg & 7) == 0) lin = (lin & 7) * (nwg >> 3) + (lin >> 3);
+  const int lin = xcd_slot(blockIdx.x + blockIdx.y * tiles, tiles * batch_count);
   const int batch = lin / tiles;
-  const int tile = lin % tiles;
-  const int bm = (tile / tiles_n) * BM;
-  const int bn = (tile % tiles_n) * BN;
+  int tm, tn;
+  grouped_tile(lin % tiles, tiles_m, tiles_n, 4, tm, tn);
+  const int bm = tm * BM;
+  const int bn = tn * BN;
 
   const size_t plane = (size_t)batch_count * np * np;     // elements per plane
   const size_t boff = (size_t)batch * np * np;
@@ -143,8 +142,12 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
 
 // Large tiles for np a multiple of 128: 128 x 128 per workgroup, 64 x 64 per
 // wavefront (16 MFMA tiles, 32 independent accumulators, so consecutive MFMAs
-// never wait on each other).  The twelve partial products are grouped by the
-// B plane they read, so only one B plane's fragments are live at a time.
+// never wait on each other).  Software pipeline, one workgroup per CU:
+//  - LDS double-buffered (2 x 72 KB); stage kt+1 is written from registers
+//    after the first group of MFMAs of stage kt, and the global loads of
+//    stage kt+2 are issued right after, so they have a whole stage to land;
+//  - the twelve partial products are grouped by the B plane they read, and
+//    the next plane's B fragments are read while the current plane's MFMAs run.
 constexpr int BM2 = 128, BN2 = 128;
 
 __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restrict__ A,
@@ -152,17 +155,16 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
                                                          float2 *__restrict__ Y, int n, int np,
                                                          int batch_count, int tiles_m,
                                                          int tiles_n) {
-  __shared__ u32x4 As[4][BM2][APAD / 8];
-  __shared__ u32x4 Bs[4][BK / 8][BN2];
+  __shared__ u32x4 As[2][4][BM2][APAD / 8];
+  __shared__ u32x4 Bs[2][4][BK / 8][BN2];
 
   const int tiles = tiles_m * tiles_n;
-  const int nwg = tiles * batch_count;
-  int lin = blockIdx.x + blockIdx.y * tiles;
-  if ((nwg & 7) == 0) lin = (lin & 7) * (nwg >> 3) + (lin >> 3);
+  const int lin = xcd_slot(blockIdx.x + blockIdx.y * tiles, tiles * batch_count);
   const int batch = lin / tiles;
-  const int tile = lin % tiles;
-  const int bm = (tile / tiles_n) * BM2;
-  const int bn = (tile % tiles_n) * BN2;
+  int tm, tn;
+  grouped_tile(lin % tiles, tiles_m, tiles_n, 4, tm, tn);
+  const int bm = tm * BM2;
+  const int bn = tn * BN2;
 
   const size_t plane = (size_t)batch_count * np * np;
   const size_t boff = (size_t)batch * np * np;
@@ -191,60 +193,81 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
                                                ((size_t)((k0) / 8 + ((L >> 7) & 3)) * np + bn + (L & 127)) * 8); \
     }                                                                                          \
   } while (0)
+#define VG_STORE128(buf)                                                                       \
+  do {                                                                                         \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                            \
+      const int L = tid + i * NT;                                                              \
+      As[buf][L >> 9][(L >> 2) & 127][L & 3] = ra[i];                                          \
+      Bs[buf][L >> 9][(L >> 7) & 3][L & 127] = rb[i];                                          \
+    }                                                                                          \
+  } while (0)
+#define VG_READB(dst, buf, pb)                                                                 \
+  _Pragma("unroll") for (int b = 0; b < 4; ++b) dst[b] = Bs[buf][pb][lg][wn0 + b * 16 + lr]
 
   const int nkt = np / BK;
   VG_LOAD128(0);
+  VG_STORE128(0);
+  __syncthreads();
+  if (nkt > 1) VG_LOAD128(BK);
   for (int kt = 0; kt < nkt; ++kt) {
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int L = tid + i * NT;
-      As[L >> 9][(L >> 2) & 127][L & 3] = ra[i];
-      Bs[L >> 9][(L >> 7) & 3][L & 127] = rb[i];
-    }
-    __syncthreads();
-    if (kt + 1 < nkt) VG_LOAD128((kt + 1) * BK);
-    u32x4 fa[4][4], nf2[4], nf3[4];
+    const int cur = kt & 1;
+    u32x4 fa[4][4], nf2[4], nf3[4], fb0[4], fb1[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) fa[a][p] = As[p][wm0 + a * 16 + lr][lg];
+      for (int p = 0; p < 4; ++p) fa[a][p] = As[cur][p][wm0 + a * 16 + lr][lg];
       nf2[a] = negate8(fa[a][2]);
       nf3[a] = negate8(fa[a][3]);
     }
+    VG_READB(fb0, cur, 0);
+    VG_READB(fb1, cur, 1);
     // B plane 0 (re_hi): Re += Ar_hi Br_hi + Ar_lo Br_hi;  Im += Ai_hi Br_hi + Ai_lo Br_hi
-    // B plane 1 (re_lo): Re += Ar_hi Br_lo;                  Im += Ai_hi Br_lo
-    // B plane 2 (im_hi): Re -= Ai_hi Bi_hi + Ai_lo Bi_hi;  Im += Ar_hi Bi_hi + Ar_lo Bi_hi
-    // B plane 3 (im_lo): Re -= Ai_hi Bi_lo;                  Im += Ar_hi Bi_lo
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb) {
-      u32x4 fb[4];
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) fb[b] = Bs[pb][lg][wn0 + b * 16 + lr];
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (pb == 0) {
-            cr[a][b] = mma(fa[a][0], fb[b], cr[a][b]);
-            ci[a][b] = mma(fa[a][2], fb[b], ci[a][b]);
-            cr[a][b] = mma(fa[a][1], fb[b], cr[a][b]);
-            ci[a][b] = mma(fa[a][3], fb[b], ci[a][b]);
-          } else if (pb == 1) {
-            cr[a][b] = mma(fa[a][0], fb[b], cr[a][b]);
-            ci[a][b] = mma(fa[a][2], fb[b], ci[a][b]);
-          } else if (pb == 2) {
-            cr[a][b] = mma(nf2[a], fb[b], cr[a][b]);
-            ci[a][b] = mma(fa[a][0], fb[b], ci[a][b]);
-            cr[a][b] = mma(nf3[a], fb[b], cr[a][b]);
-            ci[a][b] = mma(fa[a][1], fb[b], ci[a][b]);
-          } else {
-            cr[a][b] = mma(nf2[a], fb[b], cr[a][b]);
-            ci[a][b] = mma(fa[a][0], fb[b], ci[a][b]);
-          }
-        }
+      for (int a = 0; a < 4; ++a) {
+        cr[a][b] = mma(fa[a][0], fb0[b], cr[a][b]);
+        ci[a][b] = mma(fa[a][2], fb0[b], ci[a][b]);
+        cr[a][b] = mma(fa[a][1], fb0[b], cr[a][b]);
+        ci[a][b] = mma(fa[a][3], fb0[b], ci[a][b]);
+      }
+    if (kt + 1 < nkt) {
+      VG_STORE128(cur ^ 1);
+      if (kt + 2 < nkt) VG_LOAD128((kt + 2) * BK);
     }
+    VG_READB(fb0, cur, 2);
+    // B plane 1 (re_lo): Re += Ar_hi Br_lo;  Im += Ai_hi Br_lo
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        cr[a][b] = mma(fa[a][0], fb1[b], cr[a][b]);
+        ci[a][b] = mma(fa[a][2], fb1[b], ci[a][b]);
+      }
+    VG_READB(fb1, cur, 3);
+    // B plane 2 (im_hi): Re -= Ai_hi Bi_hi + Ai_lo Bi_hi;  Im += Ar_hi Bi_hi + Ar_lo Bi_hi
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        cr[a][b] = mma(nf2[a], fb0[b], cr[a][b]);
+        ci[a][b] = mma(fa[a][0], fb0[b], ci[a][b]);
+        cr[a][b] = mma(nf3[a], fb0[b], cr[a][b]);
+        ci[a][b] = mma(fa[a][1], fb0[b], ci[a][b]);
+      }
+    // B plane 3 (im_lo): Re -= Ai_hi Bi_lo;  Im += Ar_hi Bi_lo
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        cr[a][b] = mma(nf2[a], fb1[b], cr[a][b]);
+        ci[a][b] = mma(fa[a][0], fb1[b], ci[a][b]);
+      }
+    __syncthreads();
   }
+#undef VG_LOAD128
+#undef VG_STORE128
+#undef VG_READB
 
   float2 *Yb = Y + (size_t)batch * n * n;
 #pragma unroll
@@ -257,7 +280,6 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
         const int col = bn + wn0 + b * 16 + lr;
         if (row < n && col < n) Yb[(size_t)row * n + col] = make_float2(cr[a][b][j], ci[a][b][j]);
       }
-#undef VG_LOAD128
 }
 
 }  // namespace

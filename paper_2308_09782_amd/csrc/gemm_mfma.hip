@@ -4,7 +4,8 @@
 //
 // Each complex multiply-accumulate is four real MFMAs on interleaved
 // (re, im) operands: Cr += ar br - ai bi, Ci += ar bi + ai br.
-// A workgroup owns a BM x BN output tile; its WM x WN wavefronts each own a
+// A workgroup owns a BM x BN output tile (XCD-aware, grouped tile order); its
+// WM x WN wavefronts each own a
 // (BM/WM) x (BN/WN) sub-tile made of 16 x 16 MFMA tiles.  Operand tiles of
 // depth BK are staged through LDS (A stored k-major so that the sixteen
 // lanes of an MFMA row group read consecutive addresses), double-buffered
@@ -61,13 +62,12 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm(const typename Mfma<T>::C
   // XCD-aware tile order: consecutive workgroup ids land on different XCDs,
   // so give each XCD a contiguous run of tiles (same A rows, same batch).
   const int tiles = tiles_m * tiles_n;
-  const int nwg = tiles * gridDim.y;
-  int lin = blockIdx.x + blockIdx.y * tiles;
-  if ((nwg & 7) == 0) lin = (lin & 7) * (nwg >> 3) + (lin >> 3);
+  const int lin = xcd_slot(blockIdx.x + blockIdx.y * tiles, tiles * gridDim.y);
   const int batch = lin / tiles;
-  const int tile = lin % tiles;
-  const int bm = (tile / tiles_n) * BM;
-  const int bn = (tile % tiles_n) * BN;
+  int tm, tn;
+  grouped_tile(lin % tiles, tiles_m, tiles_n, 8, tm, tn);
+  const int bm = tm * BM;
+  const int bn = tn * BN;
 
   const size_t boff = (size_t)batch * n * n;
   const C2 *Ab = A + boff;

@@ -18,6 +18,26 @@ constexpr double kLightSpeed = 137.035999084;
 // Atoms per row group of the sparse product (consecutive atom indices).
 constexpr int kGroup = 8;
 
+// Workgroup scheduling.  The dispatcher hands consecutive workgroup ids to the
+// eight XCDs in turn, and each XCD has its own L2.  xcd_slot() renumbers a
+// dispatch id so that each XCD receives a contiguous range of the logical
+// index space (when the count divides by 8); grouped_tile() then walks the
+// output tiles of one batch entry in blocks of gm row panels, column-major
+// within a block, so the workgroups resident on one XCD share A row panels
+// and B column panels in its L2.
+__device__ inline int xcd_slot(int lin, int total) {
+  return (total & 7) == 0 ? (lin & 7) * (total >> 3) + (lin >> 3) : lin;
+}
+__device__ inline void grouped_tile(int tile, int tiles_m, int tiles_n, int gm, int &tm, int &tn) {
+  const int per_group = gm * tiles_n;
+  const int g = tile / per_group;
+  const int first = g * gm;
+  const int rows = min(gm, tiles_m - first);
+  const int r = tile % per_group;
+  tm = first + r % rows;
+  tn = r / rows;
+}
+
 // Device view of the real-space blocks, grouped by atom pair (I, J): pairs
 // of row atom I are row_ptr[I] .. row_ptr[I+1]-1, sorted by J; the periodic
 // images of pair p are img_ptr[p] .. img_ptr[p+1]-1.
