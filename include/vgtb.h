@@ -215,6 +215,20 @@ vgtb_status vgtb_profile_read(vgtb_ctx *ctx, int32_t kernel, double *total_ms_ho
                               int64_t *launches_host);
 
 /*
+ * Spectrum of a delta-kick run (paper Eqs. 15-16), on the device:
+ *   sigma(w) = (1/E0) int_0^T exp(i w t) (J(t) - <J>) exp(-t / tau0) dt
+ *   epsilon(w) = 1 + 4 pi i sigma(w) / w
+ * with the trapezoid rule on t_n = n dt.  j_host: n_t samples of one current
+ * component; omega_host: n_w frequencies (nonzero); e0 the kick field
+ * (E0 = -A0 / c for A(t) = A0 from t = 0); subtract_mean != 0 removes the mean
+ * current first.  sigma_host / eps_host (either may be NULL) receive n_w
+ * complex128 values.  Synchronous; uses the context's stream and scratch.
+ */
+vgtb_status vgtb_spectrum(vgtb_ctx *ctx, int64_t n_t, const double *j_host, double dt,
+                          int64_t n_w, const double *omega_host, double e0, double tau0,
+                          int subtract_mean, void *sigma_host, void *eps_host);
+
+/*
  * Stand-alone kernel entry: C = A * B for `batch` row-major N x N complex128
  * matrices (strides N*N), on the FP64 matrix cores - the dense product
  * S_k^-1 (H_k D_k) of Eq. 6.  Device pointers, queued on hip_stream.

@@ -931,6 +931,39 @@ vgtb_status vgtb_profile_read(vgtb_ctx *c, int32_t kernel, double *ms, int64_t *
   return VGTB_OK;
 }
 
+vgtb_status vgtb_spectrum(vgtb_ctx *c, int64_t n_t, const double *j, double dt, int64_t n_w,
+                          const double *omega, double e0, double tau0, int subtract_mean,
+                          void *sigma_out, void *eps_out) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (n_t < 2 || n_w < 1 || !j || !omega || !(std::fabs(e0) > 0.0) || !(tau0 > 0.0) ||
+      !std::isfinite(dt) || n_t > (int64_t)1 << 30 || n_w > (int64_t)1 << 24)
+    return fail(c, VGTB_E_INVAL, "bad spectrum arguments");
+  for (int64_t i = 0; i < n_w; ++i)
+    if (!(std::fabs(omega[i]) > 0.0)) return fail(c, VGTB_E_INVAL, "frequencies must be nonzero");
+  // Device scratch: the FP64 product buffer (n_k * N * N complex) is unused between steps.
+  const size_t need = (size_t)n_t + (size_t)n_w + 2 + 4 * (size_t)n_w;
+  const size_t have = 2 * (size_t)c->n * c->n * c->nk;
+  if (need > have) return fail(c, VGTB_E_INVAL, "spectrum too large for the context scratch");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double *dj = reinterpret_cast<double *>(c->y);
+  double *dw = dj + n_t;
+  double *dm = dw + n_w;
+  double2 *dout = reinterpret_cast<double2 *>(dm + 1 + ((n_t + n_w + 1) & 1));
+  HIP_TRY(c, hipMemcpyAsync(dj, j, sizeof(double) * n_t, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dw, omega, sizeof(double) * n_w, hipMemcpyHostToDevice, c->stream));
+  vgtb::launch_spectrum(dj, (int)n_t, dt, dw, (int)n_w, e0, tau0, subtract_mean != 0, dm, dout, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  std::vector<double2> out(2 * n_w);
+  HIP_TRY(c, hipMemcpyAsync(out.data(), dout, sizeof(double2) * 2 * n_w, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int64_t i = 0; i < n_w; ++i) {
+    if (sigma_out) static_cast<double2 *>(sigma_out)[i] = out[2 * i];
+    if (eps_out) static_cast<double2 *>(eps_out)[i] = out[2 * i + 1];
+  }
+  return VGTB_OK;
+}
+
 int64_t vgtb_step_index(const vgtb_ctx *c) { return c ? c->step : -1; }
 
 const char *vgtb_last_error(const vgtb_ctx *c) { return c ? c->err.c_str() : g_global_err.c_str(); }

@@ -106,6 +106,10 @@ void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 
                     const double2 *spk, double *tpart, const double *target, double *fac,
                     hipStream_t s);
 void launch_add(const double2 *a, const double2 *b, double2 *out, size_t count, hipStream_t s);
+// sigma and epsilon interleaved in out (2 * nw complex); j and omega on the device.
+void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
+                     double tau0, bool subtract_mean, double *scratch_mean, double2 *out,
+                     hipStream_t s);
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s);
 void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
                                  int nk, hipStream_t s);

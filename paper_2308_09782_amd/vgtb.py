@@ -28,6 +28,7 @@ EXPORTED = [
     "vgtb_read_observables", "vgtb_get_density", "vgtb_get_reference_charges",
     "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
+    "vgtb_spectrum",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
            "assemble": 6}
@@ -86,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_zgemm": [vp, vp, vp, i32, i32, vp],
         "vgtb_profile_enable": [vp, ctypes.c_int],
         "vgtb_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+        "vgtb_spectrum": [vp, i64, vp, ctypes.c_double, i64, vp, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_int, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -311,6 +314,18 @@ class Propagator:
             _check(self.lib.vgtb_profile_read(self.ctx, kid, ctypes.byref(ms), ctypes.byref(cnt)), self.ctx)
             out[name] = (float(ms.value), int(cnt.value))
         return out
+
+    def spectrum(self, j, dt: float, omegas, e0: float, tau0: float = 200.0,
+                 subtract_mean: bool = True):
+        """(sigma, epsilon) of one current component on the GPU (Eqs. 15-16)."""
+        j = np.ascontiguousarray(j, dtype=np.float64).reshape(-1)
+        w = np.ascontiguousarray(omegas, dtype=np.float64).reshape(-1)
+        sig = np.zeros(w.size, dtype=np.complex128)
+        eps = np.zeros(w.size, dtype=np.complex128)
+        _check(self.lib.vgtb_spectrum(self.ctx, j.size, j.ctypes.data, float(dt), w.size, w.ctypes.data,
+                                      float(e0), float(tau0), 1 if subtract_mean else 0,
+                                      sig.ctypes.data, eps.ctypes.data), self.ctx)
+        return sig, eps
 
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))

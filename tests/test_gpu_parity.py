@@ -224,3 +224,27 @@ def test_error_paths():
     with pytest.raises(pkg.VgtbError) as ei:
         pkg.Propagator(dataclasses.replace(sysm, blk_s=bad_s), 0.2)
     assert ei.value.status == 3                          # VGTB_E_NOT_PD
+
+
+# ---------------------------------------------------------------------------
+def test_spectrum_matches_oracle():
+    """Eqs. 15-16 on the GPU vs the oracle, on a kick run's current and on a
+    synthetic damped sinusoid (mean subtraction on and off)."""
+    c = vs.CONFIGS["si8_k64"]
+    sysm = vs.diamond_supercell(1, (2, 2, 2), seed=1001)
+    n = 1500
+    g = run_gpu(sysm, vs.kick_table(1, 0.01), 0.2, n)
+    j = g["hist"]["J"][:, 0]
+    omegas = np.arange(0.005, 0.5, 0.001)
+    e0 = -0.01 / vs.C_LIGHT
+    with pkg.Propagator(sysm, 0.2) as p:
+        sig, eps = p.spectrum(j, 0.2, omegas, e0)
+        t = np.arange(4001) * 0.05
+        js = np.sin(0.3 * t) * np.exp(-t / 500.0) + 0.1
+        sig2, eps2 = p.spectrum(js, 0.05, omegas, 1.0, tau0=150.0, subtract_mean=False)
+    ref = oracle.conductivity(j, 0.2, omegas, e0)
+    assert np.abs(sig - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(eps - oracle.dielectric(ref, omegas)).max() < 1e-12 * np.abs(eps).max()
+    ref2 = oracle.conductivity(js, 0.05, omegas, 1.0, tau0=150.0, subtract_mean=False)
+    assert np.abs(sig2 - ref2).max() < 1e-12 * np.abs(ref2).max()
+    assert np.imag(eps).max() > 0
