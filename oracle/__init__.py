@@ -26,6 +26,7 @@ from .tddftb import (  # noqa: F401
     ground_state,
     occupations,
     density_derivative,
+    density_derivative_columns,
     observables,
     propagate,
     OracleState,

@@ -154,6 +154,16 @@ def density_derivative(s_inv: np.ndarray, h: np.ndarray, d: np.ndarray) -> np.nd
     return -1j * (s_inv @ h @ d - d @ h @ s_inv)
 
 
+def density_derivative_columns(s_inv: np.ndarray, h: np.ndarray, d: np.ndarray, cols) -> np.ndarray:
+    """Selected columns of Eq. (6): dD/dt[:, j] = -i (S^-1 (H D[:, j]) - D (H S^-1[:, j])).
+
+    The same expression as density_derivative, evaluated one column at a time
+    (O(N^2) per column) so that large systems can be sampled.
+    """
+    cols = np.asarray(cols)
+    return -1j * (s_inv @ (h @ d[:, cols]) - d @ (h @ s_inv[:, cols]))
+
+
 def observables(sysm, dens, ovl, a_vec, z):
     """Current (Eq. 14), band + SCC energy, Tr(D S) and Mulliken charges of one time level."""
     nk = sysm.n_k

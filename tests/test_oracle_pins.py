@@ -377,3 +377,28 @@ def test_golden_paper_parameters():
     assert abs(e_v_per_a - g["laser_E0_eV_per_A"]["value"]) < g["laser_E0_eV_per_A"]["rel_tol"] * 0.274
     # 20 fs in atomic time.
     assert abs(g["laser_duration_fs"]["value"] * vs.FS_AU - 826.827) < 1e-2
+
+
+def test_column_derivative_equals_full():
+    """The column-sampled Eq. 6 agrees with the full one (used at full size)."""
+    sysm = _small_si((1, 1, 1))
+    rng = np.random.default_rng(8)
+    d = _random_hermitian(sysm.n_orb, rng)
+    s = oracle.overlap_k(sysm, sysm.kpts[0])
+    h = oracle.h0_k(sysm, sysm.kpts[0], np.array([0.02, 0.0, 0.01]))
+    si = oracle.overlap_inverse(s)
+    cols = [0, 5, 31]
+    full = oracle.density_derivative(si, h, d)
+    assert np.abs(oracle.density_derivative_columns(si, h, d, cols) - full[:, cols]).max() < 1e-14
+    # the derivative of a Hermitian density is Hermitian
+    assert np.abs(full - full.conj().T).max() < 1e-13
+
+
+def test_occupations_by_hand():
+    """Aufbau with a degenerate group straddling the Fermi level (equal sharing)."""
+    eps = np.array([0.3, -1.0, 0.0, 0.0, 0.0, 2.0])
+    f = oracle.occupations(eps, 5.0)
+    assert np.allclose(f, [0.0, 2.0, 1.0, 1.0, 1.0, 0.0])
+    f = oracle.occupations(np.array([-1.0, 0.0, 1e-10, 1.0]), 4.0)
+    assert np.allclose(f, [2.0, 1.0, 1.0, 0.0])
+    assert oracle.occupations(np.array([-1.0, 0.0]), 0.0).sum() == 0.0

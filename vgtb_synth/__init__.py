@@ -18,6 +18,7 @@ from .systems import (  # noqa: F401
     amorphous_si,
     linear_chain,
     random_cell,
+    random_hermitian_density,
     primitive_diamond,
     gamma_mesh,
     config_system,

@@ -359,3 +359,18 @@ def random_cell(n_atoms: int, kmesh=(1, 1, 1), seed: int = 7, gamma_u=None,
     if n_electrons is None:
         n_electrons = 4 * n_atoms
     return _sp_system(name or f"random{n_atoms}", cell, pos, vh, vs, kmesh, n_electrons, gamma_u)
+
+
+def random_hermitian_density(n: int, n_k: int, seed: int = 5, scale: float = 0.05,
+                             diag: float = 0.5) -> np.ndarray:
+    """Seeded Hermitian matrices (n_k, n, n) shaped like a density: diag + noise.
+
+    Used as a non-stationary starting density where only the equation of
+    motion, not the ground state, is being tested.
+    """
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_k, n, n), dtype=np.complex128)
+    for k in range(n_k):
+        a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        out[k] = scale * 0.5 * (a + a.conj().T) + diag * np.eye(n)
+    return out
