@@ -140,9 +140,10 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
 #undef VG_LOAD64
 }
 
-// Large tiles for np a multiple of 128: 128 x 128 per workgroup, 64 x 64 per
-// wavefront (16 MFMA tiles, 32 independent accumulators, so consecutive MFMAs
-// never wait on each other).  Software pipeline, one workgroup per CU:
+// Large tiles for np a multiple of 128: 128 x 128 per workgroup of WGM x WGN
+// wavefronts (several per SIMD, so one wave's stalls are covered by another),
+// each computing (128/WGM) x (128/WGN) from 16 x 16 MFMA tiles.
+// Software pipeline, one workgroup per CU:
 //  - LDS double-buffered (2 x 72 KB); stage kt+1 is written from registers
 //    after the first group of MFMAs of stage kt, and the global loads of
 //    stage kt+2 are issued right after, so they have a whole stage to land;
@@ -150,11 +151,15 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
 //    the next plane's B fragments are read while the current plane's MFMAs run.
 constexpr int BM2 = 128, BN2 = 128;
 
-__global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restrict__ A,
-                                                         const uint16_t *__restrict__ B,
-                                                         float2 *__restrict__ Y, int n, int np,
-                                                         int batch_count, int tiles_m,
-                                                         int tiles_n) {
+template <int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint16_t *__restrict__ A,
+                                                                     const uint16_t *__restrict__ B,
+                                                                     float2 *__restrict__ Y, int n,
+                                                                     int np, int batch_count,
+                                                                     int tiles_m, int tiles_n) {
+  constexpr int NT2 = 64 * WGM * WGN;
+  constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
+  constexpr int LD = 2048 / NT2;             // u32x4 per thread per operand and stage
   __shared__ u32x4 As[2][4][BM2][APAD / 8];
   __shared__ u32x4 Bs[2][4][BK / 8][BN2];
 
@@ -169,24 +174,24 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
   const size_t plane = (size_t)batch_count * np * np;
   const size_t boff = (size_t)batch * np * np;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int wm0 = (wave / WGN) * (BM2 / WGM), wn0 = (wave % WGN) * (BN2 / WGN);
   const int lr = lane & 15, lg = lane >> 4;
 
-  v4f cr[4][4], ci[4][4];
+  v4f cr[TM][TN], ci[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < TN; ++b) {
       cr[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
       ci[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
   // Per stage: 2048 u32x4 of A (4 planes x 128 rows x 4) and 2048 of B (4 x 4 x 128).
-  u32x4 ra[8], rb[8];
+  u32x4 ra[LD], rb[LD];
 #define VG_LOAD128(k0)                                                                         \
   do {                                                                                         \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                            \
-      const int L = tid + i * NT;                                                              \
+    _Pragma("unroll") for (int i = 0; i < LD; ++i) {                                           \
+      const int L = tid + i * NT2;                                                             \
       ra[i] = *reinterpret_cast<const u32x4 *>(A + (L >> 9) * plane + boff +                   \
                                                (size_t)(bm + ((L >> 2) & 127)) * np + (k0) + (L & 3) * 8); \
       rb[i] = *reinterpret_cast<const u32x4 *>(B + (L >> 9) * plane + boff +                   \
@@ -195,14 +200,14 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
   } while (0)
 #define VG_STORE128(buf)                                                                       \
   do {                                                                                         \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                            \
-      const int L = tid + i * NT;                                                              \
+    _Pragma("unroll") for (int i = 0; i < LD; ++i) {                                           \
+      const int L = tid + i * NT2;                                                             \
       As[buf][L >> 9][(L >> 2) & 127][L & 3] = ra[i];                                          \
       Bs[buf][L >> 9][(L >> 7) & 3][L & 127] = rb[i];                                          \
     }                                                                                          \
   } while (0)
 #define VG_READB(dst, buf, pb)                                                                 \
-  _Pragma("unroll") for (int b = 0; b < 4; ++b) dst[b] = Bs[buf][pb][lg][wn0 + b * 16 + lr]
+  _Pragma("unroll") for (int b = 0; b < TN; ++b) dst[b] = Bs[buf][pb][lg][wn0 + b * 16 + lr]
 
   const int nkt = np / BK;
   VG_LOAD128(0);
@@ -211,9 +216,9 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
   if (nkt > 1) VG_LOAD128(BK);
   for (int kt = 0; kt < nkt; ++kt) {
     const int cur = kt & 1;
-    u32x4 fa[4][4], nf2[4], nf3[4], fb0[4], fb1[4];
+    u32x4 fa[TM][4], nf2[TM], nf3[TM], fb0[TN], fb1[TN];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < TM; ++a) {
 #pragma unroll
       for (int p = 0; p < 4; ++p) fa[a][p] = As[cur][p][wm0 + a * 16 + lr][lg];
       nf2[a] = negate8(fa[a][2]);
@@ -223,9 +228,9 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
     VG_READB(fb1, cur, 1);
     // B plane 0 (re_hi): Re += Ar_hi Br_hi + Ar_lo Br_hi;  Im += Ai_hi Br_hi + Ai_lo Br_hi
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma(fa[a][0], fb0[b], cr[a][b]);
         ci[a][b] = mma(fa[a][2], fb0[b], ci[a][b]);
         cr[a][b] = mma(fa[a][1], fb0[b], cr[a][b]);
@@ -238,18 +243,18 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
     VG_READB(fb0, cur, 2);
     // B plane 1 (re_lo): Re += Ar_hi Br_lo;  Im += Ai_hi Br_lo
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma(fa[a][0], fb1[b], cr[a][b]);
         ci[a][b] = mma(fa[a][2], fb1[b], ci[a][b]);
       }
     VG_READB(fb1, cur, 3);
     // B plane 2 (im_hi): Re -= Ai_hi Bi_hi + Ai_lo Bi_hi;  Im += Ar_hi Bi_hi + Ar_lo Bi_hi
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma(nf2[a], fb0[b], cr[a][b]);
         ci[a][b] = mma(fa[a][0], fb0[b], ci[a][b]);
         cr[a][b] = mma(nf3[a], fb0[b], cr[a][b]);
@@ -257,9 +262,9 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
       }
     // B plane 3 (im_lo): Re -= Ai_hi Bi_lo;  Im += Ar_hi Bi_lo
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma(nf2[a], fb1[b], cr[a][b]);
         ci[a][b] = mma(fa[a][0], fb1[b], ci[a][b]);
       }
@@ -271,9 +276,9 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3_128(const uint16_t *__restr
 
   float2 *Yb = Y + (size_t)batch * n * n;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = bm + wm0 + a * 16 + 4 * lg + j;
@@ -288,8 +293,8 @@ void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n,
                          hipStream_t s) {
   if (np % BM2 == 0 && np >= 512) {
     const int tm = np / BM2, tn = np / BN2;
-    hipLaunchKernelGGL(k_cgemm_bf16x3_128, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np,
-                       batch, tm, tn);
+    hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 4>), dim3(tm * tn, batch), dim3(64 * 16), 0, s, a, b,
+                       y, n, np, batch, tm, tn);
   } else {
     const int tm = np / BM, tn = np / BN;
     hipLaunchKernelGGL(k_cgemm_bf16x3, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
