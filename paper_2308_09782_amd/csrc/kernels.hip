@@ -250,7 +250,7 @@ __device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
 // DELTA: the deviation form W = H_k dD + dH_k D0, dH_k = H_k - H0_k(A=0), with
 // exp(i(k+A/c).d) - exp(i k.d) = 2 sin(a/2) i exp(i(k.d + a/2)), a = A.d/c.
 //
-// A workgroup owns the rows of kGroup consecutive atoms and one chunk of
+// A workgroup owns the rows of KG consecutive atoms and one chunk of
 // columns (one column per thread).  It walks the union of those atoms'
 // neighbours once: each neighbour's D rows are loaded a single time and
 // applied to every group atom that pairs with it (mask bits, uniform
@@ -336,9 +336,12 @@ __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpt
   hq[((size_t)k * g.n_pairs + q) * E2 + e] = h;
 }
 
-// DELTA: W = H_k (D0 + dD) - C0 with the constant C0 = H0_k(A=0) D0, i.e.
-// H dD + (H - H0) D0 in one product; FP64 keeps the cancellation harmless.
-template <int NO, bool DELTA, int OUT>
+// DELTA: W = H_k D - C0 with D = D0 + dD (kept by the update kernel) and the
+// constant C0 = H0_k(A=0) D0, i.e. H dD + (H - H0) D0 in one product; FP64
+// keeps the cancellation harmless.
+// KG atoms per row group; CPT columns per thread (stride blockDim), which
+// reuses each H value read from LDS CPT times.
+template <int NO, bool DELTA, int OUT, int KG, int CPT>
 __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d,
                                               const double2 *__restrict__ d0, int n,
                                               const double2 *__restrict__ hq,
@@ -346,25 +349,31 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
                                               void *__restrict__ wout, int np, int nk,
                                               float2 *__restrict__ w32) {
   constexpr int E2 = NO * NO;
-  constexpr int CP = kEntChunk * kGroup;       // pair blocks per chunk, at most
+  constexpr int CP = kEntChunk * KG;           // pair blocks per chunk, at most
   __shared__ double2 hs[CP * E2];
   __shared__ int s_j[kEntChunk], s_mask[kEntChunk], s_pp[kEntChunk];
   const int grp = blockIdx.y, k = blockIdx.z;
-  const int I0 = grp * kGroup;
+  const int I0 = grp * KG;
   const int tid = threadIdx.x;
-  const int col = blockIdx.x * blockDim.x + tid;
-  const int cl = col < n ? col : n - 1;        // clamped column for loads
+  int col[CPT], cl[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    col[c] = blockIdx.x * blockDim.x * CPT + c * blockDim.x + tid;
+    cl[c] = col[c] < n ? col[c] : n - 1;       // clamped column for loads
+  }
   const size_t base = (size_t)k * n * n;
-  double2 acc[kGroup][NO];
+  double2 acc[KG][NO][CPT];
 #pragma unroll
-  for (int il = 0; il < kGroup; ++il)
+  for (int il = 0; il < KG; ++il)
 #pragma unroll
-    for (int mu = 0; mu < NO; ++mu) acc[il][mu] = make_double2(0.0, 0.0);
+    for (int mu = 0; mu < NO; ++mu)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) acc[il][mu][c] = make_double2(0.0, 0.0);
   const int e0 = g.grp_ptr[grp], e1 = g.grp_ptr[grp + 1];
   for (int ec = e0; ec < e1; ec += kEntChunk) {
     const int ne = min(kEntChunk, e1 - ec);
     const int q0 = g.ent_pp[ec];
-    const int nq = g.ent_pp[ec + ne] - q0;     // <= ne * kGroup
+    const int nq = g.ent_pp[ec + ne] - q0;     // <= ne * KG
     const size_t hoff = ((size_t)k * g.n_pairs + q0) * E2;
     for (int t = tid; t < nq * E2; t += blockDim.x) hs[t] = hq[hoff + t];
     if (tid < ne) {
@@ -374,38 +383,30 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
     }
     __syncthreads();
     // Software pipeline: the D rows of neighbour el+1 load while el is applied.
-    double2 dv[NO], dn[NO], rn[NO];
+    double2 dv[NO][CPT], dn[NO][CPT];
     {
       const int J = s_j[0];
 #pragma unroll
-      for (int nu = 0; nu < NO; ++nu) {
-        const size_t idx = base + (size_t)(J * NO + nu) * n + cl;
-        dn[nu] = d[idx];
-        if (DELTA) rn[nu] = d0[idx];
-      }
+      for (int nu = 0; nu < NO; ++nu)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) dn[nu][c] = d[base + (size_t)(J * NO + nu) * n + cl[c]];
     }
     for (int el = 0; el < ne; ++el) {
 #pragma unroll
-      for (int nu = 0; nu < NO; ++nu) {
-        dv[nu] = dn[nu];
-        if (DELTA) {
-          dv[nu].x += rn[nu].x;
-          dv[nu].y += rn[nu].y;
-        }
-      }
+      for (int nu = 0; nu < NO; ++nu)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) dv[nu][c] = dn[nu][c];
       if (el + 1 < ne) {
         const int J = s_j[el + 1];
 #pragma unroll
-        for (int nu = 0; nu < NO; ++nu) {
-          const size_t idx = base + (size_t)(J * NO + nu) * n + cl;
-          dn[nu] = d[idx];
-          if (DELTA) rn[nu] = d0[idx];
-        }
+        for (int nu = 0; nu < NO; ++nu)
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) dn[nu][c] = d[base + (size_t)(J * NO + nu) * n + cl[c]];
       }
       const int mask = s_mask[el];
       int slot = s_pp[el];
 #pragma unroll
-      for (int il = 0; il < kGroup; ++il) {
+      for (int il = 0; il < KG; ++il) {
         if (mask & (1 << il)) {
           const double2 *h = hs + slot * E2;
 #pragma unroll
@@ -413,10 +414,13 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
 #pragma unroll
             for (int nu = 0; nu < NO; ++nu) {
               const double2 hv = h[mu * NO + nu];
-              acc[il][mu].x = fma(hv.x, dv[nu].x, acc[il][mu].x);
-              acc[il][mu].x = fma(-hv.y, dv[nu].y, acc[il][mu].x);
-              acc[il][mu].y = fma(hv.x, dv[nu].y, acc[il][mu].y);
-              acc[il][mu].y = fma(hv.y, dv[nu].x, acc[il][mu].y);
+#pragma unroll
+              for (int c = 0; c < CPT; ++c) {
+                acc[il][mu][c].x = fma(hv.x, dv[nu][c].x, acc[il][mu][c].x);
+                acc[il][mu][c].x = fma(-hv.y, dv[nu][c].y, acc[il][mu][c].x);
+                acc[il][mu][c].y = fma(hv.x, dv[nu][c].y, acc[il][mu][c].y);
+                acc[il][mu][c].y = fma(hv.y, dv[nu][c].x, acc[il][mu][c].y);
+              }
             }
           ++slot;
         }
@@ -424,19 +428,23 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
     }
     __syncthreads();
   }
-  if (col < n) {
 #pragma unroll
-    for (int il = 0; il < kGroup; ++il) {
+  for (int c = 0; c < CPT; ++c) {
+    if (col[c] >= n) continue;
+#pragma unroll
+    for (int il = 0; il < KG; ++il) {
       if (I0 + il < g.n_atoms) {
-        if (DELTA) {
+        double2 out[NO];
 #pragma unroll
-          for (int mu = 0; mu < NO; ++mu) {
-            const double2 cv = c0[base + (size_t)((I0 + il) * NO + mu) * n + col];
-            acc[il][mu].x -= cv.x;
-            acc[il][mu].y -= cv.y;
+        for (int mu = 0; mu < NO; ++mu) {
+          out[mu] = acc[il][mu][c];
+          if (DELTA) {
+            const double2 cv = c0[base + (size_t)((I0 + il) * NO + mu) * n + col[c]];
+            out[mu].x -= cv.x;
+            out[mu].y -= cv.y;
           }
         }
-        store_rows<NO, OUT>(acc[il], (I0 + il) * NO, col, k, n, np, nk, wout, w32);
+        store_rows<NO, OUT>(out, (I0 + il) * NO, col[c], k, n, np, nk, wout, w32);
       }
     }
   }
@@ -450,12 +458,15 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
 // m0 (may be null): a constant term -i X0 added as fac * m0, where
 // X0 = S^-1 H0 D0 - D0 H0 S^-1 is the part of dD/dt the deviation form leaves
 // out when the reference density D0 is not stationary.
+// ref / dfull (deviation forms): also write the full density D0 + dD of the
+// new level, the operand of the next step's sparse product and observables.
 template <typename YT, bool SPLIT>
 __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
                                                 const float2 *__restrict__ wsplit,
                                                 const double2 *__restrict__ m0,
                                                 const double2 *dbase, double2 *dout, int n,
-                                                double fac) {
+                                                double fac, const double2 *__restrict__ ref,
+                                                double2 *__restrict__ dfull) {
   __shared__ double2 tt[32][33];
   const int k = blockIdx.z;
   const size_t base = (size_t)k * n * n;
@@ -498,6 +509,10 @@ __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
         o.y += fac * mv.y;
       }
       dout[idx] = o;
+      if (dfull != nullptr) {
+        const double2 r0 = ref[idx];
+        dfull[idx] = make_double2(r0.x + o.x, r0.y + o.y);
+      }
     }
   }
 }
@@ -634,7 +649,8 @@ __global__ void k_trace_factors(const double *__restrict__ tpart, double *target
 // in-place update never races with its mirror.
 __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
                                                  const double2 *__restrict__ d0,
-                                                 const double *__restrict__ fac, int n, int nt) {
+                                                 const double *__restrict__ fac, int n, int nt,
+                                                 double2 *__restrict__ dfull) {
   __shared__ double2 t1[32][33], t2[32][33];
   const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
   if (bi > bj) return;
@@ -671,7 +687,9 @@ __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
       const double2 a = t1[r][tx], m = t2[tx][r];        // D[i][j], D[j][i]
       const size_t idx = base + (size_t)i1 * n + j1;
       const double2 r0 = d0[idx];
-      d[idx] = make_double2(c * 0.5 * (a.x + m.x) - r0.x, c * 0.5 * (a.y - m.y) - r0.y);
+      const double2 dd = make_double2(c * 0.5 * (a.x + m.x) - r0.x, c * 0.5 * (a.y - m.y) - r0.y);
+      d[idx] = dd;
+      if (lev == 0) dfull[idx] = make_double2(r0.x + dd.x, r0.y + dd.y);
     }
     if (bi != bj) {
       const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
@@ -679,7 +697,9 @@ __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
         const double2 b = t2[r][tx], m = t1[tx][r];
         const size_t idx = base + (size_t)i2 * n + j2;
         const double2 r0 = d0[idx];
-        d[idx] = make_double2(c * 0.5 * (b.x + m.x) - r0.x, c * 0.5 * (b.y - m.y) - r0.y);
+        const double2 dd = make_double2(c * 0.5 * (b.x + m.x) - r0.x, c * 0.5 * (b.y - m.y) - r0.y);
+        d[idx] = dd;
+        if (lev == 0) dfull[idx] = make_double2(r0.x + dd.x, r0.y + dd.y);
       }
     }
   }
@@ -780,11 +800,22 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
 }
 
 template <int NO, bool DELTA, int OUT>
-static void spmm_launch(dim3 grid, int threads, hipStream_t s, const PairGraph &g,
-                        const double2 *d, const double2 *d0, int n, const double2 *hq,
-                        const double2 *c0, void *w, int np, int nk, float2 *w32) {
-  hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT>), grid, dim3(threads), 0, s, g, d, d0, n, hq, c0, w,
-                     np, nk, w32);
+static void spmm_launch(int threads, hipStream_t s, const PairGraph &g, const double2 *d,
+                        const double2 *d0, int n, const double2 *hq, const double2 *c0, void *w,
+                        int np, int nk, float2 *w32, int cpt) {
+  const int ng = g.n_groups;
+  if (g.group_size == 8 && cpt == 1)
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 1>), dim3(blocks_for(n, threads), ng, nk),
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+  else if (g.group_size == 4 && cpt == 2)
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 2>), dim3(blocks_for(n, 2 * threads), ng, nk),
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+  else if (g.group_size == 4 && cpt == 1)
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 1>), dim3(blocks_for(n, threads), ng, nk),
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+  else
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 2>), dim3(blocks_for(n, 2 * threads), ng, nk),
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
 }
 
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
@@ -797,10 +828,9 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f
 
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, hipStream_t s) {
+                 float2 *w32, int cpt, hipStream_t s) {
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
-  dim3 grid(blocks_for(n, threads), g.n_groups, nk);
-#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(grid, threads, s, g, d, d0, n, hq, c0, w, np, nk, w32)
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt)
   if (g.norb == 4) {
     if (!d0) VG_SPMM(4, false, 0);
     else if (out_format == 0) VG_SPMM(4, true, 0);
@@ -819,20 +849,24 @@ void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n,
                    double fac, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
-                     (const double2 *)nullptr, dbase, dout, n, fac);
+                     (const double2 *)nullptr, dbase, dout, n, fac, (const double2 *)nullptr,
+                     (double2 *)nullptr);
 }
 
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
-                         double2 *dout, int n, int nk, double fac, hipStream_t s) {
+                         double2 *dout, int n, int nk, double fac, const double2 *ref,
+                         double2 *dfull, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
-  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac);
+  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac,
+                     ref, dfull);
 }
 
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
-                     (const double2 *)nullptr, dbase, dout, n, 1.0);
+                     (const double2 *)nullptr, dbase, dout, n, 1.0, (const double2 *)nullptr,
+                     (double2 *)nullptr);
 }
 
 void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,
@@ -854,14 +888,14 @@ void launch_trace_target(const PairGraph &g, const double2 *dd, const double2 *d
 
 void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 *d0, int n, int nk,
                     const double2 *spk, double *tpart, const double *target, double *fac,
-                    hipStream_t s) {
+                    double2 *dfull, hipStream_t s) {
   dim3 grid(g.n_atoms, nk, 2);
   if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, da, db, d0, n, spk, tpart);
   else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, da, db, d0, n, spk, tpart);
   hipLaunchKernelGGL(k_trace_factors, dim3(blocks_for(2 * nk, 64)), dim3(64), 0, s, tpart,
                      const_cast<double *>(target), fac, nk, g.n_atoms, 0);
   const int nt = (int)blocks_for(n, 32);
-  hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, d0, fac, n, nt);
+  hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, d0, fac, n, nt, dfull);
 }
 
 void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -56,9 +57,19 @@ struct HostGraph {
   std::vector<int> grp_ptr, ent_j, ent_mask, ent_pp, gp_pair, gp_il;
 };
 
-// Row groups of kGroup consecutive atoms and the union of their neighbours.
-void build_groups(HostGraph &hg) {
-  const int G = vgtb::kGroup;
+// Sparse-product tuning: atoms per row group and columns per thread
+// (VGTB_SPMM_GROUP in {4, 8}, VGTB_SPMM_CPT in {1, 2}; defaults 8 and 1).
+int spmm_group_size() {
+  const char *e = std::getenv("VGTB_SPMM_GROUP");
+  return (e && std::atoi(e) == 4) ? 4 : 8;
+}
+int spmm_cols_per_thread() {
+  const char *e = std::getenv("VGTB_SPMM_CPT");
+  return (e && std::atoi(e) == 2) ? 2 : 1;
+}
+
+// Row groups of G consecutive atoms and the union of their neighbours.
+void build_groups(HostGraph &hg, int G) {
   const int ng = (hg.na + G - 1) / G;
   hg.grp_ptr.assign(1, 0);
   hg.ent_pp.assign(1, 0);
@@ -165,7 +176,7 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
       msg = "atom " + std::to_string(i) + " has no blocks (an on-site block is required)";
       return VGTB_E_INVAL;
     }
-  build_groups(hg);
+  build_groups(hg, spmm_group_size());
   return VGTB_OK;
 }
 
@@ -286,8 +297,9 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->tfac = cv.template take<double>((size_t)2 * z.nk);
     c->trace0 = cv.template take<double>(z.nk);
     c->m0 = cv.template take<double2>(n2);
+    c->dfull = cv.template take<double2>(n2);
   } else {
-    c->m0 = nullptr;
+    c->m0 = c->dfull = nullptr;
     c->sinv_lo = c->w_lo = nullptr;
     c->y_lo = c->w32 = nullptr;
     c->tpart = c->tfac = c->trace0 = nullptr;
@@ -307,7 +319,7 @@ struct SizeProbe {
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
   double *tpart, *tfac, *trace0;
-  double2 *m0;
+  double2 *m0, *dfull;
 };
 
 struct DevPtrs : SizeProbe {};
@@ -371,10 +383,12 @@ void timed(vgtb_ctx *c, int id, F &&launch) {
 // Deviation forms: C0 = H0_k(A=0) D0 (constant part of the sparse product)
 // and, for a reference that is not stationary, m0 = -i (S^-1 C0 - C0^dag S^-1).
 void prepare_reference(vgtb_ctx *c, bool with_m0) {
+  // full density of the current level (dlev[cur] is the deviation)
+  vgtb::launch_add(c->d0, c->dlev[c->cur], c->dfull, (size_t)c->n * c->n * c->nk, c->stream);
   const vgtb::StepField f0{0.0, 0.0, 0.0};
   vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, c->stream);
   vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
-                    c->stream);
+                    c->spmm_cpt, c->stream);
   c->m0_active = with_m0;
   if (!with_m0) return;
   vgtb::launch_zgemm_f64(c->sinv, c->c0, c->y, c->n, c->nk, c->stream);
@@ -475,6 +489,8 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.img_d = dp.g.img_d;
   c->g.img_h0 = dp.g.img_h0;
   c->g.img_s = dp.g.img_s;
+  c->g.group_size = spmm_group_size();
+  c->spmm_cpt = spmm_cols_per_thread();
   c->g.n_groups = z.ng;
   c->g.n_entries = z.ne;
   c->g.grp_ptr = dp.g.grp_ptr;
@@ -513,6 +529,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->tfac = dp.tfac;
   c->trace0 = dp.trace0;
   c->m0 = dp.m0;
+  c->dfull = dp.dfull;
 
   hipStream_t st_ = c->stream;
 #define CREATE_HIP(expr)                                                              \
@@ -629,12 +646,12 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
   double2 *dtarget = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
   vgtb::launch_density_from_vectors(c->y, c->occ, dtarget, n, nk, s);
   HIP_TRY(c, hipGetLastError());
+  c->cur = 0;
   if (c->precision != VGTB_FP64) {
     vgtb::launch_fill_zero(c->dlev[0], n2, s);
     vgtb::launch_trace_target(c->g, c->dlev[0], c->d0, n, nk, c->spk, c->tpart, c->trace0, s);
     prepare_reference(c, false);   // the ground state commutes with S^-1 H0: no m0 term
   }
-  c->cur = 0;
   c->have_density = true;
   c->have_prev = false;
   c->step = 0;
@@ -663,6 +680,7 @@ vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   double2 *target = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
   HIP_TRY(c, hipMemcpyAsync(target, d, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  c->cur = 0;
   if (c->precision != VGTB_FP64) {
     const size_t n2 = (size_t)c->n * c->n * c->nk;
     vgtb::launch_fill_zero(c->dlev[0], n2, c->stream);
@@ -710,10 +728,10 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     const vgtb::StepField f{a[0] / vgtb::kLightSpeed, a[1] / vgtb::kLightSpeed, a[2] / vgtb::kLightSpeed};
     double2 *dcur = c->dlev[c->cur];
     double2 *doth = c->dlev[c->cur ^ 1];
-    const double2 *ref = dev ? c->d0 : nullptr;
+    const double2 *dfull = dev ? c->dfull : dcur;   // full density of level n
     double *hrow = c->hist + (size_t)(c->step % c->hist_cap) * (5 + c->na);
     timed(c, VGTB_K_OBSERVE, [&] {
-      vgtb::launch_observe(c->g, dcur, ref, n, c->kpts_dev, nk, f, c->spk, c->part, s);
+      vgtb::launch_observe(c->g, dfull, nullptr, n, c->kpts_dev, nk, f, c->spk, c->part, s);
     });
     timed(c, VGTB_K_REDUCE, [&] {
       vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
@@ -724,7 +742,8 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     });
     if (!dev) {
       timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr, s);
+        vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr,
+                          c->spmm_cpt, s);
       });
       timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
       timed(c, VGTB_K_UPDATE, [&] {
@@ -739,7 +758,8 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       // S^-1 W = W + (S^-1 - I) W with only the second term in reduced precision.
       const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
       timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32, s);
+        vgtb::launch_spmm(c->g, dfull, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32,
+                          c->spmm_cpt, s);
       });
       timed(c, VGTB_K_GEMM, [&] {
         if (fmt == 1)
@@ -753,9 +773,10 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       const double2 *m0 = c->m0_active ? c->m0 : nullptr;
       timed(c, VGTB_K_UPDATE, [&] {
         if (c->have_prev)
-          vgtb::launch_update_split(c->y_lo, wid, m0, doth, doth, n, nk, 2.0 * c->dt, s);
+          vgtb::launch_update_split(c->y_lo, wid, m0, doth, doth, n, nk, 2.0 * c->dt, c->d0,
+                                    c->dfull, s);
         else
-          vgtb::launch_update_split(c->y_lo, wid, m0, dcur, doth, n, nk, c->dt, s);
+          vgtb::launch_update_split(c->y_lo, wid, m0, dcur, doth, n, nk, c->dt, c->d0, c->dfull, s);
       });
     }
     c->cur ^= 1;
@@ -764,7 +785,7 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     if (dev && c->rescale_every > 0 && c->step % c->rescale_every == 0) {
       timed(c, VGTB_K_RESCALE, [&] {
         vgtb::launch_rescale(c->g, c->dlev[c->cur], c->dlev[c->cur ^ 1], c->d0, n, nk, c->spk,
-                             c->tpart, c->trace0, c->tfac, s);
+                             c->tpart, c->trace0, c->tfac, c->dfull, s);
       });
     }
   }

@@ -15,8 +15,6 @@ namespace vgtb {
 
 constexpr double kLightSpeed = 137.035999084;
 
-// Atoms per row group of the sparse product (consecutive atom indices).
-constexpr int kGroup = 8;
 
 // Workgroup scheduling.  The dispatcher hands consecutive workgroup ids to the
 // eight XCDs in turn, and each XCD has its own L2.  xcd_slot() renumbers a
@@ -42,13 +40,13 @@ __device__ inline void grouped_tile(int tile, int tiles_m, int tiles_n, int gm, 
 // of row atom I are row_ptr[I] .. row_ptr[I+1]-1, sorted by J; the periodic
 // images of pair p are img_ptr[p] .. img_ptr[p+1]-1.
 //
-// Row groups of kGroup atoms: group g's neighbour union is entries
-// grp_ptr[g] .. grp_ptr[g+1]-1; entry e is atom ent_j[e] with bit il of
-// ent_mask[e] set when atom g*kGroup + il pairs with it; its pairs, in il
+// Row groups of group_size consecutive atoms (4 or 8): group g's neighbour
+// union is entries grp_ptr[g] .. grp_ptr[g+1]-1; entry e is atom ent_j[e]
+// with bit il of ent_mask[e] set when atom g*group_size + il pairs with it; its pairs, in il
 // order, are gp_pair[ent_pp[e] .. ent_pp[e+1]-1] (local atom gp_il[...]).
 struct PairGraph {
   int n_atoms = 0, norb = 0, n_pairs = 0, n_images = 0;
-  int n_groups = 0, n_entries = 0;
+  int group_size = 8, n_groups = 0, n_entries = 0;
   const int *grp_ptr = nullptr;   // n_groups + 1
   const int *ent_j = nullptr;     // n_entries
   const int *ent_mask = nullptr;  // n_entries
@@ -88,13 +86,15 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f
 // 1 complex64, 2 bf16 planes (k-packed, padded np) + complex64 copy w32.
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, hipStream_t s);
+                 float2 *w32, int cpt, hipStream_t s);
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, hipStream_t s);
 // D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each);
 // m0 may be null.
+// Also writes dfull = ref + D_out (the full density of the new level).
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
-                         double2 *dout, int n, int nk, double fac, hipStream_t s);
+                         double2 *dout, int n, int nk, double fac, const double2 *ref,
+                         double2 *dfull, hipStream_t s);
 // D_out = D_base - i (Y - Y^dag) (used to form the constant term m0 = -i X0).
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s);
@@ -102,9 +102,10 @@ void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk
                             hipStream_t s);
 void launch_trace_target(const PairGraph &g, const double2 *dd, const double2 *d0, int n, int nk,
                          const double2 *spk, double *tpart, double *target, hipStream_t s);
+// da is the current level; dfull (its full density D0 + dD) is refreshed.
 void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 *d0, int n, int nk,
                     const double2 *spk, double *tpart, const double *target, double *fac,
-                    hipStream_t s);
+                    double2 *dfull, hipStream_t s);
 void launch_add(const double2 *a, const double2 *b, double2 *out, size_t count, hipStream_t s);
 // sigma and epsilon interleaved in out (2 * nw complex); j and omega on the device.
 void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
@@ -129,6 +130,7 @@ struct vgtb_ctx {
   int na = 0, no = 0, n = 0, nk = 0;
   double volume = 0.0, n_electrons = 0.0, dt = 0.0;
   int precision = 0, rescale_every = 0, hist_cap = 1;
+  int spmm_cpt = 1;            // columns per thread of the sparse product
   bool scc = false, z_from_ground_state = false;
 
   hipStream_t stream = nullptr;
@@ -172,6 +174,7 @@ struct vgtb_ctx {
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk
   double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density
+  double2 *dfull = nullptr;    // nk * n * n, D0 + dD of the current level
   bool m0_active = false;
 
   // per-kernel event timing (vgtb_profile_*)
