@@ -55,7 +55,7 @@ typedef enum {
 
 typedef enum {
   VGTB_FP64 = 0,   /* every product in FP64 on the FP64 matrix cores                       */
-  VGTB_FP32 = 1,   /* deviation form, S^-1 (H dD + dH D0) product in FP32 on matrix cores  */
+  VGTB_FP32 = 1,   /* deviation form, S^-1 (H D - H0 D0) product in FP32 on matrix cores   */
   VGTB_BF16X3 = 2  /* deviation form, the same product as three BF16 products (hi/lo split) */
 } vgtb_precision;
 
@@ -135,7 +135,7 @@ vgtb_status vgtb_ground_state(vgtb_ctx *ctx, double *min_gap_host);
  * Set D_k(0) from n_k * N * N complex128 values (on_device != 0: device
  * pointer read on the context stream; else host).  Resets the step index to
  * 0 and forgets the previous level.  In the deviation forms this density
- * is the reference D0 and the deviation starts at zero.
+ * also becomes the reference D0 of the reduced-precision product.
  */
 vgtb_status vgtb_set_density(vgtb_ctx *ctx, const void *d, int on_device);
 
@@ -196,7 +196,7 @@ void vgtb_destroy(vgtb_ctx *ctx);
 typedef enum {
   VGTB_K_OBSERVE = 0,   /* Mulliken / energy / current sweep of D_n            */
   VGTB_K_REDUCE = 1,    /* k-sum, SCC shift, history row                       */
-  VGTB_K_SPMM = 2,      /* block-sparse W = H D (deviation: H dD + dH D0)      */
+  VGTB_K_SPMM = 2,      /* block-sparse W = H D (deviation forms: H D - H0 D0) */
   VGTB_K_GEMM = 3,      /* dense Y = S^-1 W on the matrix cores (all k)        */
   VGTB_K_UPDATE = 4,    /* leapfrog D_{n+1} = D_{n-1} - 2 i dt (Y - Y^dag)     */
   VGTB_K_RESCALE = 5,   /* deviation forms: re-Hermitise + trace rescale       */

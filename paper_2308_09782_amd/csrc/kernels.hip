@@ -4,8 +4,10 @@
 // reduction with the SCC shift, and the leapfrog update.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "vgtb_internal.h"
 
@@ -85,9 +87,8 @@ __global__ void k_scatter_pairs(PairGraph g, const double *kpts, const double2 *
 // One wavefront per (atom I, k): sweep the pair blocks of row I of D_k and
 // accumulate  q = Re sum D conj(S)  (Mulliken, row I),  E = Re sum conj(D) H0,
 // J^a = Re sum conj(D) Pi^a  with Pi^a = sum_images i d^a exp(i(k+A/c).d) H0.
-template <int NO, bool DELTA>
-__global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__restrict__ d,
-                                                const double2 *__restrict__ d0, int n,
+template <int NO>
+__global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__restrict__ d, int n,
                                                 const double *kpts, StepField f,
                                                 const double2 *__restrict__ spk,
                                                 double *__restrict__ part) {
@@ -104,12 +105,7 @@ __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__re
   for (int p = g.row_ptr[I] + slot; p < p1; p += P) {
     const int J = g.pair_col[p];
     const size_t idx = base + (size_t)(I * NO + mu) * n + (J * NO + nu);
-    double2 dv = d[idx];
-    if (DELTA) {
-      const double2 r = d0[idx];
-      dv.x += r.x;
-      dv.y += r.y;
-    }
+    const double2 dv = d[idx];
     const double2 s = spk[((size_t)k * g.n_pairs + p) * E2 + e];
     q += dv.x * s.x + dv.y * s.y;
     for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
@@ -245,10 +241,9 @@ __device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
   lo = to_bf16(xf - from_bf16(hi));
 }
 
-// Fused assembly + block-sparse product W = H_k D_k (Eqs. 8-10).
+// Block-sparse product W = H_k D_k (Eqs. 8-10) over the pair blocks
 //   H_k(I,J) = sum_images exp(i(k+A/c).d) H0 + 1/2 (V_I + V_J) S_k(I,J)
-// DELTA: the deviation form W = H_k dD + dH_k D0, dH_k = H_k - H0_k(A=0), with
-// exp(i(k+A/c).d) - exp(i k.d) = 2 sin(a/2) i exp(i(k.d + a/2)), a = A.d/c.
+// that k_assemble writes in grouped order.
 //
 // A workgroup owns the rows of KG consecutive atoms and one chunk of
 // columns (one column per thread).  It walks the union of those atoms'
@@ -336,9 +331,9 @@ __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpt
   hq[((size_t)k * g.n_pairs + q) * E2 + e] = h;
 }
 
-// DELTA: W = H_k D - C0 with D = D0 + dD (kept by the update kernel) and the
-// constant C0 = H0_k(A=0) D0, i.e. H dD + (H - H0) D0 in one product; FP64
-// keeps the cancellation harmless.
+// DELTA: W = H_k D - C0 with the constant C0 = H0_k(A=0) D0 of a reference
+// density D0, i.e. H (D - D0) + (H - H0) D0 in one product; FP64 keeps the
+// cancellation harmless.
 // KG atoms per row group; CPT columns per thread (stride blockDim), which
 // reuses each H value read from LDS CPT times.
 template <int NO, bool DELTA, int OUT, int KG, int CPT>
@@ -450,6 +445,144 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
   }
 }
 
+// The same product on the FP64 matrix cores (four orbitals per atom).  One
+// v_mfma_f64_4x4x4_4b multiplies a 4x4 pair block by 16 consecutive columns
+// of the neighbour's four D rows, the four blocks of the instruction being
+// four 4-column slices that share the pair block.  It is issued transposed,
+// A = D^T and B = H^T, so that
+//   A operand of lane l: D[4J + (l >> 4)][c0 + (l & 15)]   (coalesced rows)
+//   B operand of lane l: H[I][l & 3][l >> 4]               (one LDS read)
+//   result of lane l:    W[4I + (l & 3)][c0 + 4((l >> 2) & 3) + (l >> 4)]
+// with the four rows of an atom in four neighbouring lanes.  A wave owns CB
+// such 16-column slices; complex arithmetic is four real products per slice
+// (re += Dr Hr - Di Hi, im += Di Hr + Dr Hi) into separate accumulators.
+// Compared with the vector form, one LDS read of H now feeds 16 matrix
+// instructions instead of four FMAs, and no zero blocks are multiplied.
+__device__ inline double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+template <bool DELTA, int OUT, int KG, int CB>
+__global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *__restrict__ d,
+                                                   int n, const double2 *__restrict__ hq,
+                                                   const double2 *__restrict__ c0,
+                                                   void *__restrict__ wout, int np, int nk,
+                                                   float2 *__restrict__ w32) {
+  constexpr int E2 = 16;
+  constexpr int CP = kEntChunk * KG;
+  __shared__ double2 hs[CP * E2];
+  __shared__ int s_j[kEntChunk], s_mask[kEntChunk], s_pp[kEntChunk];
+  const int grp = blockIdx.y, k = blockIdx.z;
+  const int I0 = grp * KG;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int cw = (blockIdx.x * (blockDim.x >> 6) + (tid >> 6)) * 16 * CB;   // first column of the wave
+  const int nu = lane >> 4;                   // D row (orbital of J) of the A operand
+  const int hsel = (lane & 3) * 4 + nu;       // H[mu][nu] of the B operand
+  int lcol[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) lcol[cb] = min(cw + cb * 16 + (lane & 15), n - 1);
+  const size_t base = (size_t)k * n * n;
+  double accr[KG][CB], acci[KG][CB];
+#pragma unroll
+  for (int il = 0; il < KG; ++il)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) accr[il][cb] = acci[il][cb] = 0.0;
+  // Every atom has at least its on-site block (checked when the graph is
+  // built), so a group has at least one entry and the loop runs at least
+  // once; saying so keeps the accumulators in place up to the epilogue.
+  const int e0 = g.grp_ptr[grp], e1 = max(g.grp_ptr[grp + 1], e0 + 1);
+  int ec = e0;
+  do {
+    const int ne = min(kEntChunk, e1 - ec);
+    const int q0 = g.ent_pp[ec];
+    const int nq = g.ent_pp[ec + ne] - q0;
+    const size_t hoff = ((size_t)k * g.n_pairs + q0) * E2;
+    for (int t = tid; t < nq * E2; t += blockDim.x) hs[t] = hq[hoff + t];
+    if (tid < ne) {
+      s_j[tid] = g.ent_j[ec + tid];
+      s_mask[tid] = g.ent_mask[ec + tid];
+      s_pp[tid] = g.ent_pp[ec + tid] - q0;
+    }
+    __syncthreads();
+    // The D rows of neighbour el + 1 load while el is applied.
+    double2 dv[CB], dn[CB];
+    {
+      const size_t roff = base + (size_t)(s_j[0] * 4 + nu) * n;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) dn[cb] = d[roff + lcol[cb]];
+    }
+    for (int el = 0; el < ne; ++el) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) dv[cb] = dn[cb];
+      if (el + 1 < ne) {
+        const size_t roff = base + (size_t)(s_j[el + 1] * 4 + nu) * n;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) dn[cb] = d[roff + lcol[cb]];
+      }
+      const int mask = __builtin_amdgcn_readfirstlane(s_mask[el]);
+      int slot = __builtin_amdgcn_readfirstlane(s_pp[el]);
+#pragma unroll
+      for (int il = 0; il < KG; ++il) {
+        if (mask & (1 << il)) {
+          const double2 h = hs[slot * E2 + hsel];
+          const double nhi = -h.y;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            accr[il][cb] = mfma4(dv[cb].x, h.x, accr[il][cb]);
+            acci[il][cb] = mfma4(dv[cb].y, h.x, acci[il][cb]);
+            accr[il][cb] = mfma4(dv[cb].y, nhi, accr[il][cb]);
+            acci[il][cb] = mfma4(dv[cb].x, h.y, acci[il][cb]);
+          }
+          ++slot;
+        }
+      }
+    }
+    __syncthreads();
+    ec += kEntChunk;
+  } while (ec < e1);
+  const int mu = lane & 3;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int col = cw + cb * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+#pragma unroll
+    for (int il = 0; il < KG; ++il) {
+      const int r = (I0 + il) * 4 + mu;
+      const bool ok = col < n && I0 + il < g.n_atoms;
+      double2 out = make_double2(accr[il][cb], acci[il][cb]);
+      if (DELTA && ok) {
+        const double2 cv = c0[base + (size_t)r * n + col];
+        out.x -= cv.x;
+        out.y -= cv.y;
+      }
+      if (OUT == 0) {
+        if (ok) static_cast<double2 *>(wout)[base + (size_t)r * n + col] = out;
+      } else if (OUT == 1) {
+        if (ok) static_cast<float2 *>(wout)[base + (size_t)r * n + col] = make_float2((float)out.x, (float)out.y);
+      } else {
+        if (ok) w32[base + (size_t)r * n + col] = make_float2((float)out.x, (float)out.y);
+        // bf16 planes: the four rows of the atom sit in lanes 4m..4m+3; lane 4m
+        // gathers them and writes one 8-byte word per plane.
+        uint16_t hv[4];
+        split_bf16(out.x, hv[0], hv[1]);
+        split_bf16(out.y, hv[2], hv[3]);
+        uint16_t *w = static_cast<uint16_t *>(wout);
+        const size_t plane = (size_t)nk * np * np;
+        const size_t off = (size_t)k * np * np + ((size_t)(r >> 3) * np + col) * 8 + (r & 7);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const uint32_t v = hv[p];
+          const uint32_t lo = v | ((uint32_t)__shfl_down((int)v, 1) << 16);
+          const uint32_t hi = (uint32_t)__shfl_down((int)lo, 2);
+          if (ok && mu == 0) *reinterpret_cast<uint2 *>(w + p * plane + off) = make_uint2(lo, hi);
+        }
+      }
+      // One atom's results at a time: keeps the accumulators from being
+      // moved out of the matrix registers all at once.
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 // Leapfrog (Eq. 13) in the form D_out = D_base - i fac (Y - Y^dag), Y = S^-1 H D,
 // so that dD/dt = -i (Y - Y^dag) is anti-Hermitian bit for bit.  32x32 tiles;
 // the transposed partner tile of Y is staged through LDS.
@@ -458,15 +591,12 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
 // m0 (may be null): a constant term -i X0 added as fac * m0, where
 // X0 = S^-1 H0 D0 - D0 H0 S^-1 is the part of dD/dt the deviation form leaves
 // out when the reference density D0 is not stationary.
-// ref / dfull (deviation forms): also write the full density D0 + dD of the
-// new level, the operand of the next step's sparse product and observables.
 template <typename YT, bool SPLIT>
 __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
                                                 const float2 *__restrict__ wsplit,
                                                 const double2 *__restrict__ m0,
                                                 const double2 *dbase, double2 *dout, int n,
-                                                double fac, const double2 *__restrict__ ref,
-                                                double2 *__restrict__ dfull) {
+                                                double fac) {
   __shared__ double2 tt[32][33];
   const int k = blockIdx.z;
   const size_t base = (size_t)k * n * n;
@@ -509,10 +639,6 @@ __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
         o.y += fac * mv.y;
       }
       dout[idx] = o;
-      if (dfull != nullptr) {
-        const double2 r0 = ref[idx];
-        dfull[idx] = make_double2(r0.x + o.x, r0.y + o.y);
-      }
     }
   }
 }
@@ -608,11 +734,10 @@ __global__ void k_convert_operand(const double2 *__restrict__ src, void *__restr
   }
 }
 
-// Per-row partial traces Re sum_{pairs of I} (D0 + dD)_{mu nu} conj(S_{mu nu}) of one level.
+// Per-row partial traces Re sum_{pairs of I} D_{mu nu} conj(S_{mu nu}) of one level.
 template <int NO>
 __global__ __launch_bounds__(64) void k_trace_rows(PairGraph g, const double2 *__restrict__ da,
-                                                   const double2 *__restrict__ db,
-                                                   const double2 *__restrict__ d0, int n,
+                                                   const double2 *__restrict__ db, int n,
                                                    const double2 *__restrict__ spk, double *tpart) {
   constexpr int E2 = NO * NO;
   constexpr int P = 64 / E2;
@@ -623,8 +748,8 @@ __global__ __launch_bounds__(64) void k_trace_rows(PairGraph g, const double2 *_
   double q = 0.0;
   for (int p = g.row_ptr[I] + slot; p < g.row_ptr[I + 1]; p += P) {
     const size_t idx = base + (size_t)(I * NO + mu) * n + (g.pair_col[p] * NO + nu);
-    const double2 a = d[idx], r = d0[idx], sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
-    q += (a.x + r.x) * sv.x + (a.y + r.y) * sv.y;
+    const double2 a = d[idx], sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+    q += a.x * sv.x + a.y * sv.y;
   }
   q = wave_sum(q);
   if (lane == 0) tpart[((size_t)lev * gridDim.y + k) * g.n_atoms + I] = q;
@@ -644,13 +769,10 @@ __global__ void k_trace_factors(const double *__restrict__ tpart, double *target
   }
 }
 
-// Both levels: D <- c * 1/2 (D + D^dag) with D = D0 + dD, stored back as a
-// deviation from D0.  Tile pairs (bi <= bj) are handled by one block so the
-// in-place update never races with its mirror.
+// Both levels: D <- c * 1/2 (D + D^dag).  Tile pairs (bi <= bj) are handled
+// by one block so the in-place update never races with its mirror.
 __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
-                                                 const double2 *__restrict__ d0,
-                                                 const double *__restrict__ fac, int n, int nt,
-                                                 double2 *__restrict__ dfull) {
+                                                 const double *__restrict__ fac, int n, int nt) {
   __shared__ double2 t1[32][33], t2[32][33];
   const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
   if (bi > bj) return;
@@ -662,54 +784,25 @@ __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
   for (int r = ty; r < 32; r += 8) {
     const int i1 = bi * 32 + r, j1 = bj * 32 + tx;
     const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
-    double2 z = make_double2(0.0, 0.0), a = z, b = z;
-    if (i1 < n && j1 < n) {
-      const size_t idx = base + (size_t)i1 * n + j1;
-      a = d[idx];
-      const double2 r0 = d0[idx];
-      a.x += r0.x;
-      a.y += r0.y;
-    }
-    if (i2 < n && j2 < n) {
-      const size_t idx = base + (size_t)i2 * n + j2;
-      b = d[idx];
-      const double2 r0 = d0[idx];
-      b.x += r0.x;
-      b.y += r0.y;
-    }
-    t1[r][tx] = a;   // full D, tile (bi, bj)
-    t2[r][tx] = b;   // full D, tile (bj, bi)
+    const double2 z = make_double2(0.0, 0.0);
+    t1[r][tx] = (i1 < n && j1 < n) ? d[base + (size_t)i1 * n + j1] : z;   // tile (bi, bj)
+    t2[r][tx] = (i2 < n && j2 < n) ? d[base + (size_t)i2 * n + j2] : z;   // tile (bj, bi)
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int i1 = bi * 32 + r, j1 = bj * 32 + tx;
     if (i1 < n && j1 < n) {
       const double2 a = t1[r][tx], m = t2[tx][r];        // D[i][j], D[j][i]
-      const size_t idx = base + (size_t)i1 * n + j1;
-      const double2 r0 = d0[idx];
-      const double2 dd = make_double2(c * 0.5 * (a.x + m.x) - r0.x, c * 0.5 * (a.y - m.y) - r0.y);
-      d[idx] = dd;
-      if (lev == 0) dfull[idx] = make_double2(r0.x + dd.x, r0.y + dd.y);
+      d[base + (size_t)i1 * n + j1] = make_double2(c * 0.5 * (a.x + m.x), c * 0.5 * (a.y - m.y));
     }
     if (bi != bj) {
       const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
       if (i2 < n && j2 < n) {
         const double2 b = t2[r][tx], m = t1[tx][r];
-        const size_t idx = base + (size_t)i2 * n + j2;
-        const double2 r0 = d0[idx];
-        const double2 dd = make_double2(c * 0.5 * (b.x + m.x) - r0.x, c * 0.5 * (b.y - m.y) - r0.y);
-        d[idx] = dd;
-        if (lev == 0) dfull[idx] = make_double2(r0.x + dd.x, r0.y + dd.y);
+        d[base + (size_t)i2 * n + j2] = make_double2(c * 0.5 * (b.x + m.x), c * 0.5 * (b.y - m.y));
       }
     }
   }
-}
-
-__global__ void k_add(const double2 *__restrict__ a, const double2 *__restrict__ b,
-                      double2 *__restrict__ out, size_t count) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < count; i += stride) out[i] = make_double2(a[i].x + b[i].x, a[i].y + b[i].y);
 }
 
 // Filtered Fourier transform of the current (Eq. 15) and the dielectric
@@ -774,17 +867,11 @@ void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const 
                      spk, which, dense, n);
 }
 
-void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int n,
-                    const double *kpts, int nk, StepField f, const double2 *spk, double *part,
-                    hipStream_t s) {
+void launch_observe(const PairGraph &g, const double2 *d, int n, const double *kpts, int nk,
+                    StepField f, const double2 *spk, double *part, hipStream_t s) {
   dim3 grid(g.n_atoms, nk);
-  if (g.norb == 4) {
-    if (d0) hipLaunchKernelGGL((k_observe<4, true>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
-    else hipLaunchKernelGGL((k_observe<4, false>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
-  } else {
-    if (d0) hipLaunchKernelGGL((k_observe<1, true>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
-    else hipLaunchKernelGGL((k_observe<1, false>), grid, dim3(64), 0, s, g, d, d0, n, kpts, f, spk, part);
-  }
+  if (g.norb == 4) hipLaunchKernelGGL(k_observe<4>, grid, dim3(64), 0, s, g, d, n, kpts, f, spk, part);
+  else hipLaunchKernelGGL(k_observe<1>, grid, dim3(64), 0, s, g, d, n, kpts, f, spk, part);
 }
 
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
@@ -826,9 +913,44 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f
   else hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, f, spk, v, hq);
 }
 
+template <bool DELTA, int OUT, int CB>
+static void spmm_mfma_launch_cb(hipStream_t s, const PairGraph &g, const double2 *d, int n,
+                                const double2 *hq, const double2 *c0, void *w, int np, int nk,
+                                float2 *w32) {
+  const int nw = std::max(1, std::min(4, (n + 16 * CB - 1) / (16 * CB)));
+  dim3 grid(blocks_for(n, 16 * CB * nw), g.n_groups, nk);
+  if (g.group_size == 16)
+    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 16, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq,
+                       c0, w, np, nk, w32);
+  else if (g.group_size == 8)
+    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 8, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
+                       w, np, nk, w32);
+  else
+    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 4, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
+                       w, np, nk, w32);
+}
+
+template <bool DELTA, int OUT>
+static void spmm_mfma_launch(hipStream_t s, const PairGraph &g, const double2 *d, int n,
+                             const double2 *hq, const double2 *c0, void *w, int np, int nk,
+                             float2 *w32, int cb) {
+  if (cb == 4) spmm_mfma_launch_cb<DELTA, OUT, 4>(s, g, d, n, hq, c0, w, np, nk, w32);
+  else if (cb == 2) spmm_mfma_launch_cb<DELTA, OUT, 2>(s, g, d, n, hq, c0, w, np, nk, w32);
+  else spmm_mfma_launch_cb<DELTA, OUT, 1>(s, g, d, n, hq, c0, w, np, nk, w32);
+}
+
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, int cpt, hipStream_t s) {
+                 float2 *w32, int variant, hipStream_t s) {
+  if (g.norb == 4 && variant < 0) {
+    const int cb = -variant;
+    if (!d0) spmm_mfma_launch<false, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
+    else if (out_format == 0) spmm_mfma_launch<true, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
+    else if (out_format == 1) spmm_mfma_launch<true, 1>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
+    else spmm_mfma_launch<true, 2>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
+    return;
+  }
+  const int cpt = variant == 2 ? 2 : 1;
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
 #define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt)
   if (g.norb == 4) {
@@ -849,24 +971,20 @@ void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n,
                    double fac, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
-                     (const double2 *)nullptr, dbase, dout, n, fac, (const double2 *)nullptr,
-                     (double2 *)nullptr);
+                     (const double2 *)nullptr, dbase, dout, n, fac);
 }
 
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
-                         double2 *dout, int n, int nk, double fac, const double2 *ref,
-                         double2 *dfull, hipStream_t s) {
+                         double2 *dout, int n, int nk, double fac, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
-  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac,
-                     ref, dfull);
+  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac);
 }
 
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
-                     (const double2 *)nullptr, dbase, dout, n, 1.0, (const double2 *)nullptr,
-                     (double2 *)nullptr);
+                     (const double2 *)nullptr, dbase, dout, n, 1.0);
 }
 
 void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,
@@ -877,25 +995,24 @@ void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk
                      dst, n, np, nk, fmt);
 }
 
-void launch_trace_target(const PairGraph &g, const double2 *dd, const double2 *d0, int n, int nk,
-                         const double2 *spk, double *tpart, double *target, hipStream_t s) {
+void launch_trace_target(const PairGraph &g, const double2 *dd, int n, int nk, const double2 *spk,
+                         double *tpart, double *target, hipStream_t s) {
   dim3 grid(g.n_atoms, nk, 2);
-  if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, dd, dd, d0, n, spk, tpart);
-  else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, dd, dd, d0, n, spk, tpart);
+  if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, dd, dd, n, spk, tpart);
+  else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, dd, dd, n, spk, tpart);
   hipLaunchKernelGGL(k_trace_factors, dim3(blocks_for(2 * nk, 64)), dim3(64), 0, s, tpart, target,
                      (double *)nullptr, nk, g.n_atoms, 1);
 }
 
-void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 *d0, int n, int nk,
-                    const double2 *spk, double *tpart, const double *target, double *fac,
-                    double2 *dfull, hipStream_t s) {
+void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk, const double2 *spk,
+                    double *tpart, const double *target, double *fac, hipStream_t s) {
   dim3 grid(g.n_atoms, nk, 2);
-  if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, da, db, d0, n, spk, tpart);
-  else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, da, db, d0, n, spk, tpart);
+  if (g.norb == 4) hipLaunchKernelGGL(k_trace_rows<4>, grid, dim3(64), 0, s, g, da, db, n, spk, tpart);
+  else hipLaunchKernelGGL(k_trace_rows<1>, grid, dim3(64), 0, s, g, da, db, n, spk, tpart);
   hipLaunchKernelGGL(k_trace_factors, dim3(blocks_for(2 * nk, 64)), dim3(64), 0, s, tpart,
                      const_cast<double *>(target), fac, nk, g.n_atoms, 0);
   const int nt = (int)blocks_for(n, 32);
-  hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, d0, fac, n, nt, dfull);
+  hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, fac, n, nt);
 }
 
 void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
@@ -908,13 +1025,6 @@ void launch_spectrum(const double *j, int nt, double dt, const double *omega, in
     (void)hipStreamSynchronize(s);
   }
   hipLaunchKernelGGL(k_spectrum, dim3(nw), dim3(64), 0, s, j, nt, dt, jmean, omega, e0, tau0, out);
-}
-
-void launch_add(const double2 *a, const double2 *b, double2 *out, size_t count, hipStream_t s) {
-  unsigned blk = blocks_for(count, 256);
-  if (blk > 65536u) blk = 65536u;
-  if (blk == 0) return;
-  hipLaunchKernelGGL(k_add, dim3(blk), dim3(256), 0, s, a, b, out, count);
 }
 
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s) {

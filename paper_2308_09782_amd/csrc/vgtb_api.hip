@@ -57,15 +57,26 @@ struct HostGraph {
   std::vector<int> grp_ptr, ent_j, ent_mask, ent_pp, gp_pair, gp_il;
 };
 
-// Sparse-product tuning: atoms per row group and columns per thread
-// (VGTB_SPMM_GROUP in {4, 8}, VGTB_SPMM_CPT in {1, 2}; defaults 8 and 1).
-int spmm_group_size() {
-  const char *e = std::getenv("VGTB_SPMM_GROUP");
-  return (e && std::atoi(e) == 4) ? 4 : 8;
-}
-int spmm_cols_per_thread() {
+// Sparse-product tuning, read when a context is created.  VGTB_SPMM_CPT = 1
+// or 2 selects vector FMAs with that many columns per thread (always the
+// vector form for one orbital per atom); otherwise the FP64 matrix cores
+// with VGTB_SPMM_CB (1 default, 2 or 4) 16-column slices per wave.
+// VGTB_SPMM_GROUP: atoms per row group, 4 or 8 (default), or 16 with the
+// matrix-core kernel.
+int spmm_variant() {
   const char *e = std::getenv("VGTB_SPMM_CPT");
-  return (e && std::atoi(e) == 2) ? 2 : 1;
+  const int v = e ? std::atoi(e) : 0;
+  if (v == 1 || v == 2) return v;
+  const char *b = std::getenv("VGTB_SPMM_CB");
+  const int cb = b ? std::atoi(b) : 1;
+  return -(cb == 2 || cb == 4 ? cb : 1);
+}
+int spmm_group_size(int orbs_per_atom) {
+  const bool mfma = orbs_per_atom == 4 && spmm_variant() < 0;
+  const char *e = std::getenv("VGTB_SPMM_GROUP");
+  const int v = e ? std::atoi(e) : 8;
+  if (v == 16 && mfma) return 16;
+  return v == 4 ? 4 : 8;
 }
 
 // Row groups of G consecutive atoms and the union of their neighbours.
@@ -176,7 +187,7 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
       msg = "atom " + std::to_string(i) + " has no blocks (an on-site block is required)";
       return VGTB_E_INVAL;
     }
-  build_groups(hg, spmm_group_size());
+  build_groups(hg, spmm_group_size(no));
   return VGTB_OK;
 }
 
@@ -297,9 +308,8 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->tfac = cv.template take<double>((size_t)2 * z.nk);
     c->trace0 = cv.template take<double>(z.nk);
     c->m0 = cv.template take<double2>(n2);
-    c->dfull = cv.template take<double2>(n2);
   } else {
-    c->m0 = c->dfull = nullptr;
+    c->m0 = nullptr;
     c->sinv_lo = c->w_lo = nullptr;
     c->y_lo = c->w32 = nullptr;
     c->tpart = c->tfac = c->trace0 = nullptr;
@@ -319,7 +329,7 @@ struct SizeProbe {
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
   double *tpart, *tfac, *trace0;
-  double2 *m0, *dfull;
+  double2 *m0;
 };
 
 struct DevPtrs : SizeProbe {};
@@ -383,12 +393,10 @@ void timed(vgtb_ctx *c, int id, F &&launch) {
 // Deviation forms: C0 = H0_k(A=0) D0 (constant part of the sparse product)
 // and, for a reference that is not stationary, m0 = -i (S^-1 C0 - C0^dag S^-1).
 void prepare_reference(vgtb_ctx *c, bool with_m0) {
-  // full density of the current level (dlev[cur] is the deviation)
-  vgtb::launch_add(c->d0, c->dlev[c->cur], c->dfull, (size_t)c->n * c->n * c->nk, c->stream);
   const vgtb::StepField f0{0.0, 0.0, 0.0};
   vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, c->stream);
   vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
-                    c->spmm_cpt, c->stream);
+                    c->spmm_variant, c->stream);
   c->m0_active = with_m0;
   if (!with_m0) return;
   vgtb::launch_zgemm_f64(c->sinv, c->c0, c->y, c->n, c->nk, c->stream);
@@ -489,8 +497,8 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.img_d = dp.g.img_d;
   c->g.img_h0 = dp.g.img_h0;
   c->g.img_s = dp.g.img_s;
-  c->g.group_size = spmm_group_size();
-  c->spmm_cpt = spmm_cols_per_thread();
+  c->g.group_size = spmm_group_size(c->g.norb);
+  c->spmm_variant = spmm_variant();
   c->g.n_groups = z.ng;
   c->g.n_entries = z.ne;
   c->g.grp_ptr = dp.g.grp_ptr;
@@ -529,7 +537,6 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->tfac = dp.tfac;
   c->trace0 = dp.trace0;
   c->m0 = dp.m0;
-  c->dfull = dp.dfull;
 
   hipStream_t st_ = c->stream;
 #define CREATE_HIP(expr)                                                              \
@@ -643,13 +650,14 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
     width = std::max(width, e[n - 1] - e[0]);
   }
   HIP_TRY(c, hipMemcpyAsync(c->occ, occ.data(), sizeof(double) * occ.size(), hipMemcpyHostToDevice, s));
-  double2 *dtarget = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
+  double2 *dtarget = c->dlev[0];
   vgtb::launch_density_from_vectors(c->y, c->occ, dtarget, n, nk, s);
   HIP_TRY(c, hipGetLastError());
   c->cur = 0;
   if (c->precision != VGTB_FP64) {
-    vgtb::launch_fill_zero(c->dlev[0], n2, s);
-    vgtb::launch_trace_target(c->g, c->dlev[0], c->d0, n, nk, c->spk, c->tpart, c->trace0, s);
+    // The ground state is also the reference D0 of the reduced-precision product.
+    HIP_TRY(c, hipMemcpyAsync(c->d0, c->dlev[0], sizeof(double2) * n2, hipMemcpyDeviceToDevice, s));
+    vgtb::launch_trace_target(c->g, c->dlev[0], n, nk, c->spk, c->tpart, c->trace0, s);
     prepare_reference(c, false);   // the ground state commutes with S^-1 H0: no m0 term
   }
   c->have_density = true;
@@ -658,7 +666,7 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
   if (c->z_from_ground_state) {
     // Reference charges = Mulliken charges of the ground state (dq = 0 at t = 0).
     vgtb::StepField f0{0.0, 0.0, 0.0};
-    vgtb::launch_observe(c->g, dtarget, nullptr, n, c->kpts_dev, nk, f0, c->spk, c->part, s);
+    vgtb::launch_observe(c->g, dtarget, n, c->kpts_dev, nk, f0, c->spk, c->part, s);
     vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, 0.0, nullptr, c->z, c->v, c->qbuf,
                         c->rowpart, c->hist, c->flag, s);
     HIP_TRY(c, hipGetLastError());
@@ -678,14 +686,11 @@ vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
   if (st != VGTB_OK) return st;
   if (!d) return fail(c, VGTB_E_INVAL, "null density");
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
-  double2 *target = (c->precision != VGTB_FP64) ? c->d0 : c->dlev[0];
-  HIP_TRY(c, hipMemcpyAsync(target, d, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->dlev[0], d, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
   c->cur = 0;
   if (c->precision != VGTB_FP64) {
-    const size_t n2 = (size_t)c->n * c->n * c->nk;
-    vgtb::launch_fill_zero(c->dlev[0], n2, c->stream);
-    vgtb::launch_trace_target(c->g, c->dlev[0], c->d0, c->n, c->nk, c->spk, c->tpart, c->trace0,
-                              c->stream);
+    HIP_TRY(c, hipMemcpyAsync(c->d0, c->dlev[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+    vgtb::launch_trace_target(c->g, c->dlev[0], c->n, c->nk, c->spk, c->tpart, c->trace0, c->stream);
     // A density given by the caller need not be stationary: keep the constant
     // part of dD/dt, m0 = -i (S^-1 H0 D0 - D0 H0 S^-1), in FP64.
     prepare_reference(c, true);
@@ -728,10 +733,9 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     const vgtb::StepField f{a[0] / vgtb::kLightSpeed, a[1] / vgtb::kLightSpeed, a[2] / vgtb::kLightSpeed};
     double2 *dcur = c->dlev[c->cur];
     double2 *doth = c->dlev[c->cur ^ 1];
-    const double2 *dfull = dev ? c->dfull : dcur;   // full density of level n
     double *hrow = c->hist + (size_t)(c->step % c->hist_cap) * (5 + c->na);
     timed(c, VGTB_K_OBSERVE, [&] {
-      vgtb::launch_observe(c->g, dfull, nullptr, n, c->kpts_dev, nk, f, c->spk, c->part, s);
+      vgtb::launch_observe(c->g, dcur, n, c->kpts_dev, nk, f, c->spk, c->part, s);
     });
     timed(c, VGTB_K_REDUCE, [&] {
       vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
@@ -743,7 +747,7 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     if (!dev) {
       timed(c, VGTB_K_SPMM, [&] {
         vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr,
-                          c->spmm_cpt, s);
+                          c->spmm_variant, s);
       });
       timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
       timed(c, VGTB_K_UPDATE, [&] {
@@ -753,13 +757,13 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
           vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
       });
     } else {
-      // Deviation form: W = H dD + dH D0 = H (D0 + dD) - H0 D0 in FP64, rounded to
-      // the product's format;
-      // S^-1 W = W + (S^-1 - I) W with only the second term in reduced precision.
+      // Deviation form: W = H D - H0 D0 in FP64 (C0 = H0 D0 kept from the
+      // reference), rounded to the product's format; S^-1 W = W + (S^-1 - I) W
+      // with only the second term in reduced precision.  The state D stays FP64.
       const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
       timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dfull, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32,
-                          c->spmm_cpt, s);
+        vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32,
+                          c->spmm_variant, s);
       });
       timed(c, VGTB_K_GEMM, [&] {
         if (fmt == 1)
@@ -773,10 +777,9 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       const double2 *m0 = c->m0_active ? c->m0 : nullptr;
       timed(c, VGTB_K_UPDATE, [&] {
         if (c->have_prev)
-          vgtb::launch_update_split(c->y_lo, wid, m0, doth, doth, n, nk, 2.0 * c->dt, c->d0,
-                                    c->dfull, s);
+          vgtb::launch_update_split(c->y_lo, wid, m0, doth, doth, n, nk, 2.0 * c->dt, s);
         else
-          vgtb::launch_update_split(c->y_lo, wid, m0, dcur, doth, n, nk, c->dt, c->d0, c->dfull, s);
+          vgtb::launch_update_split(c->y_lo, wid, m0, dcur, doth, n, nk, c->dt, s);
       });
     }
     c->cur ^= 1;
@@ -784,8 +787,8 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     c->step += 1;
     if (dev && c->rescale_every > 0 && c->step % c->rescale_every == 0) {
       timed(c, VGTB_K_RESCALE, [&] {
-        vgtb::launch_rescale(c->g, c->dlev[c->cur], c->dlev[c->cur ^ 1], c->d0, n, nk, c->spk,
-                             c->tpart, c->trace0, c->tfac, c->dfull, s);
+        vgtb::launch_rescale(c->g, c->dlev[c->cur], c->dlev[c->cur ^ 1], n, nk, c->spk, c->tpart,
+                             c->trace0, c->tfac, s);
       });
     }
   }
@@ -831,12 +834,6 @@ vgtb_status vgtb_get_density(vgtb_ctx *c, int32_t level, void *out, int on_devic
   if (!out) return fail(c, VGTB_E_INVAL, "null output");
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   const double2 *src = c->dlev[level == 0 ? c->cur : (c->cur ^ 1)];
-  if (c->precision != VGTB_FP64) {
-    // D = D0 + dD, formed in the FP64 scratch product buffer.
-    vgtb::launch_add(c->d0, src, c->y, (size_t)c->n * c->n * c->nk, c->stream);
-    HIP_TRY(c, hipGetLastError());
-    src = c->y;
-  }
   HIP_TRY(c, hipMemcpyAsync(out, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VGTB_OK;

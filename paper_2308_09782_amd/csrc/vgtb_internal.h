@@ -73,40 +73,39 @@ void launch_pair_bloch_s(const PairGraph &g, const double *kpts, int nk, double2
                          hipStream_t s);
 void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
                           int which, double2 *dense, int n, hipStream_t s);
-void launch_observe(const PairGraph &g, const double2 *d, const double2 *d0, int n,
-                    const double *kpts, int nk, StepField f, const double2 *spk, double *part,
-                    hipStream_t s);
+void launch_observe(const PairGraph &g, const double2 *d, int n, const double *kpts, int nk,
+                    StepField f, const double2 *spk, double *part, hipStream_t s);
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
                    double *rowpart, double *hist_row, int *flag, hipStream_t s);
 // Pair blocks of H_k(t) in grouped pair order.
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
                      const double2 *spk, const double *v, double2 *hq, hipStream_t s);
-// W = H D (d0 == null) or W = H (D0 + dD) - C0; out_format: 0 complex128,
-// 1 complex64, 2 bf16 planes (k-packed, padded np) + complex64 copy w32.
+// W = H D (d0 == null) or W = H D - C0 (d0 != null marks the deviation form);
+// out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np)
+// + complex64 copy w32.  variant: -1, -2, -4 = FP64 matrix cores with that
+// many 16-column slices per wave (four orbitals per atom only); 1, 2 = vector
+// FMAs with that many columns per thread.
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, int cpt, hipStream_t s);
+                 float2 *w32, int variant, hipStream_t s);
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, hipStream_t s);
 // D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each);
 // m0 may be null.
-// Also writes dfull = ref + D_out (the full density of the new level).
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
-                         double2 *dout, int n, int nk, double fac, const double2 *ref,
-                         double2 *dfull, hipStream_t s);
+                         double2 *dout, int n, int nk, double fac, hipStream_t s);
 // D_out = D_base - i (Y - Y^dag) (used to form the constant term m0 = -i X0).
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s);
 void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,
                             hipStream_t s);
-void launch_trace_target(const PairGraph &g, const double2 *dd, const double2 *d0, int n, int nk,
-                         const double2 *spk, double *tpart, double *target, hipStream_t s);
-// da is the current level; dfull (its full density D0 + dD) is refreshed.
-void launch_rescale(const PairGraph &g, double2 *da, double2 *db, const double2 *d0, int n, int nk,
-                    const double2 *spk, double *tpart, const double *target, double *fac,
-                    double2 *dfull, hipStream_t s);
-void launch_add(const double2 *a, const double2 *b, double2 *out, size_t count, hipStream_t s);
+// target[k] = Tr(D_k S_k) of the density dd.
+void launch_trace_target(const PairGraph &g, const double2 *dd, int n, int nk, const double2 *spk,
+                         double *tpart, double *target, hipStream_t s);
+// Both levels: D <- (target / Tr(D S)) 1/2 (D + D^dag), per k.
+void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk, const double2 *spk,
+                    double *tpart, const double *target, double *fac, hipStream_t s);
 // sigma and epsilon interleaved in out (2 * nw complex); j and omega on the device.
 void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
                      double tau0, bool subtract_mean, double *scratch_mean, double2 *out,
@@ -130,7 +129,7 @@ struct vgtb_ctx {
   int na = 0, no = 0, n = 0, nk = 0;
   double volume = 0.0, n_electrons = 0.0, dt = 0.0;
   int precision = 0, rescale_every = 0, hist_cap = 1;
-  int spmm_cpt = 1;            // columns per thread of the sparse product
+  int spmm_variant = -1;       // sparse-product kernel (see launch_spmm)
   bool scc = false, z_from_ground_state = false;
 
   hipStream_t stream = nullptr;
@@ -174,7 +173,6 @@ struct vgtb_ctx {
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk
   double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density
-  double2 *dfull = nullptr;    // nk * n * n, D0 + dD of the current level
   bool m0_active = false;
 
   // per-kernel event timing (vgtb_profile_*)
