@@ -5,8 +5,8 @@ Workload: the 512-atom amorphous-Si supercell (2048 sp3 orbitals) on the
 Gamma-centred 2x2x2 mesh (8 k-points), SCC shift on, 20 fs sin^2 pulse
 (omega = 0.1 Ha, peak A = 0.05 au), dt = 0.2 au.  One step = one pass of the
 whole hot path over all k-points: observables + Mulliken + SCC shift,
-fused Peierls assembly and block-sparse H D, dense S^-1 (H D) on the matrix
-cores, and the leapfrog update.  Inputs are seeded synthetic stand-ins of
+Peierls assembly of the pair blocks, block-sparse H D and dense S^-1 (H D)
+on the matrix cores, and the leapfrog update.  Inputs are seeded synthetic stand-ins of
 the paper's a-Si structure (no dataset is read).
 
 Prints one JSON line: k-steps/s of the 3xBF16 deviation form over the timed
@@ -84,17 +84,17 @@ def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps):
 KERNEL_SOURCES = {"fp64": "gemm_mfma.hip", "fp32": "gemm_mfma.hip", "bf16x3": "gemm_bf16x3.hip"}
 
 
-def counter_traffic(precision):
+def counter_traffic(precision, workload):
     """HBM bytes per launch of the dense product from the committed rocprofv3
-    counter runs (profiles/traffic.json), or None when the kernel's source has
-    changed since those counters were taken."""
+    counter runs (profiles/traffic.json), or None when they were taken on
+    another workload or the kernel's source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_2308_09782_amd", "csrc", KERNEL_SOURCES[precision])
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(precision)
-    if not rec:
+    if not rec or rec.get("workload") != workload:
         return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("source_sha256") != digest:
@@ -102,7 +102,7 @@ def counter_traffic(precision):
     return rec.get("bytes_per_launch")
 
 
-def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset):
+def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload):
     """Ground state, warmup, then `steps` timed steps of one precision form."""
     total = warmup + steps
     prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total, 1))
@@ -136,7 +136,7 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset):
     peak = PEAK_TFLOPS[precision]
     roof = {"bound": "mfma", "kernel": f"dense S^-1 W product ({precision}, all {nk} k-points)",
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": counter_traffic(precision), "flops_per_launch": flops_per_launch,
+            "traffic": counter_traffic(precision, workload), "flops_per_launch": flops_per_launch,
             "avg_launch_ms": gemm_avg_s * 1e3}
     if precision == "bf16x3":
         # three bf16 products per real product: the matrix cores execute 3x the flops
@@ -187,10 +187,12 @@ def main():
     total = args.warmup + args.steps
     # Warmup and timed steps sit in the middle of the pulse, where A is large.
     offset = min(2000, max(0, atab.shape[0] - total))
-    head = run_form(vg, torch, sysm, atab, dt, args.precision, args.warmup, args.steps, offset)
+    head = run_form(vg, torch, sysm, atab, dt, args.precision, args.warmup, args.steps, offset,
+                    args.workload)
     ref = None
     if args.precision != "fp64" and not args.no_fp64_compare:
-        ref = run_form(vg, torch, sysm, atab, dt, "fp64", args.warmup, args.steps, offset)
+        ref = run_form(vg, torch, sysm, atab, dt, "fp64", args.warmup, args.steps, offset,
+                       args.workload)
 
     n, nk = sysm.n_orb, sysm.n_k
     out = {
