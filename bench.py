@@ -105,7 +105,7 @@ def counter_traffic(precision, workload):
 def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload):
     """Ground state, warmup, then `steps` timed steps of one precision form."""
     total = warmup + steps
-    prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total, 1))
+    prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total + min(steps, 20), 1))
     t_init = time.perf_counter()
     gap = prop.ground_state()
     t_init = time.perf_counter() - t_init
@@ -113,34 +113,51 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
     prop.step(warmup)
     prop.synchronize()
     prop.profile(True)
-    events = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        events[i].record()
-        prop.step(1)
-    events[-1].record()
+    prop.step(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prop.synchronize()
     prof = prop.profile_read()
-    step_ms = np.array([events[i].elapsed_time(events[i + 1]) for i in range(steps)])
     obs = prop.read_observables(0, total)
+    # Latency of single-step calls, after the timed region.
+    prop.profile(False)
+    n_lat = min(steps, 20)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat + 1)]
+    events[0].record()
+    for i in range(n_lat):
+        prop.step(1)
+        events[i + 1].record()
+    torch.cuda.synchronize()
+    step_ms = np.array([events[i].elapsed_time(events[i + 1]) for i in range(n_lat)])
     prop.close()
 
     n, nk = sysm.n_orb, sysm.n_k
     gemm_ms, gemm_n = prof["gemm"]
-    gemm_avg_s = gemm_ms / max(gemm_n, 1) / 1e3
-    flops_per_launch = 8.0 * n ** 3 * nk
-    achieved = flops_per_launch / gemm_avg_s / 1e12
-    peak = PEAK_TFLOPS[precision]
-    roof = {"bound": "mfma", "kernel": f"dense S^-1 W product ({precision}, all {nk} k-points)",
-            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": counter_traffic(precision, workload), "flops_per_launch": flops_per_launch,
-            "avg_launch_ms": gemm_avg_s * 1e3}
-    if precision == "bf16x3":
-        # three bf16 products per real product: the matrix cores execute 3x the flops
-        roof["mfma_issued_frac"] = 3.0 * achieved / peak
+    if gemm_n:
+        gemm_avg_s = gemm_ms / gemm_n / 1e3
+        flops_per_launch = 8.0 * n ** 3 * nk
+        achieved = flops_per_launch / gemm_avg_s / 1e12
+        peak = PEAK_TFLOPS[precision]
+        roof = {"bound": "mfma", "kernel": f"dense S^-1 W product ({precision}, all {nk} k-points)",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": counter_traffic(precision, workload), "flops_per_launch": flops_per_launch,
+                "avg_launch_ms": gemm_avg_s * 1e3}
+        if precision == "bf16x3":
+            # three bf16 products per real product: the matrix cores execute 3x the flops
+            roof["mfma_issued_frac"] = 3.0 * achieved / peak
+    else:
+        # Small systems: whole blocks of steps per launch, FP64 vector arithmetic in LDS.
+        sm_ms, sm_n = prof["small"]
+        avg_s = sm_ms / max(sm_n, 1) / 1e3
+        nnz = len(set(zip(sysm.blk_i.tolist(), sysm.blk_j.tolist()))) * (n // sysm.n_atoms) ** 2
+        flops_per_launch = (8.0 * n ** 3 + 8.0 * nnz * n) * nk * steps / max(sm_n, 1)
+        achieved = flops_per_launch / avg_s / 1e12
+        roof = {"bound": "alu", "kernel": f"whole steps in one launch (FP64, all {nk} k-points)",
+                "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_s * 1e3}
     kernels = {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1],
                    "share": (v[0] / max(sum(x[0] for x in prof.values()), 1e-30))}
                for k, v in prof.items() if v[1]}

@@ -201,7 +201,10 @@ typedef enum {
   VGTB_K_UPDATE = 4,    /* leapfrog D_{n+1} = D_{n-1} - 2 i dt (Y - Y^dag)     */
   VGTB_K_RESCALE = 5,   /* deviation forms: re-Hermitise + trace rescale       */
   VGTB_K_ASSEMBLE = 6,  /* Peierls assembly of the pair blocks of H_k(t)       */
-  VGTB_K_COUNT = 7
+  VGTB_K_SMALL = 7,     /* small N, FP64, no SCC: up to 64 whole steps in one
+                           launch (the other classes then stay at zero except
+                           REDUCE, which is the per-block history reduction)  */
+  VGTB_K_COUNT = 8
 } vgtb_kernel;
 
 /*

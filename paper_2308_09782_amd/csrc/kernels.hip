@@ -583,6 +583,216 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
   }
 }
 
+// ---- Small systems: a block of steps in one launch ---------------------------
+// Without the SCC shift the k-points do not interact within a step, so for
+// N <= kSmallN one workgroup per k keeps S_k^-1, both leapfrog levels, H_k(t)
+// and W in LDS (5 N^2 complex128, 125 KB at N = 40), with the Peierls phase of
+// each periodic image computed once per step (at most kSmallImages), and takes up to
+// kSmallChunk steps per launch: per step the observables of D_n (the same
+// lane mapping and arithmetic as k_observe, written per step to `part`), the
+// Peierls assembly of H_k(t_n) (Eqs. 8-9) as a dense matrix, W = H D and
+// Y = S^-1 W in LDS, and the leapfrog D_{n+1} = D_{n-1} - 2i dt (Y - Y^dag)
+// (Eqs. 6, 13; forward Euler when there is no previous level).
+
+// C = A B for complex n x n matrices in LDS on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: A operand of lane l = A[l % 16][l / 16], B operand =
+// B[l / 16][l % 16], result element j at row l / 16 + 4 j, column l % 16).
+// A is given transposed (At[k n + r] = A[r][k]) so that both operand reads are
+// sixteen consecutive elements; one wavefront per 16 x 16 output tile, edges
+// zero-filled.  Complex MAC: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+__device__ inline void lds_zgemm(const double2 *At, const double2 *B, double2 *C, int n) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int nt = (n + 15) >> 4;
+  const double2 z = make_double2(0.0, 0.0);
+  for (int tile = threadIdx.x >> 6; tile < nt * nt; tile += blockDim.x >> 6) {
+    const int r0 = (tile / nt) * 16, c0 = (tile % nt) * 16;
+    const int r = r0 + lr, c = c0 + lr;
+    v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const int kk = k0 + lk;
+      const double2 a = (r < n && kk < n) ? At[kk * n + r] : z;
+      const double2 b = (c < n && kk < n) ? B[kk * n + c] : z;
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = r0 + lk + 4 * j;
+      if (row < n && c < n) C[row * n + c] = make_double2(cr[j], ci[j]);
+    }
+  }
+}
+
+template <int NO>
+__global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *__restrict__ kpts,
+                                                     const double2 *__restrict__ spk,
+                                                     const double2 *__restrict__ sinv,
+                                                     double2 *dlev0, double2 *dlev1, int cur,
+                                                     int have_prev, int n, FieldChunk f,
+                                                     int nsteps, double dt,
+                                                     double *__restrict__ part) {
+  constexpr int E2 = NO * NO;
+  constexpr int P = 64 / E2;
+  __shared__ double2 lds[5 * kSmallN * kSmallN];
+  __shared__ double2 ph[kSmallImages];        // (cos, sin) of (k + A/c).d per image
+  const int k = blockIdx.x, nk = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int n2 = n * n;
+  // St = (S_k^-1)^T; Hm holds H_k(t)^T, then Y = S^-1 W (row-major).
+  double2 *St = lds, *Dc = lds + n2, *Dp = lds + 2 * n2, *Hm = lds + 3 * n2, *Wm = lds + 4 * n2;
+  const size_t base = (size_t)k * n2;
+  {
+    const double2 *dc = cur ? dlev1 : dlev0, *dp = cur ? dlev0 : dlev1;
+    for (int t = tid; t < n2; t += blockDim.x) {
+      St[t] = sinv[base + (size_t)(t % n) * n + t / n];
+      Dc[t] = dc[base + t];
+      Dp[t] = have_prev ? dp[base + t] : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  const int e = lane % E2, slot = lane / E2, mu = e / NO, nu = e % NO;
+  bool hp = have_prev != 0;
+  for (int s = 0; s < nsteps; ++s) {
+    const double kx = kpts[3 * k] + f.a[3 * s], ky = kpts[3 * k + 1] + f.a[3 * s + 1],
+                 kz = kpts[3 * k + 2] + f.a[3 * s + 2];
+    // Peierls phases of step n, once per image.
+    for (int m = tid; m < g.n_images; m += blockDim.x) {
+      double sn, cs;
+      sincos(kx * g.img_d[3 * m] + ky * g.img_d[3 * m + 1] + kz * g.img_d[3 * m + 2], &sn, &cs);
+      ph[m] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    // Observables of D_n: Mulliken row sums, band energy and current.
+    for (int I = wave; I < g.n_atoms; I += nwaves) {
+      double q = 0.0, en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+      for (int p = g.row_ptr[I] + slot; p < g.row_ptr[I + 1]; p += P) {
+        const int J = g.pair_col[p];
+        const double2 dv = Dc[(I * NO + mu) * n + (J * NO + nu)];
+        const double2 sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+        q += dv.x * sv.x + dv.y * sv.y;
+        for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+          const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
+          const double cs = ph[m].x, sn = ph[m].y;
+          const double h = g.img_h0[(size_t)m * E2 + e];
+          const double re = (dv.x * cs + dv.y * sn) * h;
+          const double im = (dv.x * sn - dv.y * cs) * h;
+          en += re;
+          jx -= dx * im;
+          jy -= dy * im;
+          jz -= dz * im;
+        }
+      }
+      q = wave_sum(q);
+      en = wave_sum(en);
+      jx = wave_sum(jx);
+      jy = wave_sum(jy);
+      jz = wave_sum(jz);
+      if (lane == 0) {
+        double *o = part + (((size_t)s * nk + k) * g.n_atoms + I) * 5;
+        o[0] = q;
+        o[1] = en;
+        o[2] = jx;
+        o[3] = jy;
+        o[4] = jz;
+      }
+    }
+    // H_k(t_n), dense and transposed.
+    for (int t = tid; t < n2; t += blockDim.x) Hm[t] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int t = tid; t < g.n_pairs * E2; t += blockDim.x) {
+      const int p = t / E2, ee = t % E2;
+      double2 h = make_double2(0.0, 0.0);
+      for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+        const double hv = g.img_h0[(size_t)m * E2 + ee];
+        h.x += ph[m].x * hv;
+        h.y += ph[m].y * hv;
+      }
+      Hm[(g.pair_col[p] * NO + ee % NO) * n + g.pair_row[p] * NO + ee / NO] = h;
+    }
+    __syncthreads();
+    lds_zgemm(Hm, Dc, Wm, n);     // W = H D_n
+    __syncthreads();
+    lds_zgemm(St, Wm, Hm, n);     // Y = S^-1 W (H no longer needed)
+    __syncthreads();
+    const double fac = hp ? 2.0 * dt : dt;
+    const double2 *Db = hp ? Dp : Dc;
+    for (int t = tid; t < n2; t += blockDim.x) {
+      const int i = t / n, j = t - i * n;
+      const double2 y = Hm[t], yt = Hm[j * n + i];
+      const double xr = y.x - yt.x;           // X = Y - conj(Y^T)
+      const double xi = y.y + yt.y;
+      const double2 b = Db[t];
+      Dp[t] = make_double2(b.x + fac * xi, b.y - fac * xr);
+    }
+    __syncthreads();
+    double2 *tmp = Dc;
+    Dc = Dp;
+    Dp = tmp;
+    hp = true;
+  }
+  double2 *dc = ((cur ^ (nsteps & 1)) != 0) ? dlev1 : dlev0;
+  double2 *dp = ((cur ^ (nsteps & 1)) != 0) ? dlev0 : dlev1;
+  for (int t = tid; t < n2; t += blockDim.x) {
+    dc[base + t] = Dc[t];
+    if (hp) dp[base + t] = Dp[t];
+  }
+}
+
+// History rows of a block of steps from the per-(step, k, atom) partials of
+// k_small_steps (no SCC term): for each step the same sums, in the same order,
+// as k_reduce_atoms followed by k_reduce_final.
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_steps(const double *__restrict__ part,
+                                                                 int nk, int na,
+                                                                 const double *__restrict__ kw,
+                                                                 double jscale, double *hist,
+                                                                 int64_t step0, int cap,
+                                                                 int *flag) {
+  __shared__ double red[6][kReduceWaves];
+  const int s = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double *row = hist + (size_t)((step0 + s) % cap) * (5 + na);
+  const double *ps = part + (size_t)s * nk * na * 5;
+  double c[6] = {0, 0, 0, 0, 0, 0};
+  for (int I = t; I < na; I += kReduceThreads) {
+    double q = 0.0, en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      const double *o = ps + ((size_t)k * na + I) * 5;
+      q += kw[k] * o[0];
+      en += kw[k] * o[1];
+      jx += o[2];
+      jy += o[3];
+      jz += o[4];
+    }
+    row[5 + I] = q;
+    c[0] += en;
+    c[1] += jx;
+    c[2] += jy;
+    c[3] += jz;
+    c[4] += 0.0;
+    c[5] += q;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    c[i] = wave_sum(c[i]);
+    if (lane == 0) red[i][wave] = c[i];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double o[6] = {0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < kReduceWaves; ++w)
+      for (int i = 0; i < 6; ++i) o[i] += red[i][w];
+    row[0] = o[1] * jscale;
+    row[1] = o[2] * jscale;
+    row[2] = o[3] * jscale;
+    row[3] = o[0] + o[4];
+    row[4] = o[5];
+    if (!isfinite(o[5]) || !isfinite(o[0])) *flag = 1;
+  }
+}
+
 // Leapfrog (Eq. 13) in the form D_out = D_base - i fac (Y - Y^dag), Y = S^-1 H D,
 // so that dD/dt = -i (Y - Y^dag) is anti-Hermitian bit for bit.  32x32 tiles;
 // the transposed partner tile of Y is staged through LDS.
@@ -1025,6 +1235,25 @@ void launch_spectrum(const double *j, int nt, double dt, const double *omega, in
     (void)hipStreamSynchronize(s);
   }
   hipLaunchKernelGGL(k_spectrum, dim3(nw), dim3(64), 0, s, j, nt, dt, jmean, omega, e0, tau0, out);
+}
+
+void launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                        const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
+                        bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
+                        double *part, hipStream_t s) {
+  if (g.norb == 4)
+    hipLaunchKernelGGL(k_small_steps<4>, dim3(nk), dim3(256), 0, s, g, kpts, spk, sinv, dlev0, dlev1,
+                       cur, have_prev ? 1 : 0, n, f, nsteps, dt, part);
+  else
+    hipLaunchKernelGGL(k_small_steps<1>, dim3(nk), dim3(256), 0, s, g, kpts, spk, sinv, dlev0, dlev1,
+                       cur, have_prev ? 1 : 0, n, f, nsteps, dt, part);
+}
+
+void launch_reduce_steps(const double *part, int nk, int na, const double *kw, double jscale,
+                         double *hist, int64_t step0, int cap, int nsteps, int *flag,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_steps, dim3(nsteps), dim3(kReduceThreads), 0, s, part, nk, na, kw,
+                     jscale, hist, step0, cap, flag);
 }
 
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s) {

@@ -71,6 +71,13 @@ int spmm_variant() {
   const int cb = b ? std::atoi(b) : 1;
   return -(cb == 2 || cb == 4 ? cb : 1);
 }
+// VGTB_SMALL_STEPS=0 turns off the one-launch-per-block-of-steps path of
+// small systems (kSmallN), which is otherwise taken in the FP64 form without
+// the SCC shift.
+bool small_path_enabled() {
+  const char *e = std::getenv("VGTB_SMALL_STEPS");
+  return !(e && std::atoi(e) == 0);
+}
 int spmm_group_size(int orbs_per_atom) {
   const bool mfma = orbs_per_atom == 4 && spmm_variant() < 0;
   const char *e = std::getenv("VGTB_SPMM_GROUP");
@@ -254,7 +261,7 @@ struct Carver {
 
 struct Sizes {
   int na, no, n, nk, np, ni, cap, precision, npad, ng, ne;
-  bool scc, deviation;
+  bool scc, deviation, small;
 };
 
 template <typename Ctx>
@@ -314,6 +321,7 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->y_lo = c->w32 = nullptr;
     c->tpart = c->tfac = c->trace0 = nullptr;
   }
+  c->sm_part = z.small ? cv.template take<double>((size_t)vgtb::kSmallChunk * z.nk * z.na * 5) : nullptr;
 }
 
 // Mutable stand-in used for the size query (PairGraph members are const).
@@ -330,6 +338,7 @@ struct SizeProbe {
   float2 *y_lo, *w32;
   double *tpart, *tfac, *trace0;
   double2 *m0;
+  double *sm_part;
 };
 
 struct DevPtrs : SizeProbe {};
@@ -349,6 +358,8 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.deviation = o->precision != VGTB_FP64;
   z.precision = o->precision;
   z.npad = (z.n + 63) / 64 * 64;
+  z.small = small_path_enabled() && !z.deviation && !z.scc && z.n <= vgtb::kSmallN &&
+            z.ni <= vgtb::kSmallImages;
   return z;
 }
 
@@ -537,6 +548,8 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->tfac = dp.tfac;
   c->trace0 = dp.trace0;
   c->m0 = dp.m0;
+  c->sm_part = dp.sm_part;
+  c->small_path = z.small;
 
   hipStream_t st_ = c->stream;
 #define CREATE_HIP(expr)                                                              \
@@ -727,6 +740,30 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
   const int64_t nf = (int64_t)(c->field.size() / 3);
   const double jscale = -1.0 / (c->volume * nk);
   hipStream_t s = c->stream;
+  if (c->small_path) {
+    for (int64_t done = 0; done < n_steps;) {
+      const int ns = (int)std::min<int64_t>(vgtb::kSmallChunk, n_steps - done);
+      vgtb::FieldChunk fc;
+      for (int i = 0; i < ns; ++i) {
+        const double *a = c->field.data() + 3 * std::min<int64_t>(c->step + i, nf - 1);
+        for (int x = 0; x < 3; ++x) fc.a[3 * i + x] = a[x] / vgtb::kLightSpeed;
+      }
+      timed(c, VGTB_K_SMALL, [&] {
+        vgtb::launch_small_steps(c->g, c->kpts_dev, nk, c->spk, c->sinv, c->dlev[0], c->dlev[1],
+                                 c->cur, c->have_prev, n, fc, ns, c->dt, c->sm_part, s);
+      });
+      timed(c, VGTB_K_REDUCE, [&] {
+        vgtb::launch_reduce_steps(c->sm_part, nk, c->na, c->kw_dev, jscale, c->hist, c->step,
+                                  c->hist_cap, ns, c->flag, s);
+      });
+      c->cur ^= (ns & 1);
+      c->have_prev = true;
+      c->step += ns;
+      done += ns;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return VGTB_OK;
+  }
   for (int64_t it = 0; it < n_steps; ++it) {
     const int64_t idx = std::min<int64_t>(c->step, nf - 1);
     const double *a = c->field.data() + 3 * idx;

@@ -67,6 +67,16 @@ struct StepField {
   double ax, ay, az;   // A(t_n) / c
 };
 
+// Small systems without the SCC shift: a block of up to kSmallChunk steps per
+// launch, one workgroup per k with everything in LDS (N <= kSmallN, at most
+// kSmallImages periodic images).
+constexpr int kSmallN = 40;
+constexpr int kSmallImages = 1536;
+constexpr int kSmallChunk = 64;
+struct FieldChunk {
+  double a[3 * kSmallChunk];   // A(t_n) / c of the block's steps
+};
+
 // ---- launchers (kernels.hip) ------------------------------------------------
 void launch_fill_zero(double2 *p, size_t n, hipStream_t s);
 void launch_pair_bloch_s(const PairGraph &g, const double *kpts, int nk, double2 *spk,
@@ -110,6 +120,15 @@ void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk,
 void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
                      double tau0, bool subtract_mean, double *scratch_mean, double2 *out,
                      hipStream_t s);
+// Steps [step, step + nsteps) of a small system (see kSmallN); per-step
+// partials [nsteps][nk][na][5] into part, then launch_reduce_steps.
+void launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                        const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
+                        bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
+                        double *part, hipStream_t s);
+void launch_reduce_steps(const double *part, int nk, int na, const double *kw, double jscale,
+                         double *hist, int64_t step0, int cap, int nsteps, int *flag,
+                         hipStream_t s);
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s);
 void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
                                  int nk, hipStream_t s);
@@ -131,6 +150,7 @@ struct vgtb_ctx {
   int precision = 0, rescale_every = 0, hist_cap = 1;
   int spmm_variant = -1;       // sparse-product kernel (see launch_spmm)
   bool scc = false, z_from_ground_state = false;
+  bool small_path = false;     // whole blocks of steps per launch (kSmallN)
 
   hipStream_t stream = nullptr;
   rocblas_handle blas = nullptr;
@@ -172,6 +192,7 @@ struct vgtb_ctx {
   double *tpart = nullptr;     // 2 * nk * na
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk
+  double *sm_part = nullptr;   // kSmallChunk * nk * na * 5 per-step partials (small path)
   double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density
   bool m0_active = false;
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "vgtb_spectrum",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
-           "assemble": 6}
+           "assemble": 6, "small": 7}
 
 
 class VgtbError(RuntimeError):

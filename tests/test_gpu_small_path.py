@@ -1,0 +1,98 @@
+"""Small systems take whole blocks of steps in one launch (FP64, no SCC shift,
+N <= 40): the result must match the per-step kernels and the oracle.
+
+The calls below use step counts that cross the 64-step blocks (1, 63, 70,
+16), a history ring smaller than the run, a checkpoint taken in the middle,
+and both orbital counts (sp3 silicon and the one-orbital chain).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import vgtb_synth as vs
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2308_09782_amd")
+
+pytestmark = pytest.mark.gpu
+
+CALLS = [1, 63, 70, 16]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.load_library()
+
+
+def _run(monkeypatch, small, sysm, dt, atab, calls, cap):
+    monkeypatch.setenv("VGTB_SMALL_STEPS", "1" if small else "0")
+    with pkg.Propagator(sysm, dt, "fp64", history_capacity=cap) as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.profile(True)
+        for c in calls:
+            p.step(c)
+        prof = p.profile_read()
+        total = sum(calls)
+        hist = p.read_observables(total - cap, cap)
+        cur = p.get_density(0).cpu().numpy()
+        prev = p.get_density(1).cpu().numpy()
+    return hist, cur, prev, prof
+
+
+def _cases():
+    c = vs.CONFIGS["si8_k64"]
+    yield "si8_k64", vs.config_system("si8_k64"), c["dt"], vs.kick_table(1, c["a0"])
+    chain = vs.linear_chain(16)
+    yield "chain16", chain, 0.2, vs.kick_table(1, 0.02)
+
+
+@pytest.mark.parametrize("case", ["si8_k64", "chain16"])
+def test_small_path_matches_per_step_path(monkeypatch, case):
+    name, sysm, dt, atab = next(x for x in _cases() if x[0] == case)
+    assert sysm.n_orb <= 40 and sysm.gamma is None
+    cap = 100
+    h1, d1, p1, prof1 = _run(monkeypatch, True, sysm, dt, atab, CALLS, cap)
+    h0, d0, p0, prof0 = _run(monkeypatch, False, sysm, dt, atab, CALLS, cap)
+    assert prof1["small"][1] == sum((c + 63) // 64 for c in CALLS)   # one launch per block
+    assert prof1["gemm"][1] == 0 and prof0["small"][1] == 0
+    for a, b in ((d1, d0), (p1, p0)):
+        err = max(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) for k in range(sysm.n_k))
+        assert err < 1e-12
+    jmax = np.abs(h0["J"]).max()
+    assert jmax > 0
+    assert np.abs(h1["J"] - h0["J"]).max() < 1e-12 * jmax
+    assert np.abs(h1["E"] - h0["E"]).max() < 1e-12 * np.abs(h0["E"]).max()
+    assert np.abs(h1["trace"] - h0["trace"]).max() < 1e-12 * np.abs(h0["trace"]).max()
+    assert np.abs(h1["q"] - h0["q"]).max() < 1e-12
+
+
+def test_small_path_against_oracle_with_checkpoint(monkeypatch):
+    c = vs.CONFIGS["si8_k64"]
+    sysm = vs.config_system("si8_k64")
+    atab = vs.kick_table(1, c["a0"])
+    n1, n2 = 90, 60
+    d_init, z, _ = oracle.ground_state(sysm)
+    ref, st = oracle.propagate(sysm, d_init, atab, c["dt"], n1 + n2, z=z)
+    monkeypatch.setenv("VGTB_SMALL_STEPS", "1")
+    with pkg.Propagator(sysm, c["dt"], "fp64", history_capacity=n1 + n2) as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.step(n1)
+        blob = p.save_state()
+        p.step(n2)
+        h_a = p.read_observables(0, n1 + n2)
+        cur_a = p.get_density(0).cpu().numpy()
+        p.load_state(blob)
+        p.step(n2)
+        cur_b = p.get_density(0).cpu().numpy()
+        prev_b = p.get_density(1).cpu().numpy()
+    assert np.array_equal(cur_a, cur_b)          # resume is bit-exact
+    for got, want in ((cur_b, st.d_cur), (prev_b, st.d_prev)):
+        err = max(np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k]) for k in range(sysm.n_k))
+        assert err < 1e-10
+    jmax = np.abs(ref["J"]).max()
+    assert np.abs(h_a["J"] - ref["J"]).max() <= 1e-10 * jmax
+    assert np.abs(h_a["q"] - ref["q"]).max() < 1e-10
