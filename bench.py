@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=4)
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="instead of timing: run the workload's full step count in the reduced "
+                         "forms and in FP64 and report the current and spectrum errors")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(read N, write N): the reference kernel for hardware byte counters")
@@ -175,6 +178,65 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
     }
 
 
+def accuracy_run(vg, torch, sysm, atab, dt, forms, n_steps, workload):
+    """Full-length runs of each form from the ground state: J(t) over the whole run and
+    the spectra of Eqs. 15-16 (computed on the GPU), reduced forms against FP64."""
+    c_light = 137.035999084
+    omegas = np.linspace(0.02, 0.30, 281)
+    # E(t) = -(1/c) dA/dt of the drive, transformed like the current (Eq. 15 with E0 = 1).
+    ax = atab[:n_steps, 0] if atab.shape[0] >= n_steps else np.concatenate(
+        [atab[:, 0], np.full(n_steps - atab.shape[0], atab[-1, 0])])
+    ef = -np.gradient(ax, dt) / c_light
+    runs = {}
+    for prec in forms:
+        with vg.Propagator(sysm, dt, prec, history_capacity=n_steps) as prop:
+            prop.ground_state()
+            prop.set_field_table(atab)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prop.step(n_steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            obs = prop.read_observables(0, n_steps)
+            jt, _ = prop.spectrum(obs["J"][:, 0], dt, omegas, 1.0)
+            if atab.shape[0] == 1:      # kick: E(t) = -(A0/c) delta(t)
+                et = np.full(omegas.size, -atab[0, 0] / c_light, dtype=np.complex128)
+            else:
+                et, _ = prop.spectrum(ef, dt, omegas, 1.0, subtract_mean=False)
+        runs[prec] = {"J": obs["J"][:, 0], "trace": obs["trace"], "jw": jt, "ew": et,
+                      "value": sysm.n_k * n_steps / el, "seconds": el}
+    ref = runs["fp64"]
+    band = np.abs(ref["ew"]) >= 0.1 * np.abs(ref["ew"]).max()
+    def absorption(r):
+        return 4.0 * np.pi * np.real(r["jw"][band] / r["ew"][band]) / omegas[band]
+    a_ref = absorption(ref)
+    jmax = np.abs(ref["J"]).max()
+    out = {"metric": f"accuracy of the reduced forms against FP64, full {n_steps}-step run",
+           "workload": workload, "steps": n_steps, "dt": dt,
+           "omega_band_ha": [float(omegas[band].min()), float(omegas[band].max())],
+           "fp64": {"k_steps_per_s": ref["value"], "seconds": ref["seconds"],
+                    "trace_drift": float(np.abs(ref["trace"] - sysm.n_electrons).max()),
+                    "peak_omega_ha": float(omegas[np.argmax(np.abs(ref["jw"]))]),
+                    "absorption_peak_omega_ha": float(omegas[band][np.argmax(a_ref)])}}
+    for prec in forms:
+        if prec == "fp64":
+            continue
+        r = runs[prec]
+        a = absorption(r)
+        ip = np.argmax(np.abs(ref["jw"]))
+        out[prec] = {
+            "k_steps_per_s": r["value"], "seconds": r["seconds"],
+            "j_err_max_over_run": float(np.abs(r["J"] - ref["J"]).max() / jmax),
+            "trace_drift": float(np.abs(r["trace"] - sysm.n_electrons).max()),
+            "current_spectrum_err": float(np.abs(r["jw"] - ref["jw"]).max() / np.abs(ref["jw"]).max()),
+            "peak_omega_ha": float(omegas[np.argmax(np.abs(r["jw"]))]),
+            "peak_height_rel_err": float(abs(abs(r["jw"][ip]) - abs(ref["jw"][ip])) / abs(ref["jw"][ip])),
+            "absorption_err_in_band": float(np.abs(a - a_ref).max() / np.abs(a_ref).max()),
+            "absorption_peak_omega_ha": float(omegas[band][np.argmax(a)]),
+        }
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -201,6 +263,11 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.accuracy:
+        forms = ["fp64"] + [p for p in ("bf16x3", "fp32") if p != "fp64"]
+        print(json.dumps(accuracy_run(vg, torch, sysm, atab, dt, forms, cfg["n_steps"],
+                                      args.workload)), flush=True)
+        return 0
     total = args.warmup + args.steps
     # Warmup and timed steps sit in the middle of the pulse, where A is large.
     offset = min(2000, max(0, atab.shape[0] - total))
