@@ -84,12 +84,28 @@ __global__ void k_scatter_pairs(PairGraph g, const double *kpts, const double2 *
   dense[(size_t)k * n * n + (size_t)(I * g.norb + mu) * n + (J * g.norb + nu)] = val;
 }
 
+// A(t_n)/c of the step the device counter names, from the ring of kStepRing
+// slots (slot = step mod kStepRing); a null ring means A = 0.
+__device__ inline StepField step_field(StepSource src) {
+  if (src.ring == nullptr) return StepField{0.0, 0.0, 0.0};
+  const int64_t st = src.ctr ? *src.ctr : 0;
+  const double *a = src.ring + 3 * (st % kStepRing);
+  return StepField{a[0], a[1], a[2]};
+}
+
+__global__ void k_store_ring(FieldChunk f, int64_t step0, int ns, double *ring) {
+  const int i = threadIdx.x;
+  if (i < 3 * ns) ring[3 * ((step0 + i / 3) % kStepRing) + i % 3] = f.a[i];
+}
+
+__global__ void k_set_counter(int64_t *ctr, int64_t v) { *ctr = v; }
+
 // One wavefront per (atom I, k): sweep the pair blocks of row I of D_k and
 // accumulate  q = Re sum D conj(S)  (Mulliken, row I),  E = Re sum conj(D) H0,
 // J^a = Re sum conj(D) Pi^a  with Pi^a = sum_images i d^a exp(i(k+A/c).d) H0.
 template <int NO>
 __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__restrict__ d, int n,
-                                                const double *kpts, StepField f,
+                                                const double *kpts, StepSource src,
                                                 const double2 *__restrict__ spk,
                                                 double *__restrict__ part) {
   constexpr int E2 = NO * NO;
@@ -98,6 +114,7 @@ __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__re
   const int lane = threadIdx.x;
   const int e = lane % E2, slot = lane / E2;
   const int mu = e / NO, nu = e % NO;
+  const StepField f = step_field(src);
   const double kx = kpts[3 * k] + f.ax, ky = kpts[3 * k + 1] + f.ay, kz = kpts[3 * k + 2] + f.az;
   const size_t base = (size_t)k * n * n;
   double q = 0.0, en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -148,9 +165,11 @@ __global__ __launch_bounds__(256) void k_reduce_atoms(const double *__restrict__
                                                       int na, const double *__restrict__ kw,
                                                       double *__restrict__ qbuf,
                                                       double *__restrict__ rowpart,
-                                                      double *__restrict__ hist_row) {
+                                                      double *__restrict__ hist, int cap,
+                                                      const int64_t *ctr) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= na) return;
+  double *hist_row = hist + (size_t)(ctr ? *ctr % cap : 0) * (5 + na);
   double q = 0.0, en = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   for (int k = 0; k < nk; ++k) {
     const double *o = part + ((size_t)k * na + I) * 5;
@@ -194,10 +213,11 @@ constexpr int kReduceWaves = kReduceThreads / 64;
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(int na, double jscale,
                                                                  const double *__restrict__ qbuf,
                                                                  const double *__restrict__ rowpart,
-                                                                 double *__restrict__ hist_row,
-                                                                 int *flag) {
+                                                                 double *__restrict__ hist, int cap,
+                                                                 const int64_t *ctr, int *flag) {
   __shared__ double red[6][kReduceWaves];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double *hist_row = hist + (size_t)(ctr ? *ctr % cap : 0) * (5 + na);
   double c[6] = {0, 0, 0, 0, 0, 0};
   for (int I = t; I < na; I += kReduceThreads) {
     const double *r = rowpart + (size_t)I * 5;
@@ -302,7 +322,7 @@ __device__ inline void store_rows(const double2 (&acc)[NO], int r0, int col, int
 // Peierls assembly of the pair blocks of H_k(t) in the grouped pair order q
 // of the sparse product: hq[k][q][e].
 template <int NO>
-__global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpts, StepField f,
+__global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpts, StepSource src,
                                                   const double2 *__restrict__ spk,
                                                   const double *__restrict__ v,
                                                   double2 *__restrict__ hq) {
@@ -312,6 +332,7 @@ __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpt
   if (t >= g.n_pairs * E2) return;
   const int q = t / E2, e = t % E2;
   const int p = g.gp_pair[q];
+  const StepField f = step_field(src);
   const double k0x = kpts[3 * k], k0y = kpts[3 * k + 1], k0z = kpts[3 * k + 2];
   double2 h = make_double2(0.0, 0.0);
   for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
@@ -806,7 +827,7 @@ __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
                                                 const float2 *__restrict__ wsplit,
                                                 const double2 *__restrict__ m0,
                                                 const double2 *dbase, double2 *dout, int n,
-                                                double fac) {
+                                                double fac, int64_t *ctr) {
   __shared__ double2 tt[32][33];
   const int k = blockIdx.z;
   const size_t base = (size_t)k * n * n;
@@ -851,6 +872,10 @@ __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
       dout[idx] = o;
     }
   }
+  // The step is done once this kernel has run: advance the device step index
+  // (no other thread of this kernel reads it).
+  if (ctr != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+    *ctr += 1;
 }
 
 // After a lower-triangle result (row-major): m[i][j] = conj(m[j][i]) for i < j,
@@ -1078,22 +1103,31 @@ void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const 
 }
 
 void launch_observe(const PairGraph &g, const double2 *d, int n, const double *kpts, int nk,
-                    StepField f, const double2 *spk, double *part, hipStream_t s) {
+                    StepSource src, const double2 *spk, double *part, hipStream_t s) {
   dim3 grid(g.n_atoms, nk);
-  if (g.norb == 4) hipLaunchKernelGGL(k_observe<4>, grid, dim3(64), 0, s, g, d, n, kpts, f, spk, part);
-  else hipLaunchKernelGGL(k_observe<1>, grid, dim3(64), 0, s, g, d, n, kpts, f, spk, part);
+  if (g.norb == 4) hipLaunchKernelGGL(k_observe<4>, grid, dim3(64), 0, s, g, d, n, kpts, src, spk, part);
+  else hipLaunchKernelGGL(k_observe<1>, grid, dim3(64), 0, s, g, d, n, kpts, src, spk, part);
+}
+
+void launch_store_ring(const FieldChunk &f, int64_t step0, int ns, double *ring, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_ring, dim3(1), dim3(3 * kSmallChunk), 0, s, f, step0, ns, ring);
+}
+
+void launch_set_counter(int64_t *ctr, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, ctr, v);
 }
 
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
-                   double *rowpart, double *hist_row, int *flag, hipStream_t s) {
+                   double *rowpart, double *hist, int cap, const int64_t *ctr, int *flag,
+                   hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_atoms, dim3(blocks_for(na, 256)), dim3(256), 0, s, part, nk, na, kw,
-                     qbuf, rowpart, hist_row);
+                     qbuf, rowpart, hist, cap, ctr);
   if (gamma != nullptr)
     hipLaunchKernelGGL(k_reduce_scc, dim3(blocks_for(na, 16)), dim3(1024), 0, s, na, gamma, z, qbuf,
                        v, rowpart);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, s, na, jscale, qbuf, rowpart,
-                     hist_row, flag);
+                     hist, cap, ctr, flag);
 }
 
 template <int NO, bool DELTA, int OUT>
@@ -1115,12 +1149,12 @@ static void spmm_launch(int threads, hipStream_t s, const PairGraph &g, const do
                        dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
 }
 
-void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
+void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource src,
                      const double2 *spk, const double *v, double2 *hq, hipStream_t s) {
   const size_t tot = (size_t)g.n_pairs * g.norb * g.norb;
   dim3 grid(blocks_for(tot, 256), nk);
-  if (g.norb == 4) hipLaunchKernelGGL(k_assemble<4>, grid, dim3(256), 0, s, g, kpts, f, spk, v, hq);
-  else hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, f, spk, v, hq);
+  if (g.norb == 4) hipLaunchKernelGGL(k_assemble<4>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq);
+  else hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq);
 }
 
 template <bool DELTA, int OUT, int CB>
@@ -1178,23 +1212,24 @@ void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
 }
 
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
-                   double fac, hipStream_t s) {
+                   double fac, int64_t *ctr, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
-                     (const double2 *)nullptr, dbase, dout, n, fac);
+                     (const double2 *)nullptr, dbase, dout, n, fac, ctr);
 }
 
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
-                         double2 *dout, int n, int nk, double fac, hipStream_t s) {
+                         double2 *dout, int n, int nk, double fac, int64_t *ctr, hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
-  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac);
+  hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac,
+                     ctr);
 }
 
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s) {
   dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
-                     (const double2 *)nullptr, dbase, dout, n, 1.0);
+                     (const double2 *)nullptr, dbase, dout, n, 1.0, (int64_t *)nullptr);
 }
 
 void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,

@@ -74,6 +74,11 @@ int spmm_variant() {
 // VGTB_SMALL_STEPS=0 turns off the one-launch-per-block-of-steps path of
 // small systems (kSmallN), which is otherwise taken in the FP64 form without
 // the SCC shift.
+// VGTB_GRAPH=0 turns off graph replay of the per-step launches.
+bool graphs_enabled() {
+  const char *e = std::getenv("VGTB_GRAPH");
+  return !(e && std::atoi(e) == 0);
+}
 bool small_path_enabled() {
   const char *e = std::getenv("VGTB_SMALL_STEPS");
   return !(e && std::atoi(e) == 0);
@@ -322,6 +327,8 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->tpart = c->tfac = c->trace0 = nullptr;
   }
   c->sm_part = z.small ? cv.template take<double>((size_t)vgtb::kSmallChunk * z.nk * z.na * 5) : nullptr;
+  c->ring = cv.template take<double>(3 * (size_t)vgtb::kStepRing);
+  c->ctr = cv.template take<int64_t>(1);
 }
 
 // Mutable stand-in used for the size query (PairGraph members are const).
@@ -338,7 +345,8 @@ struct SizeProbe {
   float2 *y_lo, *w32;
   double *tpart, *tfac, *trace0;
   double2 *m0;
-  double *sm_part;
+  double *sm_part, *ring;
+  int64_t *ctr;
 };
 
 struct DevPtrs : SizeProbe {};
@@ -401,11 +409,14 @@ void timed(vgtb_ctx *c, int id, F &&launch) {
   c->ev_pending.push_back({id, ev.first, ev.second});
 }
 
+void drop_graphs(vgtb_ctx *c);
+
 // Deviation forms: C0 = H0_k(A=0) D0 (constant part of the sparse product)
 // and, for a reference that is not stationary, m0 = -i (S^-1 C0 - C0^dag S^-1).
 void prepare_reference(vgtb_ctx *c, bool with_m0) {
-  const vgtb::StepField f0{0.0, 0.0, 0.0};
-  vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, f0, c->spk, nullptr, c->hq, c->stream);
+  drop_graphs(c);   // captured updates name m0 (or not)
+  const vgtb::StepSource zero{nullptr, nullptr};
+  vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, zero, c->spk, nullptr, c->hq, c->stream);
   vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
                     c->spmm_variant, c->stream);
   c->m0_active = with_m0;
@@ -413,6 +424,113 @@ void prepare_reference(vgtb_ctx *c, bool with_m0) {
   vgtb::launch_zgemm_f64(c->sinv, c->c0, c->y, c->n, c->nk, c->stream);
   vgtb::launch_fill_zero(c->w, (size_t)c->n * c->n * c->nk, c->stream);
   vgtb::launch_update_const(c->y, c->w, c->m0, c->n, c->nk, c->stream);
+}
+
+void drop_graphs(vgtb_ctx *c) {
+  for (auto &g : c->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Field ring: A(t)/c of steps [lo, lo + kStepRing) at slot step mod kStepRing.
+// Refilled (one small launch) when steps [stp, stp + need) are not all in it.
+void fill_ring(vgtb_ctx *c, int64_t stp, int need) {
+  if (c->ring_lo >= 0 && stp >= c->ring_lo && stp + need <= c->ring_lo + vgtb::kStepRing) return;
+  const int64_t nf = (int64_t)(c->field.size() / 3);
+  vgtb::FieldChunk fc;
+  for (int i = 0; i < vgtb::kStepRing; ++i) {
+    const double *a = c->field.data() + 3 * std::min<int64_t>(stp + i, nf - 1);
+    for (int x = 0; x < 3; ++x) fc.a[3 * i + x] = a[x] / vgtb::kLightSpeed;
+  }
+  vgtb::launch_store_ring(fc, stp, vgtb::kStepRing, c->ring, c->stream);
+  c->ring_lo = stp;
+}
+
+// The launches of one step at the current parity, on stream s.  With
+// may_time, each launch is bracketed by profiling events when enabled
+// (never while capturing).
+void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
+  const int n = c->n, nk = c->nk;
+  const bool dev = c->precision != VGTB_FP64;
+  const double jscale = -1.0 / (c->volume * nk);
+  const vgtb::StepSource src{c->ring, c->ctr};
+  double2 *dcur = c->dlev[c->cur];
+  double2 *doth = c->dlev[c->cur ^ 1];
+  const bool first = !c->have_prev;
+  auto run = [&](int id, auto &&launch) {
+    if (may_time) timed(c, id, launch);
+    else launch();
+  };
+  run(VGTB_K_OBSERVE, [&] { vgtb::launch_observe(c->g, dcur, n, c->kpts_dev, nk, src, c->spk, c->part, s); });
+  run(VGTB_K_REDUCE, [&] {
+    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr, c->z,
+                        c->v, c->qbuf, c->rowpart, c->hist, c->hist_cap, c->ctr, c->flag, s);
+  });
+  run(VGTB_K_ASSEMBLE, [&] {
+    vgtb::launch_assemble(c->g, c->kpts_dev, nk, src, c->spk, c->scc ? c->v : nullptr, c->hq, s);
+  });
+  if (!dev) {
+    run(VGTB_K_SPMM, [&] {
+      vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr,
+                        c->spmm_variant, s);
+    });
+    run(VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
+    run(VGTB_K_UPDATE, [&] {
+      vgtb::launch_update(c->y, first ? dcur : doth, doth, n, nk, first ? c->dt : 2.0 * c->dt,
+                          c->ctr, s);
+    });
+    return;
+  }
+  // Deviation form: W = H D - H0 D0 in FP64 (C0 = H0 D0 kept from the
+  // reference), rounded to the product's format; S^-1 W = W + (S^-1 - I) W
+  // with only the second term in reduced precision.  The state D stays FP64.
+  const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
+  run(VGTB_K_SPMM, [&] {
+    vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32,
+                      c->spmm_variant, s);
+  });
+  run(VGTB_K_GEMM, [&] {
+    if (fmt == 1)
+      vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
+                             static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s);
+    else
+      vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
+                                static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s);
+  });
+  const float2 *wid = fmt == 1 ? static_cast<const float2 *>(c->w_lo) : c->w32;
+  const double2 *m0 = c->m0_active ? c->m0 : nullptr;
+  run(VGTB_K_UPDATE, [&] {
+    vgtb::launch_update_split(c->y_lo, wid, m0, first ? dcur : doth, doth, n, nk,
+                              first ? c->dt : 2.0 * c->dt, c->ctr, s);
+  });
+}
+
+// Capture two consecutive steps starting at leapfrog parity `parity` (both with
+// a previous level) on the private capture stream and instantiate the graph.
+vgtb_status capture_pair(vgtb_ctx *c, int parity) {
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const int saved_cur = c->cur;
+  const bool saved_prev = c->have_prev;
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  c->cur = parity;
+  c->have_prev = true;
+  enqueue_step(c, c->cap_stream, false);
+  c->cur ^= 1;
+  enqueue_step(c, c->cap_stream, false);
+  c->cur = saved_cur;
+  c->have_prev = saved_prev;
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
+  if (e1 != hipSuccess) return fail(c, VGTB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e1));
+  const hipError_t e2 = hipGraphInstantiate(&c->graph[parity], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    c->graph[parity] = nullptr;
+    return fail(c, VGTB_E_DEVICE, std::string("graph instantiation: ") + hipGetErrorString(e2));
+  }
+  return VGTB_OK;
 }
 
 vgtb_status check_ready(vgtb_ctx *ctx) {
@@ -549,7 +667,10 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->trace0 = dp.trace0;
   c->m0 = dp.m0;
   c->sm_part = dp.sm_part;
+  c->ring = dp.ring;
+  c->ctr = dp.ctr;
   c->small_path = z.small;
+  c->use_graphs = graphs_enabled();
 
   hipStream_t st_ = c->stream;
 #define CREATE_HIP(expr)                                                              \
@@ -577,6 +698,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
     CREATE_HIP(hipMemcpyAsync(dp.gamma, s->gamma, sizeof(double) * z.na * z.na, hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemsetAsync(dp.v, 0, sizeof(double) * z.na, st_));
   CREATE_HIP(hipMemsetAsync(dp.flag, 0, sizeof(int), st_));
+  vgtb::launch_set_counter(dp.ctr, 0, st_);
 
   // S_k on the pair graph (Eq. 7), dense S_k, then S_k^-1 by Cholesky.
   vgtb::launch_pair_bloch_s(c->g, dp.kpts_dev, z.nk, dp.spk, st_);
@@ -678,10 +800,10 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
   c->step = 0;
   if (c->z_from_ground_state) {
     // Reference charges = Mulliken charges of the ground state (dq = 0 at t = 0).
-    vgtb::StepField f0{0.0, 0.0, 0.0};
-    vgtb::launch_observe(c->g, dtarget, n, c->kpts_dev, nk, f0, c->spk, c->part, s);
+    const vgtb::StepSource zero{nullptr, nullptr};
+    vgtb::launch_observe(c->g, dtarget, n, c->kpts_dev, nk, zero, c->spk, c->part, s);
     vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, 0.0, nullptr, c->z, c->v, c->qbuf,
-                        c->rowpart, c->hist, c->flag, s);
+                        c->rowpart, c->hist, c->hist_cap, nullptr, c->flag, s);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(c->z, c->qbuf, sizeof(double) * c->na, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->z_host.data(), c->qbuf, sizeof(double) * c->na, hipMemcpyDeviceToHost, s));
@@ -724,6 +846,7 @@ vgtb_status vgtb_set_field_table(vgtb_ctx *c, int64_t n, const double *a) {
   for (int64_t i = 0; i < 3 * n; ++i)
     if (!std::isfinite(a[i])) return fail(c, VGTB_E_INVAL, "non-finite vector potential");
   c->field.assign(a, a + 3 * n);
+  c->ring_lo = -1;   // the device ring holds the old table
   return VGTB_OK;
 }
 
@@ -764,65 +887,39 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
     HIP_TRY(c, hipGetLastError());
     return VGTB_OK;
   }
-  for (int64_t it = 0; it < n_steps; ++it) {
-    const int64_t idx = std::min<int64_t>(c->step, nf - 1);
-    const double *a = c->field.data() + 3 * idx;
-    const vgtb::StepField f{a[0] / vgtb::kLightSpeed, a[1] / vgtb::kLightSpeed, a[2] / vgtb::kLightSpeed};
-    double2 *dcur = c->dlev[c->cur];
-    double2 *doth = c->dlev[c->cur ^ 1];
-    double *hrow = c->hist + (size_t)(c->step % c->hist_cap) * (5 + c->na);
-    timed(c, VGTB_K_OBSERVE, [&] {
-      vgtb::launch_observe(c->g, dcur, n, c->kpts_dev, nk, f, c->spk, c->part, s);
-    });
-    timed(c, VGTB_K_REDUCE, [&] {
-      vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr,
-                          c->z, c->v, c->qbuf, c->rowpart, hrow, c->flag, s);
-    });
-    timed(c, VGTB_K_ASSEMBLE, [&] {
-      vgtb::launch_assemble(c->g, c->kpts_dev, nk, f, c->spk, c->scc ? c->v : nullptr, c->hq, s);
-    });
-    if (!dev) {
-      timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr,
-                          c->spmm_variant, s);
-      });
-      timed(c, VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
-      timed(c, VGTB_K_UPDATE, [&] {
-        if (c->have_prev)
-          vgtb::launch_update(c->y, doth, doth, n, nk, 2.0 * c->dt, s);
-        else
-          vgtb::launch_update(c->y, dcur, doth, n, nk, c->dt, s);
-      });
-    } else {
-      // Deviation form: W = H D - H0 D0 in FP64 (C0 = H0 D0 kept from the
-      // reference), rounded to the product's format; S^-1 W = W + (S^-1 - I) W
-      // with only the second term in reduced precision.  The state D stays FP64.
-      const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
-      timed(c, VGTB_K_SPMM, [&] {
-        vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32,
-                          c->spmm_variant, s);
-      });
-      timed(c, VGTB_K_GEMM, [&] {
-        if (fmt == 1)
-          vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
-                                 static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s);
-        else
-          vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
-                                    static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s);
-      });
-      const float2 *wid = fmt == 1 ? static_cast<const float2 *>(c->w_lo) : c->w32;
-      const double2 *m0 = c->m0_active ? c->m0 : nullptr;
-      timed(c, VGTB_K_UPDATE, [&] {
-        if (c->have_prev)
-          vgtb::launch_update_split(c->y_lo, wid, m0, doth, doth, n, nk, 2.0 * c->dt, s);
-        else
-          vgtb::launch_update_split(c->y_lo, wid, m0, dcur, doth, n, nk, c->dt, s);
-      });
+  // Per-step path.  Every step's launches are the same (the kernels read the
+  // step index and A(t)/c from the device), so pairs of steps are replayed from
+  // graphs captured once per leapfrog parity; the forward-Euler first step and
+  // the steps that end in a rescale are launched directly.
+  if (c->ctr_step != c->step) {
+    vgtb::launch_set_counter(c->ctr, c->step, s);
+    c->ctr_step = c->step;
+  }
+  const bool rescale_on = dev && c->rescale_every > 0;
+  for (int64_t it = 0; it < n_steps;) {
+    const int64_t stp = c->step;
+    fill_ring(c, stp, 2);
+    const bool pair = c->use_graphs && !c->profiling && c->have_prev && it + 2 <= n_steps &&
+                      !(rescale_on && ((stp + 1) % c->rescale_every == 0 ||
+                                       (stp + 2) % c->rescale_every == 0));
+    if (pair) {
+      if (!c->graph[c->cur]) {
+        st = capture_pair(c, c->cur);
+        if (st != VGTB_OK) return st;
+      }
+      HIP_TRY(c, hipGraphLaunch(c->graph[c->cur], s));
+      c->step += 2;
+      c->ctr_step += 2;
+      it += 2;
+      continue;
     }
+    enqueue_step(c, s, true);
     c->cur ^= 1;
     c->have_prev = true;
     c->step += 1;
-    if (dev && c->rescale_every > 0 && c->step % c->rescale_every == 0) {
+    c->ctr_step += 1;
+    it += 1;
+    if (rescale_on && c->step % c->rescale_every == 0) {
       timed(c, VGTB_K_RESCALE, [&] {
         vgtb::launch_rescale(c->g, c->dlev[c->cur], c->dlev[c->cur ^ 1], n, nk, c->spk, c->tpart,
                              c->trace0, c->tfac, s);
@@ -1032,6 +1129,8 @@ void vgtb_destroy(vgtb_ctx *c) {
     (void)hipEventDestroy(e.second);
   }
   if (c->blas) rocblas_destroy_handle(c->blas);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

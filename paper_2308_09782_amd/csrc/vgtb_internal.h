@@ -62,9 +62,20 @@ struct PairGraph {
   const double *img_s = nullptr;  // n_images * norb^2
 };
 
-// Per-step scalar inputs shared by the assembly / observable kernels.
+// A(t_n) / c.
 struct StepField {
-  double ax, ay, az;   // A(t_n) / c
+  double ax, ay, az;
+};
+
+// Where the per-step kernels find the step index and the field, so that every
+// step's launches are identical (and can be captured once in a graph):
+// ctr = device step counter (advanced by the update kernel), ring = A(t)/c of
+// kStepRing consecutive steps at slot step mod kStepRing.  A null ring means
+// A = 0, a null counter step 0.
+constexpr int kStepRing = 64;
+struct StepSource {
+  const double *ring;
+  const int64_t *ctr;
 };
 
 // Small systems without the SCC shift: a block of up to kSmallChunk steps per
@@ -84,12 +95,17 @@ void launch_pair_bloch_s(const PairGraph &g, const double *kpts, int nk, double2
 void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
                           int which, double2 *dense, int n, hipStream_t s);
 void launch_observe(const PairGraph &g, const double2 *d, int n, const double *kpts, int nk,
-                    StepField f, const double2 *spk, double *part, hipStream_t s);
+                    StepSource src, const double2 *spk, double *part, hipStream_t s);
+// ring slots of steps [step0, step0 + ns), ns <= kSmallChunk (= kStepRing).
+void launch_store_ring(const FieldChunk &f, int64_t step0, int ns, double *ring, hipStream_t s);
+void launch_set_counter(int64_t *ctr, int64_t v, hipStream_t s);
+// History row = hist + (step mod cap) (5 + na), step from ctr (row 0 if null).
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
-                   double *rowpart, double *hist_row, int *flag, hipStream_t s);
+                   double *rowpart, double *hist, int cap, const int64_t *ctr, int *flag,
+                   hipStream_t s);
 // Pair blocks of H_k(t) in grouped pair order.
-void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f,
+void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource src,
                      const double2 *spk, const double *v, double2 *hq, hipStream_t s);
 // W = H D (d0 == null) or W = H D - C0 (d0 != null marks the deviation form);
 // out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np)
@@ -99,12 +115,13 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepField f
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
                  float2 *w32, int variant, hipStream_t s);
+// ctr (may be null): advanced by one when the update has run.
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
-                   double fac, hipStream_t s);
+                   double fac, int64_t *ctr, hipStream_t s);
 // D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each);
 // m0 may be null.
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
-                         double2 *dout, int n, int nk, double fac, hipStream_t s);
+                         double2 *dout, int n, int nk, double fac, int64_t *ctr, hipStream_t s);
 // D_out = D_base - i (Y - Y^dag) (used to form the constant term m0 = -i X0).
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s);
@@ -151,6 +168,11 @@ struct vgtb_ctx {
   int spmm_variant = -1;       // sparse-product kernel (see launch_spmm)
   bool scc = false, z_from_ground_state = false;
   bool small_path = false;     // whole blocks of steps per launch (kSmallN)
+  bool use_graphs = true;      // replay captured two-step graphs (general path)
+  hipStream_t cap_stream = nullptr;            // private stream graphs are captured on
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps, by the parity of cur
+  int64_t ring_lo = -1;        // first step whose field is in the ring (-1: none)
+  int64_t ctr_step = 0;        // value the device counter has after the queued work
 
   hipStream_t stream = nullptr;
   rocblas_handle blas = nullptr;
@@ -193,6 +215,8 @@ struct vgtb_ctx {
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk
   double *sm_part = nullptr;   // kSmallChunk * nk * na * 5 per-step partials (small path)
+  double *ring = nullptr;      // kStepRing * 3, A(t)/c of the steps in flight
+  int64_t *ctr = nullptr;      // device step counter
   double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density
   bool m0_active = false;
 
