@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=4)
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel variants instead of timing them first "
+                         "(vgtb_autotune)")
     ap.add_argument("--accuracy", action="store_true",
                     help="instead of timing: run the workload's full step count in the reduced "
                          "forms and in FP64 and report the current and spectrum errors")
@@ -105,13 +108,14 @@ def counter_traffic(precision, workload):
     return rec.get("bytes_per_launch")
 
 
-def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload):
+def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload, tune=True):
     """Ground state, warmup, then `steps` timed steps of one precision form."""
     total = warmup + steps
     prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total + min(steps, 20), 1))
     t_init = time.perf_counter()
     gap = prop.ground_state()
     t_init = time.perf_counter() - t_init
+    tuning = prop.autotune(5) if tune else None
     prop.set_field_table(atab[offset:])
     prop.step(warmup)
     prop.synchronize()
@@ -172,6 +176,7 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
                             "p99": float(np.percentile(step_ms, 99)), "max": float(step_ms.max())},
         "kernels": kernels,
         "init_s": t_init,
+        "autotune": tuning,
         "min_gap_ha": gap,
         "trace_drift": float(np.abs(obs["trace"] - sysm.n_electrons).max()),
         "J": obs["J"],
@@ -272,11 +277,11 @@ def main():
     # Warmup and timed steps sit in the middle of the pulse, where A is large.
     offset = min(2000, max(0, atab.shape[0] - total))
     head = run_form(vg, torch, sysm, atab, dt, args.precision, args.warmup, args.steps, offset,
-                    args.workload)
+                    args.workload, tune=not args.no_autotune)
     ref = None
     if args.precision != "fp64" and not args.no_fp64_compare:
         ref = run_form(vg, torch, sysm, atab, dt, "fp64", args.warmup, args.steps, offset,
-                       args.workload)
+                       args.workload, tune=not args.no_autotune)
 
     n, nk = sysm.n_orb, sysm.n_k
     out = {
@@ -301,13 +306,15 @@ def main():
         "step_latency_ms": head["step_latency_ms"],
         "kernels": head["kernels"],
         "init_s": head["init_s"],
+        "autotune": head["autotune"],
         "min_gap_ha": head["min_gap_ha"],
         "trace_drift": head["trace_drift"],
         "cpu_baseline": None,
     }
     if ref is not None:
         jr, jm = ref["J"][:, 0], head["J"][:, 0]
-        out["fp64"] = {k: ref[k] for k in ("value", "ms_per_step", "roofline", "step_latency_ms", "kernels")}
+        out["fp64"] = {k: ref[k] for k in ("value", "ms_per_step", "roofline", "step_latency_ms", "kernels",
+                                            "autotune")}
         out["speedup_vs_fp64"] = head["value"] / ref["value"]
         out["j_err_vs_fp64"] = float(np.abs(jm - jr).max() / np.abs(jr).max())
         out["j_err_steps"] = total

@@ -208,6 +208,37 @@ typedef enum {
 } vgtb_kernel;
 
 /*
+ * Autotuning of the kernel variants of the per-step path.
+ *
+ * Times, on this context's own buffers and stream, every candidate of
+ *   - the block-sparse product W = H D: FP64 matrix cores with 1, 2 or 4
+ *     16-column slices per wavefront (variant -1, -2, -4; four orbitals per
+ *     atom), or vector FMAs with 1 or 2 columns per thread (variant 1, 2;
+ *     row groups of at most 8 atoms);
+ *   - the dense product S^-1 W: workgroup tiles 1 = 32x32, 2 = 64x64,
+ *     3 = 128x64 (FP64 and FP32 forms); 1 = 64x64, 2 = 128x128 (3xBF16; the
+ *     latter when the padded size is a multiple of 128),
+ * each launched `reps` times after one warm-up launch, and keeps the fastest
+ * of each for the following steps.  Only scratch buffers are written: the
+ * densities, history and step index are unchanged.  The variants differ in
+ * summation order only.  Needs a density (VGTB_E_STATE otherwise), reps >= 1
+ * (VGTB_E_INVAL).  out_host may be NULL.  Synchronises the stream.  For a
+ * context on the small-system path (whole steps per launch) nothing is timed
+ * (n_spmm = n_gemm = 0).
+ */
+typedef struct {
+  int32_t spmm_variant;          /* chosen sparse-product variant               */
+  int32_t gemm_tile;             /* chosen dense-product tile (0: size rule)    */
+  int32_t n_spmm, n_gemm;        /* number of candidates timed                  */
+  int32_t spmm_candidates[8];
+  double spmm_ms[8];             /* average launch time of each candidate (ms)  */
+  int32_t gemm_candidates[4];
+  double gemm_ms[4];
+} vgtb_tuning;
+
+vgtb_status vgtb_autotune(vgtb_ctx *ctx, int32_t reps, vgtb_tuning *out_host);
+
+/*
  * Per-kernel timing with HIP events recorded on the context stream around
  * every launch of vgtb_step while enabled (enable != 0).  Enabling clears
  * the totals.  vgtb_profile_read synchronises the stream and returns the

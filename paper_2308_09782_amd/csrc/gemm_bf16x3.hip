@@ -289,9 +289,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
 
 }  // namespace
 
+// tile: 1 = 64 x 64 (four wavefronts), 2 = 128 x 128 (sixteen; np a multiple
+// of 128 only); 0 = 128 x 128 where allowed from np = 512 up.
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
-                         hipStream_t s) {
-  if (np % BM2 == 0 && np >= 512) {
+                         hipStream_t s, int tile) {
+  if (tile == 0) tile = (np % BM2 == 0 && np >= 512) ? 2 : 1;
+  if (tile == 2 && np % BM2 == 0) {
     const int tm = np / BM2, tn = np / BN2;
     hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 4>), dim3(tm * tn, batch), dim3(64 * 16), 0, s, a, b,
                        y, n, np, batch, tm, tn);

@@ -476,7 +476,7 @@ void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
       vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, 0, nullptr,
                         c->spmm_variant, s);
     });
-    run(VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s); });
+    run(VGTB_K_GEMM, [&] { vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s, c->gemm_tile); });
     run(VGTB_K_UPDATE, [&] {
       vgtb::launch_update(c->y, first ? dcur : doth, doth, n, nk, first ? c->dt : 2.0 * c->dt,
                           c->ctr, s);
@@ -494,10 +494,11 @@ void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
   run(VGTB_K_GEMM, [&] {
     if (fmt == 1)
       vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
-                             static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s);
+                             static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s, c->gemm_tile);
     else
       vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
-                                static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s);
+                                static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s,
+                                c->gemm_tile);
   });
   const float2 *wid = fmt == 1 ? static_cast<const float2 *>(c->w_lo) : c->w32;
   const double2 *m0 = c->m0_active ? c->m0 : nullptr;
@@ -1132,6 +1133,105 @@ void vgtb_destroy(vgtb_ctx *c) {
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
+}
+
+vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (reps < 1) return fail(c, VGTB_E_INVAL, "reps must be >= 1");
+  if (!c->have_density) return fail(c, VGTB_E_STATE, "vgtb_autotune before a density was set");
+  HIP_TRY(c, hipSetDevice(c->device));
+  vgtb_tuning t{};
+  t.spmm_variant = c->spmm_variant;
+  t.gemm_tile = c->gemm_tile;
+  if (c->small_path) {   // neither kernel runs on this path
+    if (out) *out = t;
+    return VGTB_OK;
+  }
+  const int n = c->n, nk = c->nk;
+  const bool dev = c->precision != VGTB_FP64;
+  const int fmt = !dev ? 0 : (c->precision == VGTB_FP32 ? 1 : 2);
+  hipStream_t s = c->stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  auto time_it = [&](auto &&launch, double &ms) -> vgtb_status {
+    launch();   // warm-up (code load, caches)
+    HIP_TRY(c, hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch();
+    HIP_TRY(c, hipEventRecord(e1, s));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float el = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&el, e0, e1));
+    ms = el / reps;
+    return VGTB_OK;
+  };
+  // Operands: H_k at A = 0 and the current level (only scratch buffers are written).
+  vgtb::launch_assemble(c->g, c->kpts_dev, nk, vgtb::StepSource{nullptr, nullptr}, c->spk,
+                        c->scc ? c->v : nullptr, c->hq, s);
+  const double2 *dcur = c->dlev[c->cur];
+  std::vector<int> sv;
+  if (c->g.norb == 4) sv = {-1, -2, -4};
+  if (c->g.group_size <= 8) {
+    sv.push_back(1);
+    sv.push_back(2);
+  }
+  double best = 1e300;
+  for (int v : sv) {
+    double ms = 0.0;
+    st = time_it([&] {
+      vgtb::launch_spmm(c->g, dcur, dev ? c->d0 : nullptr, n, nk, c->hq, dev ? c->c0 : nullptr,
+                        dev ? c->w_lo : c->w, fmt, c->np, c->w32, v, s);
+    }, ms);
+    if (st != VGTB_OK) break;
+    if (t.n_spmm < 8) {
+      t.spmm_candidates[t.n_spmm] = v;
+      t.spmm_ms[t.n_spmm++] = ms;
+    }
+    if (ms < best) {
+      best = ms;
+      t.spmm_variant = v;
+    }
+  }
+  std::vector<int> gv;
+  if (fmt == 2) {
+    gv.push_back(1);
+    if (c->np % 128 == 0) gv.push_back(2);
+  } else {
+    gv = {1, 2, 3};
+  }
+  best = 1e300;
+  for (int tile : gv) {
+    if (st != VGTB_OK) break;
+    double ms = 0.0;
+    st = time_it([&] {
+      if (fmt == 0)
+        vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s, tile);
+      else if (fmt == 1)
+        vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
+                               static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s, tile);
+      else
+        vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
+                                  static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s,
+                                  tile);
+    }, ms);
+    if (st != VGTB_OK) break;
+    t.gemm_candidates[t.n_gemm] = tile;
+    t.gemm_ms[t.n_gemm++] = ms;
+    if (ms < best) {
+      best = ms;
+      t.gemm_tile = tile;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != VGTB_OK) return st;
+  HIP_TRY(c, hipGetLastError());
+  c->spmm_variant = t.spmm_variant;
+  c->gemm_tile = t.gemm_tile;
+  drop_graphs(c);   // captured steps name the previous kernels
+  if (out) *out = t;
+  return VGTB_OK;
 }
 
 vgtb_status vgtb_zgemm(const void *a, const void *b, void *cc, int32_t n, int32_t batch,

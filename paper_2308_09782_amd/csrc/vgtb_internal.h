@@ -151,12 +151,13 @@ void launch_density_from_vectors(const double2 *evec, const double *occ, double2
                                  int nk, hipStream_t s);
 
 // ---- launchers (gemm_mfma.hip, gemm_bf16x3.hip) ------------------------------
+// tile: workgroup tile shape (0 = the size rule; see the definitions).
 void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int batch,
-                      hipStream_t s);
+                      hipStream_t s, int tile = 0);
 void launch_cgemm_f32(const float2 *a, const float2 *b, float2 *c, int n, int batch,
-                      hipStream_t s);
+                      hipStream_t s, int tile = 0);
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
-                         hipStream_t s);
+                         hipStream_t s, int tile = 0);
 
 }  // namespace vgtb
 
@@ -166,6 +167,7 @@ struct vgtb_ctx {
   double volume = 0.0, n_electrons = 0.0, dt = 0.0;
   int precision = 0, rescale_every = 0, hist_cap = 1;
   int spmm_variant = -1;       // sparse-product kernel (see launch_spmm)
+  int gemm_tile = 0;           // dense-product tile shape (0: size rule; vgtb_autotune)
   bool scc = false, z_from_ground_state = false;
   bool small_path = false;     // whole blocks of steps per launch (kSmallN)
   bool use_graphs = true;      // replay captured two-step graphs (general path)

@@ -28,7 +28,7 @@ EXPORTED = [
     "vgtb_read_observables", "vgtb_get_density", "vgtb_get_reference_charges",
     "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
-    "vgtb_spectrum",
+    "vgtb_spectrum", "vgtb_autotune",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
            "assemble": 6, "small": 7}
@@ -55,6 +55,13 @@ class VgtbOptions(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rescale_every", ctypes.c_int32), ("history_capacity", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class VgtbTuning(ctypes.Structure):
+    _fields_ = [("spmm_variant", ctypes.c_int32), ("gemm_tile", ctypes.c_int32),
+                ("n_spmm", ctypes.c_int32), ("n_gemm", ctypes.c_int32),
+                ("spmm_candidates", ctypes.c_int32 * 8), ("spmm_ms", ctypes.c_double * 8),
+                ("gemm_candidates", ctypes.c_int32 * 4), ("gemm_ms", ctypes.c_double * 4)]
 
 
 _lib = None
@@ -89,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "vgtb_spectrum": [vp, i64, vp, ctypes.c_double, i64, vp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, vp, vp],
+        "vgtb_autotune": [vp, i32, ctypes.POINTER(VgtbTuning)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -326,6 +334,14 @@ class Propagator:
                                       float(e0), float(tau0), 1 if subtract_mean else 0,
                                       sig.ctypes.data, eps.ctypes.data), self.ctx)
         return sig, eps
+
+    def autotune(self, reps: int = 5) -> dict:
+        """Time the kernel variants on this context and keep the fastest (vgtb_autotune)."""
+        t = VgtbTuning()
+        _check(self.lib.vgtb_autotune(self.ctx, int(reps), ctypes.byref(t)), self.ctx)
+        return {"spmm_variant": t.spmm_variant, "gemm_tile": t.gemm_tile,
+                "spmm_ms": {int(t.spmm_candidates[i]): float(t.spmm_ms[i]) for i in range(t.n_spmm)},
+                "gemm_ms": {int(t.gemm_candidates[i]): float(t.gemm_ms[i]) for i in range(t.n_gemm)}}
 
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
