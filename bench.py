@@ -50,6 +50,15 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants instead of timing them first "
                          "(vgtb_autotune)")
+    ap.add_argument("--serve", action="store_true",
+                    help="instead of timing one workload: serve a seeded Poisson stream of "
+                         "propagation requests and report time-to-spectrum p50/p99")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="mean arrivals per second")
+    ap.add_argument("--serve-steps", type=int, nargs=2, default=[500, 2000],
+                    help="range of step counts per request")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-arena-gib", type=float, default=64.0)
     ap.add_argument("--accuracy", action="store_true",
                     help="instead of timing: run the workload's full step count in the reduced "
                          "forms and in FP64 and report the current and spectrum errors")
@@ -242,6 +251,59 @@ def accuracy_run(vg, torch, sysm, atab, dt, forms, n_steps, workload):
     return out
 
 
+def serve_run(vg, args):
+    """A seeded Poisson stream of requests: a-Si/c-Si-shaped systems of 8-512 atoms,
+    meshes from Gamma to 4x4x4, sin^2 pulses with omega in [0.05, 0.3] Ha, the 3xBF16
+    form; served by vgtb_server_run with admission by arena footprint."""
+    import vgtb_synth as vs
+    rng = np.random.default_rng(1005)
+    n = args.serve_requests
+    gaps = rng.exponential(1.0 / args.serve_rate, n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    # (atoms, meshes allowed, weight): large systems on coarse meshes only.
+    kinds = [(8, [(1, 1, 1), (2, 2, 2), (4, 4, 4)], 0.4), (64, [(1, 1, 1), (2, 2, 2), (4, 4, 4)], 0.35),
+             (216, [(1, 1, 1), (2, 2, 2)], 0.15), (512, [(1, 1, 1), (2, 2, 2)], 0.10)]
+    cache = {}
+    omegas = np.linspace(0.02, 0.30, 57)
+    reqs = []
+    for i in range(n):
+        atoms, meshes, _ = kinds[rng.choice(len(kinds), p=[k[2] for k in kinds])]
+        mesh = meshes[rng.integers(len(meshes))]
+        key = (atoms, mesh)
+        if key not in cache:
+            ncell = {8: 1, 64: 2, 216: 3, 512: 4}[atoms]
+            cache[key] = (vs.diamond_supercell(1, mesh) if atoms == 8 else
+                          vs.amorphous_si(ncell, mesh, gamma_u=0.25))
+        steps = int(rng.integers(args.serve_steps[0], args.serve_steps[1] + 1))
+        omega = float(rng.uniform(0.05, 0.30))
+        dt = 0.2
+        field = vs.sin2_pulse_table(steps, dt, omega, 0.5 * steps * dt, 0.05)
+        reqs.append(dict(system=cache[key], dt=dt, precision="bf16x3", n_steps=steps, field=field,
+                         arrival_s=float(arrivals[i]), omegas=omegas))
+    with vg.Server(int(args.serve_arena_gib * 2 ** 30), max_active=args.serve_slots) as srv:
+        res, summ = srv.run(reqs)
+    ok = [x for x in res if x["status"] == 0]
+    tts = np.array([x["finished_s"] - x["arrival_s"] for x in ok])
+    wait = np.array([x["admitted_s"] - x["arrival_s"] for x in ok])
+    mix = {}
+    for r in reqs:
+        k = f"{r['system'].n_atoms} atoms x {r['system'].n_k} k"
+        mix[k] = mix.get(k, 0) + 1
+    return {
+        "metric": "serving: time-to-spectrum p50/p99 (s) and aggregate k*steps/s",
+        "requests": n, "completed": len(ok), "rate_per_s": args.serve_rate,
+        "steps_range": list(args.serve_steps), "slots": args.serve_slots,
+        "arena_gib": args.serve_arena_gib, "dtype": "bf16x3 products, f64 state",
+        "time_to_spectrum_s": {"p50": float(np.percentile(tts, 50)), "p99": float(np.percentile(tts, 99)),
+                               "max": float(tts.max())},
+        "admission_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+        "k_steps_per_s": summ["k_steps_per_s"], "makespan_s": summ["makespan_s"],
+        "peak_active": summ["peak_active"], "peak_gib": summ["peak_bytes"] / 2 ** 30,
+        "mix": mix,
+        "data": "synthetic (seeded a-Si/c-Si supercells, sin^2 pulses, Poisson arrivals)",
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -255,6 +317,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.serve:
+        print(json.dumps(serve_run(vg, args)), flush=True)
+        return 0
     cfg = vs.CONFIGS[args.workload]
     sysm = vs.config_system(args.workload)
     dt = cfg["dt"]

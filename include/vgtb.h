@@ -192,6 +192,66 @@ const char *vgtb_last_error(const vgtb_ctx *ctx);
 
 void vgtb_destroy(vgtb_ctx *ctx);
 
+/*
+ * Serving: several propagations overlapped on one GPU.
+ *
+ * A server owns a caller-provided device arena (dev_arena, arena_bytes; the
+ * caller keeps it alive until vgtb_server_destroy; 256-byte aligned) and
+ * max_active slots (1..64), each a HIP stream the server creates.
+ *
+ * vgtb_server_run(srv, n, requests, stats, summary) serves n requests and
+ * returns when all have finished or failed.  Request i arrives arrival_s
+ * seconds after the call starts.  Waiting requests are admitted first come
+ * first served when a slot is free and their workspace (vgtb_workspace_size,
+ * with the history capacity raised to n_steps) fits in the free part of the
+ * arena (first fit); a request larger than the whole arena fails with
+ * VGTB_E_NOMEM.  An admitted request is initialised on a worker thread
+ * (S_k^-1 and the ground state, Section 3.1; the field table), then stepped in
+ * chunks on its own stream, so the kernels of all running requests overlap.
+ * When its n_steps are done, J(t) (n_steps x 3, host j_out, may be NULL) and
+ * sigma(omega) of the x current (Eqs. 15-16 with e0 and tau0, n_omega complex
+ * values, host sigma_out, may be NULL) are written, and its slot and arena
+ * range are released.  The request's system, field table and omega grid must
+ * stay valid until the call returns.  stats (n entries) and summary may be
+ * NULL.  Results do not depend on the other requests.
+ */
+typedef struct vgtb_server vgtb_server;
+
+typedef struct {
+  const vgtb_system *system;
+  vgtb_options options;          /* history_capacity is raised to n_steps          */
+  int64_t n_steps;
+  int64_t n_field;               /* A(t_n), n_field x 3 doubles (host)             */
+  const double *field;
+  int32_t n_omega;               /* spectrum grid (host), may be 0                 */
+  const double *omega;
+  double e0, tau0;               /* Eq. 15 normalisation and damping time          */
+  double arrival_s;
+  double *j_out;                 /* host, n_steps x 3, may be NULL                 */
+  double *sigma_out;             /* host, n_omega complex128, may be NULL          */
+} vgtb_request;
+
+typedef struct {
+  vgtb_status status;
+  int32_t slot;                  /* -1 if never admitted                           */
+  size_t workspace_bytes;
+  double arrival_s, admitted_s, ready_s, finished_s;   /* seconds on the run clock */
+} vgtb_request_stats;
+
+typedef struct {
+  double makespan_s;             /* from the call to the last completion           */
+  double k_steps;                /* sum of n_k * n_steps of the finished requests  */
+  double k_steps_per_s;          /* k_steps / makespan_s                           */
+  size_t peak_bytes;             /* most arena bytes in use at once                */
+  int32_t peak_active;           /* most requests admitted at once                 */
+} vgtb_server_stats;
+
+vgtb_status vgtb_server_create(void *dev_arena, size_t arena_bytes, int32_t max_active,
+                               vgtb_server **out);
+vgtb_status vgtb_server_run(vgtb_server *srv, int32_t n, const vgtb_request *requests,
+                            vgtb_request_stats *stats_host, vgtb_server_stats *summary_host);
+void vgtb_server_destroy(vgtb_server *srv);
+
 /* Kernel classes of one step, for vgtb_profile_read. */
 typedef enum {
   VGTB_K_OBSERVE = 0,   /* Mulliken / energy / current sweep of D_n            */

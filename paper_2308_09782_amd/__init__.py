@@ -8,6 +8,7 @@ from .vgtb import (  # noqa: F401
     EXPORTED,
     LIB_PATH,
     Propagator,
+    Server,
     VgtbError,
     load_library,
     make_options,

@@ -28,7 +28,8 @@ EXPORTED = [
     "vgtb_read_observables", "vgtb_get_density", "vgtb_get_reference_charges",
     "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
-    "vgtb_spectrum", "vgtb_autotune",
+    "vgtb_spectrum", "vgtb_autotune", "vgtb_server_create", "vgtb_server_run",
+    "vgtb_server_destroy",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
            "assemble": 6, "small": 7}
@@ -64,6 +65,27 @@ class VgtbTuning(ctypes.Structure):
                 ("gemm_candidates", ctypes.c_int32 * 4), ("gemm_ms", ctypes.c_double * 4)]
 
 
+class VgtbRequest(ctypes.Structure):
+    _fields_ = [("system", ctypes.c_void_p), ("options", VgtbOptions), ("n_steps", ctypes.c_int64),
+                ("n_field", ctypes.c_int64), ("field", ctypes.c_void_p),
+                ("n_omega", ctypes.c_int32), ("omega", ctypes.c_void_p),
+                ("e0", ctypes.c_double), ("tau0", ctypes.c_double), ("arrival_s", ctypes.c_double),
+                ("j_out", ctypes.c_void_p), ("sigma_out", ctypes.c_void_p)]
+
+
+class VgtbRequestStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("slot", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t), ("arrival_s", ctypes.c_double),
+                ("admitted_s", ctypes.c_double), ("ready_s", ctypes.c_double),
+                ("finished_s", ctypes.c_double)]
+
+
+class VgtbServerStats(ctypes.Structure):
+    _fields_ = [("makespan_s", ctypes.c_double), ("k_steps", ctypes.c_double),
+                ("k_steps_per_s", ctypes.c_double), ("peak_bytes", ctypes.c_size_t),
+                ("peak_active", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -97,6 +119,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_spectrum": [vp, i64, vp, ctypes.c_double, i64, vp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, vp, vp],
         "vgtb_autotune": [vp, i32, ctypes.POINTER(VgtbTuning)],
+        "vgtb_server_create": [vp, sz, i32, ctypes.POINTER(vp)],
+        "vgtb_server_run": [vp, i32, ctypes.POINTER(VgtbRequest), ctypes.POINTER(VgtbRequestStats),
+                            ctypes.POINTER(VgtbServerStats)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -108,6 +133,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vgtb_last_error.restype = ctypes.c_char_p
     lib.vgtb_destroy.argtypes = [vp]
     lib.vgtb_destroy.restype = None
+    lib.vgtb_server_destroy.argtypes = [vp]
+    lib.vgtb_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -346,3 +373,83 @@ class Propagator:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self.lib.vgtb_load_state(self.ctx, buf, len(blob)), self.ctx)
+
+
+class Server:
+    """Several propagations overlapped on one GPU (vgtb_server_*): one device
+    arena of arena_bytes, max_active slots (streams)."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 8, device: str = "cuda:0"):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.arena.data_ptr() + 255) & ~255
+            h = ctypes.c_void_p()
+            _check(self.lib.vgtb_server_create(aligned, int(arena_bytes), int(max_active),
+                                               ctypes.byref(h)))
+        self.srv = h
+
+    def run(self, requests):
+        """requests: dicts with system, dt, precision, n_steps, field (n x 3), arrival_s and
+        optionally rescale_every, omegas, e0, tau0.  Returns (results, summary): per request
+        {status, J (n_steps x 3), sigma, slot, workspace_bytes, arrival_s, admitted_s, ready_s,
+        finished_s}, and the run's {makespan_s, k_steps, k_steps_per_s, peak_bytes, peak_active}."""
+        n = len(requests)
+        reqs = (VgtbRequest * max(n, 1))()
+        stats = (VgtbRequestStats * max(n, 1))()
+        summ = VgtbServerStats()
+        keep, outs = [], []
+        for i, r in enumerate(requests):
+            s, arrs = make_system_struct(r["system"])
+            field = np.ascontiguousarray(r["field"], dtype=np.float64).reshape(-1, 3)
+            om = np.ascontiguousarray(r.get("omegas", np.zeros(0)), dtype=np.float64)
+            jo = np.zeros((int(r["n_steps"]), 3))
+            so = np.zeros(om.size, dtype=np.complex128)
+            keep.append((s, arrs, field, om))
+            outs.append((jo, so))
+            q = reqs[i]
+            q.system = ctypes.cast(ctypes.pointer(s), ctypes.c_void_p)
+            q.options = make_options(r["dt"], r.get("precision", "bf16x3"),
+                                     r.get("rescale_every", 50), 1)
+            q.n_steps = int(r["n_steps"])
+            q.n_field = field.shape[0]
+            q.field = field.ctypes.data
+            q.n_omega = om.size
+            q.omega = om.ctypes.data if om.size else None
+            q.e0 = float(r.get("e0", 1.0))
+            q.tau0 = float(r.get("tau0", 200.0))
+            q.arrival_s = float(r.get("arrival_s", 0.0))
+            q.j_out = jo.ctypes.data
+            q.sigma_out = so.ctypes.data if om.size else None
+        _check(self.lib.vgtb_server_run(self.srv, n, reqs, stats, ctypes.byref(summ)))
+        results = []
+        for i in range(n):
+            st = stats[i]
+            results.append({"status": int(st.status), "J": outs[i][0], "sigma": outs[i][1],
+                            "slot": int(st.slot), "workspace_bytes": int(st.workspace_bytes),
+                            "arrival_s": st.arrival_s, "admitted_s": st.admitted_s,
+                            "ready_s": st.ready_s, "finished_s": st.finished_s})
+        del keep
+        summary = {"makespan_s": summ.makespan_s, "k_steps": summ.k_steps,
+                   "k_steps_per_s": summ.k_steps_per_s, "peak_bytes": int(summ.peak_bytes),
+                   "peak_active": int(summ.peak_active)}
+        return results, summary
+
+    def close(self):
+        if getattr(self, "srv", None):
+            self.lib.vgtb_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
