@@ -187,13 +187,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
     }
 
   // Per stage: 2048 u32x4 of A (4 planes x 128 rows x 4) and 2048 of B (4 x 4 x 128).
+  // A element L of a plane is row AROW(L), 16-byte column ACOL(L): sixteen
+  // consecutive lanes take sixteen rows of one column, so their LDS stores hit
+  // distinct banks (row stride APAD = 80 bytes), like the fragment reads; a
+  // wavefront still loads whole 64-byte row segments from global memory.
+#define AROW(L) (((L) & 15) | ((((L) >> 6) & 7) << 4))
+#define ACOL(L) (((L) >> 4) & 3)
   u32x4 ra[LD], rb[LD];
 #define VG_LOAD128(k0)                                                                         \
   do {                                                                                         \
     _Pragma("unroll") for (int i = 0; i < LD; ++i) {                                           \
       const int L = tid + i * NT2;                                                             \
       ra[i] = *reinterpret_cast<const u32x4 *>(A + (L >> 9) * plane + boff +                   \
-                                               (size_t)(bm + ((L >> 2) & 127)) * np + (k0) + (L & 3) * 8); \
+                                               (size_t)(bm + AROW(L)) * np + (k0) + ACOL(L) * 8); \
       rb[i] = *reinterpret_cast<const u32x4 *>(B + (L >> 9) * plane + boff +                   \
                                                ((size_t)((k0) / 8 + ((L >> 7) & 3)) * np + bn + (L & 127)) * 8); \
     }                                                                                          \
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
   do {                                                                                         \
     _Pragma("unroll") for (int i = 0; i < LD; ++i) {                                           \
       const int L = tid + i * NT2;                                                             \
-      As[buf][L >> 9][(L >> 2) & 127][L & 3] = ra[i];                                          \
+      As[buf][L >> 9][AROW(L)][ACOL(L)] = ra[i];                                               \
       Bs[buf][L >> 9][(L >> 7) & 3][L & 127] = rb[i];                                          \
     }                                                                                          \
   } while (0)
@@ -273,6 +279,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
 #undef VG_LOAD128
 #undef VG_STORE128
 #undef VG_READB
+#undef AROW
+#undef ACOL
 
   float2 *Yb = Y + (size_t)batch * n * n;
 #pragma unroll
