@@ -11,7 +11,10 @@ is stated in the docstring.  All arithmetic is complex128 / float64.
 
 Pinned by tests/test_oracle_*.py (closed-form leapfrog solution, brute-force
 matrix-exponential propagation, invariants, the gauge identity, textbook sp3
-and single-orbital-chain models, SCC special cases, spectrum closed forms).
+and single-orbital-chain models, SCC special cases, spectrum closed forms; for
+the momentum-matrix coupling of Eq. 12: Hermiticity, the closed-form
+diamagnetic current, the |A|^2 term as a pure phase, the orthogonal-basis limit,
+energy conservation at constant A and brute-force propagation).
 """
 from .tddftb import (  # noqa: F401
     C_LIGHT,
@@ -20,6 +23,10 @@ from .tddftb import (  # noqa: F401
     overlap_inverse,
     h0_k,
     momentum_k,
+    overlap_momentum_k,
+    h_ext_k,
+    field_hamiltonian_k,
+    current_matrix_k,
     scc_potential,
     hamiltonian_k,
     mulliken,

@@ -14,6 +14,15 @@ Readings where the paper leaves a choice open:
   * SCC shift of step n is evaluated from the charges of D_n.
   * Leapfrog start (Eq. 13 needs two levels): one forward Euler step.
   * Energy: E = sum_k w_k Re Tr(D_k H0_k(A)) + 1/2 dq^T gamma dq.
+
+The paper's own coupling (Eq. 12) is the second mode, coupling="momentum":
+  * H_k(t) = H0_k + (1/c) A . P_k + |A|^2 / (2 c^2) S_k + H2, with the momentum
+    matrix P_k^alpha = sum_blocks exp(i k.d) <phi_mu| p^alpha |phi_nu> and
+    <phi_mu|p|phi_nu> = i dS/dR_J = i dS(d)/dd (the text after Eq. 12), taken
+    from the overlap gradient of each two-centre block; the on-site blocks have
+    no gradient (no intra-atomic momentum term in the two-centre form).
+  * Current matrix Pi_k = P_k + (A/c) S_k (the text after Eq. 14).
+  * Energy: E = sum_k w_k Re Tr(D_k (H0_k + H_ext,k)) + 1/2 dq^T gamma dq.
 """
 from __future__ import annotations
 
@@ -71,6 +80,42 @@ def momentum_k(sysm, kvec, a_vec) -> np.ndarray:
     return np.stack(out)
 
 
+def overlap_momentum_k(sysm, kvec) -> np.ndarray:
+    """P_k^alpha, shape (3, N, N): Bloch sum of <phi_mu|p^alpha|phi_nu> = i dS/dd^alpha
+    over the blocks (Eq. 12 and the text after it)."""
+    if sysm.blk_ds is None:
+        raise ValueError("the momentum-matrix coupling needs the overlap gradients blk_ds")
+    kk = np.asarray(kvec, float)
+    return np.stack([bloch_sum(sysm, 1j * sysm.blk_ds[:, alpha], kk) for alpha in range(3)])
+
+
+def h_ext_k(sysm, kvec, a_vec, s_k) -> np.ndarray:
+    """Eq. (12) Bloch-summed: (1/c) A . P_k + |A|^2 / (2 c^2) S_k."""
+    a = np.asarray(a_vec, float) / C_LIGHT
+    p = overlap_momentum_k(sysm, kvec)
+    return np.tensordot(a, p, axes=1) + 0.5 * float(a @ a) * s_k
+
+
+def field_hamiltonian_k(sysm, kvec, a_vec, s_k, coupling: str = "peierls") -> np.ndarray:
+    """The field-dependent one-electron part of H_k(t) (no SCC term)."""
+    if coupling == "peierls":
+        return h0_k(sysm, kvec, a_vec)
+    if coupling == "momentum":
+        return h0_k(sysm, kvec, np.zeros(3)) + h_ext_k(sysm, kvec, a_vec, s_k)
+    raise ValueError(f"unknown coupling {coupling!r}")
+
+
+def current_matrix_k(sysm, kvec, a_vec, s_k, coupling: str = "peierls") -> np.ndarray:
+    """Pi_k = c dH/dA, shape (3, N, N): dH0/dk at k + A/c (Peierls), or
+    P_k + (A/c) S_k (momentum coupling, the text after Eq. 14)."""
+    if coupling == "peierls":
+        return momentum_k(sysm, kvec, a_vec)
+    if coupling == "momentum":
+        a = np.asarray(a_vec, float) / C_LIGHT
+        return overlap_momentum_k(sysm, kvec) + a[:, None, None] * s_k[None]
+    raise ValueError(f"unknown coupling {coupling!r}")
+
+
 def mulliken(sysm, dens: List[np.ndarray], ovl: List[np.ndarray]) -> np.ndarray:
     """q_I = sum_k w_k Re sum_{mu in I} [D_k S_k]_{mu mu}  (Mulliken population, Section 2)."""
     no = sysm.norb
@@ -86,9 +131,11 @@ def scc_potential(gamma: np.ndarray, q: np.ndarray, z: np.ndarray) -> np.ndarray
     return gamma @ (q - z)
 
 
-def hamiltonian_k(sysm, kvec, a_vec, s_k, v_atom: Optional[np.ndarray]) -> np.ndarray:
-    """H_k(t) = H0(k + A/c) + 1/2 (V_I + V_J) S_k^{mu nu}  (Eqs. 8-10)."""
-    h = h0_k(sysm, kvec, a_vec)
+def hamiltonian_k(sysm, kvec, a_vec, s_k, v_atom: Optional[np.ndarray],
+                  coupling: str = "peierls") -> np.ndarray:
+    """H_k(t) = field part + 1/2 (V_I + V_J) S_k^{mu nu}  (Eqs. 8-10, 12): the field
+    part is H0(k + A/c) (Peierls) or H0(k) + H_ext (momentum coupling)."""
+    h = field_hamiltonian_k(sysm, kvec, a_vec, s_k, coupling)
     if v_atom is not None:
         v_orb = np.repeat(v_atom, sysm.norb)
         h = h + 0.5 * (v_orb[:, None] + v_orb[None, :]) * s_k
@@ -164,17 +211,17 @@ def density_derivative_columns(s_inv: np.ndarray, h: np.ndarray, d: np.ndarray, 
     return -1j * (s_inv @ (h @ d[:, cols]) - d @ (h @ s_inv[:, cols]))
 
 
-def observables(sysm, dens, ovl, a_vec, z):
+def observables(sysm, dens, ovl, a_vec, z, coupling: str = "peierls"):
     """Current (Eq. 14), band + SCC energy, Tr(D S) and Mulliken charges of one time level."""
     nk = sysm.n_k
     jcur = np.zeros(3)
     e_band = 0.0
     tr = 0.0
     for w, kvec, d, s in zip(sysm.kw, sysm.kpts, dens, ovl):
-        pik = momentum_k(sysm, kvec, a_vec)
+        pik = current_matrix_k(sysm, kvec, a_vec, s, coupling)
         for alpha in range(3):
             jcur[alpha] += np.real(np.trace(d @ pik[alpha]))
-        e_band += w * np.real(np.trace(d @ h0_k(sysm, kvec, a_vec)))
+        e_band += w * np.real(np.trace(d @ field_hamiltonian_k(sysm, kvec, a_vec, s, coupling)))
         tr += w * np.real(np.trace(d @ s))
     jcur *= -1.0 / (sysm.volume * nk)
     q = mulliken(sysm, dens, ovl)
@@ -204,7 +251,7 @@ def make_state(sysm, d0, z) -> OracleState:
 
 
 def propagate(sysm, d0, a_table: np.ndarray, dt: float, n_steps: int, z=None,
-              state: Optional[OracleState] = None):
+              state: Optional[OracleState] = None, coupling: str = "peierls"):
     """Leapfrog integration of Eq. (6) with Eq. (13); records observables.
 
     Step n (time t_n = n dt) uses A(t_n) = a_table[min(n, len-1)] and the SCC
@@ -221,7 +268,7 @@ def propagate(sysm, d0, a_table: np.ndarray, dt: float, n_steps: int, z=None,
     for _ in range(n_steps):
         n = state.step
         a_vec = a_table[min(n, a_table.shape[0] - 1)]
-        jcur, e, tr, q = observables(sysm, state.d_cur, state.s, a_vec, state.z)
+        jcur, e, tr, q = observables(sysm, state.d_cur, state.s, a_vec, state.z, coupling)
         hist["J"].append(jcur)
         hist["E"].append(e)
         hist["trace"].append(tr)
@@ -229,7 +276,7 @@ def propagate(sysm, d0, a_table: np.ndarray, dt: float, n_steps: int, z=None,
         v = scc_potential(sysm.gamma, q, state.z) if sysm.gamma is not None else None
         new = []
         for ik, kvec in enumerate(sysm.kpts):
-            h = hamiltonian_k(sysm, kvec, a_vec, state.s[ik], v)
+            h = hamiltonian_k(sysm, kvec, a_vec, state.s[ik], v, coupling)
             ddot = density_derivative(state.s_inv[ik], h, state.d_cur[ik])
             if state.d_prev is None:
                 new.append(state.d_cur[ik] + dt * ddot)

@@ -58,6 +58,10 @@ class TBSystem:
     z_ref: Optional[np.ndarray] = None   # per-atom reference charge; None = ground-state charges
     gamma: Optional[np.ndarray] = None   # (n_atoms, n_atoms) SCC kernel, None = non-SCC
     hubbard_u: float = 0.0
+    # (n_blocks, 3, norb, norb) real: dS(d)/dd^alpha, the gradient of each overlap
+    # block with respect to the bond vector (= with respect to R_J); zero for the
+    # on-site blocks.  Needed by the momentum-matrix coupling; None if not provided.
+    blk_ds: Optional[np.ndarray] = None
 
     @property
     def n_atoms(self) -> int:
@@ -98,6 +102,7 @@ class TBSystem:
         arrays = {k: (np.asarray(v) if v is not None else np.zeros(0)) for k, v in arrays.items()}
         arrays["has_gamma"] = np.asarray(self.gamma is not None)
         arrays["has_z_ref"] = np.asarray(self.z_ref is not None)
+        arrays["has_blk_ds"] = np.asarray(self.blk_ds is not None)
         np.savez(path, **arrays)
 
     @staticmethod
@@ -115,6 +120,8 @@ class TBSystem:
             kw["gamma"] = None
         if not bool(f["has_z_ref"]):
             kw["z_ref"] = None
+        if "has_blk_ds" not in f.files or not bool(f["has_blk_ds"]):
+            kw["blk_ds"] = None
         return TBSystem(**kw)
 
 
@@ -140,9 +147,35 @@ def sk_block_sp(d: np.ndarray, v: np.ndarray) -> np.ndarray:
     return b
 
 
+def sk_block_sp_grad(d: np.ndarray, v: np.ndarray, dv: np.ndarray) -> np.ndarray:
+    """Gradient of sk_block_sp(d, v(|d|)) with respect to d: shape (3, 4, 4).
+
+    v and dv are the bond integrals and their radial derivatives at |d|; with
+    c = d / r, dr/dd_a = c_a and dc_i/dd_a = (delta_ia - c_i c_a) / r.
+    """
+    r = float(np.linalg.norm(d))
+    c = d / r
+    vss, vsp, vpps, vppp = v
+    dss, dsp, dpps, dppp = dv
+    dc = (np.eye(3) - np.outer(c, c)) / r            # dc[i, a] = dc_i / dd_a
+    g = np.empty((3, 4, 4))
+    for a in range(3):
+        g[a, 0, 0] = dss * c[a]
+        g[a, 0, 1:] = dc[:, a] * vsp + c * dsp * c[a]
+        g[a, 1:, 0] = -g[a, 0, 1:]
+        dcc = np.outer(dc[:, a], c) + np.outer(c, dc[:, a])
+        g[a, 1:, 1:] = dcc * (vpps - vppp) + np.outer(c, c) * (dpps - dppp) * c[a] + np.eye(3) * dppp * c[a]
+    return g
+
+
 def bond_integrals(v0: np.ndarray, r: float) -> np.ndarray:
     """Distance dependence v0 * exp(-(r - R_NN) / DECAY)."""
     return v0 * math.exp(-(r - R_NN) / DECAY)
+
+
+def bond_integrals_dr(v0: np.ndarray, r: float) -> np.ndarray:
+    """Radial derivative of bond_integrals."""
+    return -bond_integrals(v0, r) / DECAY
 
 
 def _images(cell: np.ndarray, reach: float) -> np.ndarray:
@@ -154,13 +187,16 @@ def _images(cell: np.ndarray, reach: float) -> np.ndarray:
     return n @ cell
 
 
-def build_blocks(cell, pos, norb, onsite_h, onsite_s, hop_h, hop_s, cutoff=CUTOFF):
+def build_blocks(cell, pos, norb, onsite_h, onsite_s, hop_h, hop_s, cutoff=CUTOFF,
+                 hop_s_grad=None):
     """List every (I, J, L) with 0 < |d| < cutoff plus the on-site blocks.
 
-    hop_h(d) and hop_s(d) return the norb x norb real blocks for bond d.
+    hop_h(d) and hop_s(d) return the norb x norb real blocks for bond d;
+    hop_s_grad(d) (optional) the (3, norb, norb) gradient of hop_s, and then a
+    sixth array of gradients is returned (zero on site).
     """
     L = _images(cell, cutoff)
-    bi, bj, bd, bh, bs = [], [], [], [], []
+    bi, bj, bd, bh, bs, bg = [], [], [], [], [], []
     n = pos.shape[0]
     for i in range(n):
         dvec = (pos[None, :, None, :] + L[None, None, :, :] - pos[i][None, None, None, :])[0]
@@ -173,11 +209,18 @@ def build_blocks(cell, pos, norb, onsite_h, onsite_s, hop_h, hop_s, cutoff=CUTOF
                         raise ValueError("two atoms coincide")
                     bi.append(i); bj.append(j); bd.append(np.zeros(3))
                     bh.append(onsite_h.copy()); bs.append(onsite_s.copy())
+                    if hop_s_grad is not None:
+                        bg.append(np.zeros((3, norb, norb)))
                 else:
                     bi.append(i); bj.append(j); bd.append(d)
                     bh.append(hop_h(d)); bs.append(hop_s(d))
-    return (np.asarray(bi, np.int32), np.asarray(bj, np.int32), np.asarray(bd, np.float64),
-            np.asarray(bh, np.float64), np.asarray(bs, np.float64))
+                    if hop_s_grad is not None:
+                        bg.append(hop_s_grad(d))
+    out = (np.asarray(bi, np.int32), np.asarray(bj, np.int32), np.asarray(bd, np.float64),
+           np.asarray(bh, np.float64), np.asarray(bs, np.float64))
+    if hop_s_grad is not None:
+        out = out + (np.asarray(bg, np.float64).reshape(-1, 3, norb, norb),)
+    return out
 
 
 def gamma_mesh(cell: np.ndarray, mesh) -> tuple:
@@ -222,12 +265,17 @@ def _sp_system(name, cell, pos, vh, vs, kmesh, n_electrons, gamma_u=None, cutoff
     def hop_s(d):
         return sk_block_sp(d, bond_integrals(vs, float(np.linalg.norm(d))))
 
-    bi, bj, bd, bh, bs = build_blocks(cell, pos, 4, onsite_h, onsite_s, hop_h, hop_s, cutoff)
+    def hop_s_grad(d):
+        r = float(np.linalg.norm(d))
+        return sk_block_sp_grad(d, bond_integrals(vs, r), bond_integrals_dr(vs, r))
+
+    bi, bj, bd, bh, bs, bg = build_blocks(cell, pos, 4, onsite_h, onsite_s, hop_h, hop_s, cutoff,
+                                          hop_s_grad)
     kpts, kw = gamma_mesh(cell, kmesh)
     gam = gamma_matrix(cell, pos, gamma_u) if gamma_u is not None else None
     return TBSystem(name=name, cell=cell, pos=pos, norb=4, blk_i=bi, blk_j=bj, blk_d=bd,
                     blk_h0=bh, blk_s=bs, kpts=kpts, kw=kw, n_electrons=float(n_electrons),
-                    z_ref=None, gamma=gam, hubbard_u=float(gamma_u or 0.0))
+                    z_ref=None, gamma=gam, hubbard_u=float(gamma_u or 0.0), blk_ds=bg)
 
 
 def diamond_positions(ncell: int) -> tuple:
