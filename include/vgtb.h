@@ -93,7 +93,24 @@ typedef struct {
   double n_electrons;          /* per k-point                                   */
   const double *z_ref;         /* host, n_atoms, or NULL                        */
   const double *gamma;         /* host, n_atoms * n_atoms, or NULL (non-SCC)   */
+  const double *blk_ds;        /* host, n_blocks * 3 * orbs^2: dS/dd^alpha, the
+                                  gradient of each overlap block with respect to
+                                  its bond vector (= with respect to R_J), zero on
+                                  site; partner blocks must satisfy
+                                  dS(J,I,-d) = -dS(I,J,d)^T.  NULL unless the
+                                  momentum coupling is used.                    */
 } vgtb_system;
+
+/*
+ * How the vector potential enters H_k(t) (the SCC term, Eq. 10, is the same):
+ *   PEIERLS:  H0 blocks with the phase exp(i (k + A/c).d), i.e. H0(k + A/c);
+ *             current matrix Pi = dH0/dk at k + A/c.
+ *   MOMENTUM: the paper's Eq. 12, H0_k + (1/c) A.P_k + |A|^2/(2c^2) S_k with
+ *             P_k the Bloch sum of <phi_mu|p|phi_nu> = i dS/dR_J (needs
+ *             vgtb_system.blk_ds); current matrix Pi = P_k + (A/c) S_k (the
+ *             text after Eq. 14).  Not on the small-system path.
+ */
+typedef enum { VGTB_COUPLING_PEIERLS = 0, VGTB_COUPLING_MOMENTUM = 1 } vgtb_coupling;
 
 typedef struct {
   double dt;                   /* time step (atomic time units), finite, nonzero */
@@ -101,7 +118,7 @@ typedef struct {
   int32_t rescale_every;       /* deviation forms: re-Hermitise and rescale the
                                   trace every this many steps (0 = never)        */
   int32_t history_capacity;    /* observables ring length in steps (>= 1)        */
-  int32_t reserved;            /* must be 0                                      */
+  int32_t coupling;            /* vgtb_coupling                                  */
 } vgtb_options;
 
 /* Bytes of device arena vgtb_create needs for this system and options. */

@@ -49,6 +49,35 @@ __global__ void k_pair_bloch_s(PairGraph g, const double *kpts, double2 *spk) {
   spk[((size_t)k * g.n_pairs + p) * e2 + e] = acc;
 }
 
+// Momentum coupling: the k-dependent, time-independent pair blocks
+// h0k[k][p][e] = sum_images exp(i k.d) H0 and ppk[k][p][a][e] = sum_images
+// exp(i k.d) i dS/dd^a (Eq. 12: <phi_mu|p|phi_nu> = i dS/dR_J).
+__global__ void k_pair_bloch_momentum(PairGraph g, const double *kpts, double2 *h0k, double2 *ppk) {
+  const int e2 = g.norb * g.norb;
+  const int k = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n_pairs * e2) return;
+  const int p = t / e2, e = t % e2;
+  const double kx = kpts[3 * k], ky = kpts[3 * k + 1], kz = kpts[3 * k + 2];
+  double2 h = make_double2(0.0, 0.0), pa[3] = {h, h, h};
+  for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+    const double th = kx * g.img_d[3 * m] + ky * g.img_d[3 * m + 1] + kz * g.img_d[3 * m + 2];
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double hv = g.img_h0[(size_t)m * e2 + e];
+    h.x += cs * hv;
+    h.y += sn * hv;
+    for (int a = 0; a < 3; ++a) {
+      const double gv = g.img_ds[((size_t)m * 3 + a) * e2 + e];
+      pa[a].x -= sn * gv;      // i exp(i th) = -sin th + i cos th
+      pa[a].y += cs * gv;
+    }
+  }
+  const size_t pe = (size_t)k * g.n_pairs + p;
+  h0k[pe * e2 + e] = h;
+  for (int a = 0; a < 3; ++a) ppk[(pe * 3 + a) * e2 + e] = pa[a];
+}
+
 // Scatter pair values into a dense N x N matrix per k.  which = 0: S_k from
 // spk; which = 1: H0_k at A = 0 (Eq. 8), Bloch-summed here.
 __global__ void k_scatter_pairs(PairGraph g, const double *kpts, const double2 *spk, int which,
@@ -107,6 +136,8 @@ template <int NO>
 __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__restrict__ d, int n,
                                                 const double *kpts, StepSource src,
                                                 const double2 *__restrict__ spk,
+                                                const double2 *__restrict__ h0k,
+                                                const double2 *__restrict__ ppk,
                                                 double *__restrict__ part) {
   constexpr int E2 = NO * NO;
   constexpr int P = 64 / E2;
@@ -125,6 +156,22 @@ __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__re
     const double2 dv = d[idx];
     const double2 s = spk[((size_t)k * g.n_pairs + p) * E2 + e];
     q += dv.x * s.x + dv.y * s.y;
+    if (h0k != nullptr) {
+      // Momentum coupling: H = H0_k + a.P_k + |a|^2/2 S_k, Pi = P_k + a S_k (a = A/c);
+      // Re Tr(D X) over the pair block is sum Re(D conj(X)) for Hermitian X.
+      const size_t pe = (size_t)k * g.n_pairs + p;
+      const double2 h0 = h0k[pe * E2 + e];
+      const double2 px = ppk[(pe * 3 + 0) * E2 + e], py = ppk[(pe * 3 + 1) * E2 + e],
+                    pz = ppk[(pe * 3 + 2) * E2 + e];
+      const double a2 = 0.5 * (f.ax * f.ax + f.ay * f.ay + f.az * f.az);
+      const double hr = h0.x + f.ax * px.x + f.ay * py.x + f.az * pz.x + a2 * s.x;
+      const double hi = h0.y + f.ax * px.y + f.ay * py.y + f.az * pz.y + a2 * s.y;
+      en += dv.x * hr + dv.y * hi;
+      jx += dv.x * (px.x + f.ax * s.x) + dv.y * (px.y + f.ax * s.y);
+      jy += dv.x * (py.x + f.ay * s.x) + dv.y * (py.y + f.ay * s.y);
+      jz += dv.x * (pz.x + f.az * s.x) + dv.y * (pz.y + f.az * s.y);
+      continue;
+    }
     for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
       const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
       double sn, cs;
@@ -325,7 +372,9 @@ template <int NO>
 __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpts, StepSource src,
                                                   const double2 *__restrict__ spk,
                                                   const double *__restrict__ v,
-                                                  double2 *__restrict__ hq) {
+                                                  double2 *__restrict__ hq,
+                                                  const double2 *__restrict__ h0k,
+                                                  const double2 *__restrict__ ppk) {
   constexpr int E2 = NO * NO;
   const int k = blockIdx.y;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -335,6 +384,16 @@ __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpt
   const StepField f = step_field(src);
   const double k0x = kpts[3 * k], k0y = kpts[3 * k + 1], k0z = kpts[3 * k + 2];
   double2 h = make_double2(0.0, 0.0);
+  if (h0k != nullptr) {
+    // Momentum coupling (Eq. 12): H0_k + a.P_k + |a|^2/2 S_k with a = A/c.
+    const size_t pe = (size_t)k * g.n_pairs + p;
+    const double2 h0 = h0k[pe * E2 + e], sv = spk[pe * E2 + e];
+    const double2 px = ppk[(pe * 3 + 0) * E2 + e], py = ppk[(pe * 3 + 1) * E2 + e],
+                  pz = ppk[(pe * 3 + 2) * E2 + e];
+    const double a2 = 0.5 * (f.ax * f.ax + f.ay * f.ay + f.az * f.az);
+    h.x = h0.x + f.ax * px.x + f.ay * py.x + f.az * pz.x + a2 * sv.x;
+    h.y = h0.y + f.ax * px.y + f.ay * py.y + f.az * pz.y + a2 * sv.y;
+  } else
   for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
     const double dx = g.img_d[3 * m], dy = g.img_d[3 * m + 1], dz = g.img_d[3 * m + 2];
     const double hv = g.img_h0[(size_t)m * E2 + e];
@@ -1103,10 +1162,19 @@ void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const 
 }
 
 void launch_observe(const PairGraph &g, const double2 *d, int n, const double *kpts, int nk,
-                    StepSource src, const double2 *spk, double *part, hipStream_t s) {
+                    StepSource src, const double2 *spk, const double2 *h0k, const double2 *ppk,
+                    double *part, hipStream_t s) {
   dim3 grid(g.n_atoms, nk);
-  if (g.norb == 4) hipLaunchKernelGGL(k_observe<4>, grid, dim3(64), 0, s, g, d, n, kpts, src, spk, part);
-  else hipLaunchKernelGGL(k_observe<1>, grid, dim3(64), 0, s, g, d, n, kpts, src, spk, part);
+  if (g.norb == 4)
+    hipLaunchKernelGGL(k_observe<4>, grid, dim3(64), 0, s, g, d, n, kpts, src, spk, h0k, ppk, part);
+  else
+    hipLaunchKernelGGL(k_observe<1>, grid, dim3(64), 0, s, g, d, n, kpts, src, spk, h0k, ppk, part);
+}
+
+void launch_pair_bloch_momentum(const PairGraph &g, const double *kpts, int nk, double2 *h0k,
+                                double2 *ppk, hipStream_t s) {
+  dim3 grid(blocks_for((size_t)g.n_pairs * g.norb * g.norb, 256), nk);
+  hipLaunchKernelGGL(k_pair_bloch_momentum, grid, dim3(256), 0, s, g, kpts, h0k, ppk);
 }
 
 void launch_store_ring(const FieldChunk &f, int64_t step0, int ns, double *ring, hipStream_t s) {
@@ -1150,11 +1218,14 @@ static void spmm_launch(int threads, hipStream_t s, const PairGraph &g, const do
 }
 
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource src,
-                     const double2 *spk, const double *v, double2 *hq, hipStream_t s) {
+                     const double2 *spk, const double *v, double2 *hq, const double2 *h0k,
+                     const double2 *ppk, hipStream_t s) {
   const size_t tot = (size_t)g.n_pairs * g.norb * g.norb;
   dim3 grid(blocks_for(tot, 256), nk);
-  if (g.norb == 4) hipLaunchKernelGGL(k_assemble<4>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq);
-  else hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq);
+  if (g.norb == 4)
+    hipLaunchKernelGGL(k_assemble<4>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq, h0k, ppk);
+  else
+    hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq, h0k, ppk);
 }
 
 template <bool DELTA, int OUT, int CB>

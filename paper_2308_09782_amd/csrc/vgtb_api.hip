@@ -53,7 +53,7 @@ vgtb_status fail(vgtb_ctx *ctx, vgtb_status st, const std::string &msg) {
 struct HostGraph {
   int na = 0, norb = 0;
   std::vector<int> row_ptr, pair_col, pair_row, img_ptr;
-  std::vector<double> img_d, img_h0, img_s;
+  std::vector<double> img_d, img_h0, img_s, img_ds;
   std::vector<int> grp_ptr, ent_j, ent_mask, ent_pp, gp_pair, gp_il;
 };
 
@@ -169,6 +169,15 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
           msg = "block " + std::to_string(b) + " is not the transpose of its partner";
           return VGTB_E_INVAL;
         }
+        if (s->blk_ds)
+          for (int a = 0; a < 3; ++a) {
+            const double g1 = s->blk_ds[((size_t)b * 3 + a) * e2 + mu * no + nu];
+            const double g2 = s->blk_ds[((size_t)c * 3 + a) * e2 + nu * no + mu];
+            if (!std::isfinite(g1) || !(std::fabs(g1 + g2) <= 1e-12 * (1.0 + std::fabs(g1)))) {
+              msg = "overlap gradient of block " + std::to_string(b) + " is not minus the transpose of its partner's";
+              return VGTB_E_INVAL;
+            }
+          }
       }
   }
   hg.na = na;
@@ -191,6 +200,8 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
       hg.img_h0.push_back(s->blk_h0[(size_t)b * e2 + e]);
       hg.img_s.push_back(s->blk_s[(size_t)b * e2 + e]);
     }
+    if (s->blk_ds)
+      for (int e = 0; e < 3 * e2; ++e) hg.img_ds.push_back(s->blk_ds[(size_t)b * 3 * e2 + e]);
   }
   hg.img_ptr.push_back((int)(hg.img_d.size() / 3));
   for (int i = 0; i < na; ++i) hg.row_ptr[i + 1] += hg.row_ptr[i];
@@ -233,7 +244,15 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
     return VGTB_E_INVAL;
   }
   if (o->history_capacity < 1) { msg = "history_capacity must be >= 1"; return VGTB_E_INVAL; }
-  if (o->rescale_every < 0 || o->reserved != 0) { msg = "bad options"; return VGTB_E_INVAL; }
+  if (o->rescale_every < 0) { msg = "bad options"; return VGTB_E_INVAL; }
+  if (o->coupling != VGTB_COUPLING_PEIERLS && o->coupling != VGTB_COUPLING_MOMENTUM) {
+    msg = "unknown coupling";
+    return VGTB_E_INVAL;
+  }
+  if (o->coupling == VGTB_COUPLING_MOMENTUM && !s->blk_ds) {
+    msg = "the momentum coupling needs the overlap gradients blk_ds";
+    return VGTB_E_INVAL;
+  }
   if (!(s->n_electrons >= 0.0) || s->n_electrons > 2.0 * n) {
     msg = "n_electrons out of range";
     return VGTB_E_INVAL;
@@ -266,7 +285,7 @@ struct Carver {
 
 struct Sizes {
   int na, no, n, nk, np, ni, cap, precision, npad, ng, ne;
-  bool scc, deviation, small;
+  bool scc, deviation, small, mom;
 };
 
 template <typename Ctx>
@@ -282,6 +301,7 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->g.img_d = cv.template take<double>(3 * (size_t)z.ni);
   c->g.img_h0 = cv.template take<double>(e2 * z.ni);
   c->g.img_s = cv.template take<double>(e2 * z.ni);
+  c->g.img_ds = z.mom ? cv.template take<double>(3 * e2 * z.ni) : nullptr;
   c->g.grp_ptr = cv.template take<int>(z.ng + 1);
   c->g.ent_j = cv.template take<int>(z.ne);
   c->g.ent_mask = cv.template take<int>(z.ne);
@@ -290,6 +310,8 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->g.gp_il = cv.template take<int>(z.np);
   c->spk = cv.template take<double2>(e2 * z.np * z.nk);
   c->hq = cv.template take<double2>(e2 * z.np * z.nk);
+  c->h0k = z.mom ? cv.template take<double2>(e2 * z.np * z.nk) : nullptr;
+  c->ppk = z.mom ? cv.template take<double2>(3 * e2 * z.np * z.nk) : nullptr;
   c->c0 = z.deviation ? cv.template take<double2>(n2) : nullptr;
   c->sinv = cv.template take<double2>(n2);
   c->dlev[0] = cv.template take<double2>(n2);
@@ -335,11 +357,11 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
 struct SizeProbe {
   struct {
     int *row_ptr, *pair_col, *pair_row, *img_ptr;
-    double *img_d, *img_h0, *img_s;
+    double *img_d, *img_h0, *img_s, *img_ds;
     int *grp_ptr, *ent_j, *ent_mask, *ent_pp, *gp_pair, *gp_il;
   } g;
   double *kpts_dev, *kw_dev, *part, *v, *z, *qbuf, *rowpart, *gamma, *hist, *eig, *eig_e, *occ;
-  double2 *spk, *hq, *c0, *sinv, *dlev[2], *d0, *w, *y;
+  double2 *spk, *hq, *h0k, *ppk, *c0, *sinv, *dlev[2], *d0, *w, *y;
   int *info, *flag;
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
@@ -366,7 +388,8 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.deviation = o->precision != VGTB_FP64;
   z.precision = o->precision;
   z.npad = (z.n + 63) / 64 * 64;
-  z.small = small_path_enabled() && !z.deviation && !z.scc && z.n <= vgtb::kSmallN &&
+  z.mom = o->coupling == VGTB_COUPLING_MOMENTUM;
+  z.small = small_path_enabled() && !z.deviation && !z.scc && !z.mom && z.n <= vgtb::kSmallN &&
             z.ni <= vgtb::kSmallImages;
   return z;
 }
@@ -416,7 +439,7 @@ void drop_graphs(vgtb_ctx *c);
 void prepare_reference(vgtb_ctx *c, bool with_m0) {
   drop_graphs(c);   // captured updates name m0 (or not)
   const vgtb::StepSource zero{nullptr, nullptr};
-  vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, zero, c->spk, nullptr, c->hq, c->stream);
+  vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, zero, c->spk, nullptr, c->hq, c->h0k, c->ppk, c->stream);
   vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
                     c->spmm_variant, c->stream);
   c->m0_active = with_m0;
@@ -463,13 +486,16 @@ void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
     if (may_time) timed(c, id, launch);
     else launch();
   };
-  run(VGTB_K_OBSERVE, [&] { vgtb::launch_observe(c->g, dcur, n, c->kpts_dev, nk, src, c->spk, c->part, s); });
+  run(VGTB_K_OBSERVE, [&] {
+    vgtb::launch_observe(c->g, dcur, n, c->kpts_dev, nk, src, c->spk, c->h0k, c->ppk, c->part, s);
+  });
   run(VGTB_K_REDUCE, [&] {
     vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr, c->z,
                         c->v, c->qbuf, c->rowpart, c->hist, c->hist_cap, c->ctr, c->flag, s);
   });
   run(VGTB_K_ASSEMBLE, [&] {
-    vgtb::launch_assemble(c->g, c->kpts_dev, nk, src, c->spk, c->scc ? c->v : nullptr, c->hq, s);
+    vgtb::launch_assemble(c->g, c->kpts_dev, nk, src, c->spk, c->scc ? c->v : nullptr, c->hq, c->h0k,
+                          c->ppk, s);
   });
   if (!dev) {
     run(VGTB_K_SPMM, [&] {
@@ -627,6 +653,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.img_d = dp.g.img_d;
   c->g.img_h0 = dp.g.img_h0;
   c->g.img_s = dp.g.img_s;
+  c->g.img_ds = dp.g.img_ds;
   c->g.group_size = spmm_group_size(c->g.norb);
   c->spmm_variant = spmm_variant();
   c->g.n_groups = z.ng;
@@ -639,6 +666,8 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.gp_il = dp.g.gp_il;
   c->spk = dp.spk;
   c->hq = dp.hq;
+  c->h0k = dp.h0k;
+  c->ppk = dp.ppk;
   c->c0 = dp.c0;
   c->sinv = dp.sinv;
   c->dlev[0] = dp.dlev[0];
@@ -688,6 +717,8 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   CREATE_HIP(hipMemcpyAsync(dp.g.img_d, hg.img_d.data(), sizeof(double) * hg.img_d.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.img_h0, hg.img_h0.data(), sizeof(double) * hg.img_h0.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.img_s, hg.img_s.data(), sizeof(double) * hg.img_s.size(), hipMemcpyHostToDevice, st_));
+  if (z.mom)
+    CREATE_HIP(hipMemcpyAsync(dp.g.img_ds, hg.img_ds.data(), sizeof(double) * hg.img_ds.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.grp_ptr, hg.grp_ptr.data(), sizeof(int) * hg.grp_ptr.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.ent_j, hg.ent_j.data(), sizeof(int) * hg.ent_j.size(), hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemcpyAsync(dp.g.ent_mask, hg.ent_mask.data(), sizeof(int) * hg.ent_mask.size(), hipMemcpyHostToDevice, st_));
@@ -703,6 +734,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
 
   // S_k on the pair graph (Eq. 7), dense S_k, then S_k^-1 by Cholesky.
   vgtb::launch_pair_bloch_s(c->g, dp.kpts_dev, z.nk, dp.spk, st_);
+  if (z.mom) vgtb::launch_pair_bloch_momentum(c->g, dp.kpts_dev, z.nk, dp.h0k, dp.ppk, st_);
   const size_t n2 = (size_t)z.n * z.n * z.nk;
   vgtb::launch_fill_zero(dp.sinv, n2, st_);
   vgtb::launch_scatter_pairs(c->g, dp.kpts_dev, z.nk, dp.spk, 0, dp.sinv, z.n, st_);
@@ -802,7 +834,7 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
   if (c->z_from_ground_state) {
     // Reference charges = Mulliken charges of the ground state (dq = 0 at t = 0).
     const vgtb::StepSource zero{nullptr, nullptr};
-    vgtb::launch_observe(c->g, dtarget, n, c->kpts_dev, nk, zero, c->spk, c->part, s);
+    vgtb::launch_observe(c->g, dtarget, n, c->kpts_dev, nk, zero, c->spk, c->h0k, c->ppk, c->part, s);
     vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, 0.0, nullptr, c->z, c->v, c->qbuf,
                         c->rowpart, c->hist, c->hist_cap, nullptr, c->flag, s);
     HIP_TRY(c, hipGetLastError());
@@ -1168,7 +1200,7 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   };
   // Operands: H_k at A = 0 and the current level (only scratch buffers are written).
   vgtb::launch_assemble(c->g, c->kpts_dev, nk, vgtb::StepSource{nullptr, nullptr}, c->spk,
-                        c->scc ? c->v : nullptr, c->hq, s);
+                        c->scc ? c->v : nullptr, c->hq, c->h0k, c->ppk, s);
   const double2 *dcur = c->dlev[c->cur];
   std::vector<int> sv;
   if (c->g.norb == 4) sv = {-1, -2, -4};

@@ -60,6 +60,7 @@ struct PairGraph {
   const double *img_d = nullptr;  // n_images * 3
   const double *img_h0 = nullptr; // n_images * norb^2
   const double *img_s = nullptr;  // n_images * norb^2
+  const double *img_ds = nullptr; // n_images * 3 * norb^2 (momentum coupling), or null
 };
 
 // A(t_n) / c.
@@ -94,8 +95,14 @@ void launch_pair_bloch_s(const PairGraph &g, const double *kpts, int nk, double2
                          hipStream_t s);
 void launch_scatter_pairs(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
                           int which, double2 *dense, int n, hipStream_t s);
+// h0k / ppk (both null for the Peierls coupling): H0_k and P_k pair blocks of
+// the momentum coupling.
 void launch_observe(const PairGraph &g, const double2 *d, int n, const double *kpts, int nk,
-                    StepSource src, const double2 *spk, double *part, hipStream_t s);
+                    StepSource src, const double2 *spk, const double2 *h0k, const double2 *ppk,
+                    double *part, hipStream_t s);
+// h0k[k][p][e] = sum_images exp(i k.d) H0, ppk[k][p][a][e] = sum_images exp(i k.d) i dS/dd^a.
+void launch_pair_bloch_momentum(const PairGraph &g, const double *kpts, int nk, double2 *h0k,
+                                double2 *ppk, hipStream_t s);
 // ring slots of steps [step0, step0 + ns), ns <= kSmallChunk (= kStepRing).
 void launch_store_ring(const FieldChunk &f, int64_t step0, int ns, double *ring, hipStream_t s);
 void launch_set_counter(int64_t *ctr, int64_t v, hipStream_t s);
@@ -106,7 +113,8 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
                    hipStream_t s);
 // Pair blocks of H_k(t) in grouped pair order.
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource src,
-                     const double2 *spk, const double *v, double2 *hq, hipStream_t s);
+                     const double2 *spk, const double *v, double2 *hq, const double2 *h0k,
+                     const double2 *ppk, hipStream_t s);
 // W = H D (d0 == null) or W = H D - C0 (d0 != null marks the deviation form);
 // out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np)
 // + complex64 copy w32.  variant: -1, -2, -4 = FP64 matrix cores with that
@@ -189,6 +197,8 @@ struct vgtb_ctx {
   double *kpts_dev = nullptr, *kw_dev = nullptr;
   double2 *spk = nullptr;      // nk * n_pairs * norb^2
   double2 *hq = nullptr;       // nk * n_pairs * norb^2, H_k pair blocks (grouped order)
+  double2 *h0k = nullptr;      // momentum coupling: nk * n_pairs * norb^2, H0_k pair blocks
+  double2 *ppk = nullptr;      // momentum coupling: nk * n_pairs * 3 * norb^2, P_k pair blocks
   double2 *c0 = nullptr;       // nk * n * n, H0_k(A=0) D0 (deviation forms)
   double2 *sinv = nullptr;     // nk * n * n
   double2 *dlev[2] = {nullptr, nullptr};

@@ -20,6 +20,7 @@ VGTB_OK, VGTB_E_INVAL, VGTB_E_STATE, VGTB_E_NOT_PD, VGTB_E_UNSTABLE, VGTB_E_NOME
 STATUS_NAMES = {0: "VGTB_OK", 1: "VGTB_E_INVAL", 2: "VGTB_E_STATE", 3: "VGTB_E_NOT_PD",
                 4: "VGTB_E_UNSTABLE", 5: "VGTB_E_NOMEM", 6: "VGTB_E_DEVICE", 7: "VGTB_E_NONFINITE"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+COUPLINGS = {"peierls": 0, "momentum": 1}
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = [
@@ -48,14 +49,14 @@ class VgtbSystem(ctypes.Structure):
         ("blk_i", ctypes.c_void_p), ("blk_j", ctypes.c_void_p), ("blk_d", ctypes.c_void_p),
         ("blk_h0", ctypes.c_void_p), ("blk_s", ctypes.c_void_p), ("n_k", ctypes.c_int32),
         ("kpts", ctypes.c_void_p), ("kw", ctypes.c_void_p), ("n_electrons", ctypes.c_double),
-        ("z_ref", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+        ("z_ref", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("blk_ds", ctypes.c_void_p),
     ]
 
 
 class VgtbOptions(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rescale_every", ctypes.c_int32), ("history_capacity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("coupling", ctypes.c_int32)]
 
 
 class VgtbTuning(ctypes.Structure):
@@ -171,6 +172,8 @@ def make_system_struct(system):
         "kw": np.ascontiguousarray(system.kw, dtype=np.float64),
         "z_ref": None if system.z_ref is None else np.ascontiguousarray(system.z_ref, np.float64),
         "gamma": None if system.gamma is None else np.ascontiguousarray(system.gamma, np.float64),
+        "blk_ds": (None if getattr(system, "blk_ds", None) is None
+                   else np.ascontiguousarray(system.blk_ds, dtype=np.float64)),
     }
     s = VgtbSystem()
     s.n_atoms = int(system.pos.shape[0])
@@ -181,19 +184,20 @@ def make_system_struct(system):
     s.n_blocks = int(arrs["blk_i"].shape[0])
     s.n_k = int(arrs["kpts"].shape[0])
     s.n_electrons = float(system.n_electrons)
-    for name in ("blk_i", "blk_j", "blk_d", "blk_h0", "blk_s", "kpts", "kw", "z_ref", "gamma"):
+    for name in ("blk_i", "blk_j", "blk_d", "blk_h0", "blk_s", "kpts", "kw", "z_ref", "gamma",
+                 "blk_ds"):
         setattr(s, name, _ptr(arrs[name]))
     return s, arrs
 
 
 def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
-                 history_capacity: int = 1024) -> VgtbOptions:
+                 history_capacity: int = 1024, coupling: str = "peierls") -> VgtbOptions:
     o = VgtbOptions()
     o.dt = float(dt)
     o.precision = PRECISIONS[precision]
     o.rescale_every = int(rescale_every)
     o.history_capacity = int(history_capacity)
-    o.reserved = 0
+    o.coupling = COUPLINGS[coupling]
     return o
 
 
@@ -224,7 +228,7 @@ class Propagator:
     """One propagation context: device arena, stream and the C handle."""
 
     def __init__(self, system, dt: float, precision: str = "fp64", rescale_every: int = 50,
-                 history_capacity: int = 1024, device: str = "cuda:0"):
+                 history_capacity: int = 1024, device: str = "cuda:0", coupling: str = "peierls"):
         torch = _torch()
         self._torch = torch
         self.lib = load_library()
@@ -234,7 +238,7 @@ class Propagator:
         self.n = self.n_atoms * self.norb
         self.n_k = int(np.asarray(system.kpts).shape[0])
         self.precision = precision
-        self.options = make_options(dt, precision, rescale_every, history_capacity)
+        self.options = make_options(dt, precision, rescale_every, history_capacity, coupling)
         s, keep = make_system_struct(system)
         with torch.cuda.device(self.device):
             size = ctypes.c_size_t(0)
@@ -412,7 +416,7 @@ class Server:
             q = reqs[i]
             q.system = ctypes.cast(ctypes.pointer(s), ctypes.c_void_p)
             q.options = make_options(r["dt"], r.get("precision", "bf16x3"),
-                                     r.get("rescale_every", 50), 1)
+                                     r.get("rescale_every", 50), 1, r.get("coupling", "peierls"))
             q.n_steps = int(r["n_steps"])
             q.n_field = field.shape[0]
             q.field = field.ctypes.data

@@ -58,7 +58,7 @@ def test_rejects_missing_hermitian_partner():
     keep = np.ones(s.n_blocks, bool)
     keep[np.nonzero(np.linalg.norm(s.blk_d, axis=1) > 0)[0][0]] = False
     bad = dataclasses.replace(s, blk_i=s.blk_i[keep], blk_j=s.blk_j[keep], blk_d=s.blk_d[keep],
-                              blk_h0=s.blk_h0[keep], blk_s=s.blk_s[keep])
+                              blk_h0=s.blk_h0[keep], blk_s=s.blk_s[keep], blk_ds=s.blk_ds[keep])
     _expect_inval(bad, match="Hermitian partner")
 
 
@@ -98,3 +98,19 @@ def test_product_path_refuses_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         pkg.Propagator(vs.config_system("si8_k64"), 0.2)
+
+
+def test_rejects_momentum_coupling_without_gradients_and_bad_gradients():
+    _lib()
+    s = vs.config_system("si8_k64")
+    opts = pkg.make_options(0.2, coupling="momentum")
+    _expect_inval(dataclasses.replace(s, blk_ds=None), opts, match="overlap gradients")
+    g = s.blk_ds.copy()
+    b = np.nonzero(np.linalg.norm(s.blk_d, axis=1) > 0)[0][0]
+    g[b, 0, 0, 1] += 1e-3
+    _expect_inval(dataclasses.replace(s, blk_ds=g), opts, match="overlap gradient")
+    bad = pkg.make_options(0.2)
+    bad.coupling = 7
+    _expect_inval(s, bad, match="coupling")
+    # the same system is accepted with either coupling
+    assert pkg.vgtb_workspace_size(s, opts) > pkg.vgtb_workspace_size(s, pkg.make_options(0.2))
