@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 run over the same steps (speed-up and current error)")
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--coupling", default="peierls", choices=["peierls", "momentum"],
+                    help="field coupling: Peierls phase on the H0 blocks, or the momentum "
+                         "matrix of the overlap gradients (Eq. 12)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-k", type=int, default=4)
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
@@ -68,7 +71,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps):
+def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls"):
     """The FP64 oracle as it stands, on a bounded sample of the same workload."""
     import oracle
     from threadpoolctl import threadpool_info
@@ -83,7 +86,7 @@ def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps):
     z = np.full(sysm.n_atoms, 4.0)
     state = oracle.make_state(sub, d0, z)
     t0 = time.perf_counter()
-    oracle.propagate(sub, None, atab, dt, n_steps, state=state)
+    oracle.propagate(sub, None, atab, dt, n_steps, state=state, coupling=coupling)
     el = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return {
@@ -117,10 +120,12 @@ def counter_traffic(precision, workload):
     return rec.get("bytes_per_launch")
 
 
-def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload, tune=True):
+def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload, tune=True,
+             coupling="peierls"):
     """Ground state, warmup, then `steps` timed steps of one precision form."""
     total = warmup + steps
-    prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total + min(steps, 20), 1))
+    prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total + min(steps, 20), 1),
+                         coupling=coupling)
     t_init = time.perf_counter()
     gap = prop.ground_state()
     t_init = time.perf_counter() - t_init
@@ -158,7 +163,8 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
         peak = PEAK_TFLOPS[precision]
         roof = {"bound": "mfma", "kernel": f"dense S^-1 W product ({precision}, all {nk} k-points)",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": counter_traffic(precision, workload), "flops_per_launch": flops_per_launch,
+                "traffic": counter_traffic(precision, workload) if coupling == "peierls" else None,
+                "flops_per_launch": flops_per_launch,
                 "avg_launch_ms": gemm_avg_s * 1e3}
         if precision == "bf16x3":
             # three bf16 products per real product: the matrix cores execute 3x the flops
@@ -342,11 +348,11 @@ def main():
     # Warmup and timed steps sit in the middle of the pulse, where A is large.
     offset = min(2000, max(0, atab.shape[0] - total))
     head = run_form(vg, torch, sysm, atab, dt, args.precision, args.warmup, args.steps, offset,
-                    args.workload, tune=not args.no_autotune)
+                    args.workload, tune=not args.no_autotune, coupling=args.coupling)
     ref = None
     if args.precision != "fp64" and not args.no_fp64_compare:
         ref = run_form(vg, torch, sysm, atab, dt, "fp64", args.warmup, args.steps, offset,
-                       args.workload, tune=not args.no_autotune)
+                       args.workload, tune=not args.no_autotune, coupling=args.coupling)
 
     n, nk = sysm.n_orb, sysm.n_k
     out = {
@@ -366,6 +372,7 @@ def main():
         "config": {"workload": f"{args.workload}: {sysm.n_atoms}-atom a-Si, {n} orbitals, "
                                f"{nk} k-points (2x2x2), SCC, sin^2 pulse, dt={dt}",
                    "n_orb": n, "n_k": nk, "n_atoms": sysm.n_atoms, "precision": args.precision,
+                   "coupling": args.coupling,
                    "parallelism": "single GPU, all k-points batched"},
         "roofline": head["roofline"],
         "step_latency_ms": head["step_latency_ms"],
@@ -384,7 +391,8 @@ def main():
         out["j_err_vs_fp64"] = float(np.abs(jm - jr).max() / np.abs(jr).max())
         out["j_err_steps"] = total
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysm, atab[offset:], dt, args.cpu_sample_k, args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(sysm, atab[offset:], dt, args.cpu_sample_k, args.cpu_sample_steps,
+                                           args.coupling)
     print(json.dumps(out), flush=True)
     return 0
 
