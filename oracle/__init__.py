@@ -14,7 +14,10 @@ matrix-exponential propagation, invariants, the gauge identity, textbook sp3
 and single-orbital-chain models, SCC special cases, spectrum closed forms; for
 the momentum-matrix coupling of Eq. 12: Hermiticity, the closed-form
 diamagnetic current, the |A|^2 term as a pure phase, the orthogonal-basis limit,
-energy conservation at constant A and brute-force propagation).
+energy conservation at constant A and brute-force propagation; for the
+Crank-Nicolson propagation of the coefficients (Eq. 5): the closed-form
+Cayley-transform solution, exact S-unitarity, stationarity of the ground state
+and second-order convergence towards independent fine-step integrators).
 """
 from .tddftb import (  # noqa: F401
     C_LIGHT,
@@ -38,5 +41,13 @@ from .tddftb import (  # noqa: F401
     propagate,
     OracleState,
     make_state,
+)
+from .coefficients import (  # noqa: F401
+    density_from_coefficients,
+    ground_state_coefficients,
+    propagate_crank_nicolson,
+    crank_nicolson_step,
+    CoefficientState,
+    make_coefficient_state,
 )
 from .spectrum import conductivity, dielectric, absorption  # noqa: F401
