@@ -112,6 +112,20 @@ typedef struct {
  */
 typedef enum { VGTB_COUPLING_PEIERLS = 0, VGTB_COUPLING_MOMENTUM = 1 } vgtb_coupling;
 
+/*
+ * What is propagated (Section 2, Eqs. 5, 6 and 13):
+ *   LEAPFROG:       the density matrices D_k by leapfrog on Eq. 6 (Eq. 13).
+ *   CRANK_NICOLSON: the coefficient vectors C_nk of Eq. 5 by the unitary
+ *                   Crank-Nicolson scheme the paper names beside it,
+ *                   (S + i dt/2 H) C(t + dt) = (S - i dt/2 H) C(t), with H at
+ *                   the midpoint: A = (A(t_n) + A(t_{n+1}))/2 and the SCC
+ *                   shift extrapolated as (3 V_n - V_{n-1})/2.  The density
+ *                   D_k = sum_n f_n C_nk C_nk^dag is formed on the pair
+ *                   pattern for the observables.  FP64 only; the state is set
+ *                   by vgtb_ground_state or vgtb_set_coefficients.
+ */
+typedef enum { VGTB_PROP_LEAPFROG = 0, VGTB_PROP_CRANK_NICOLSON = 1 } vgtb_propagator;
+
 typedef struct {
   double dt;                   /* time step (atomic time units), finite, nonzero */
   int32_t precision;           /* vgtb_precision                                 */
@@ -119,6 +133,7 @@ typedef struct {
                                   trace every this many steps (0 = never)        */
   int32_t history_capacity;    /* observables ring length in steps (>= 1)        */
   int32_t coupling;            /* vgtb_coupling                                  */
+  int32_t propagator;          /* vgtb_propagator                                */
 } vgtb_options;
 
 /* Bytes of device arena vgtb_create needs for this system and options. */
@@ -156,6 +171,27 @@ vgtb_status vgtb_ground_state(vgtb_ctx *ctx, double *min_gap_host);
  */
 vgtb_status vgtb_set_density(vgtb_ctx *ctx, const void *d, int on_device);
 
+/*
+ * Crank-Nicolson contexts only (VGTB_E_STATE otherwise).  Set the state to
+ * n_states coefficient vectors per k: c is n_k * N * n_states complex128,
+ * element (k, i, s) at offset (k * N + i) * n_states + s (on_device != 0:
+ * device pointer read on the context stream; else host); occ_host holds the
+ * n_k * n_states occupations f_s (finite, >= 0).  1 <= n_states <= N.  Resets
+ * the step index to 0.  vgtb_ground_state sets the occupied ground-state
+ * vectors instead (n_states = the largest occupied count over k; a k-point
+ * with fewer occupied states carries its next states with f = 0).
+ */
+vgtb_status vgtb_set_coefficients(vgtb_ctx *ctx, const void *c, const double *occ_host,
+                                  int32_t n_states, int on_device);
+
+/* Number of coefficient vectors per k of a Crank-Nicolson context (0 before a
+ * state is set, -1 for a null or leapfrog context). */
+int32_t vgtb_num_states(const vgtb_ctx *ctx);
+
+/* Copy the current coefficients (layout as in vgtb_set_coefficients, device
+ * or host) and, if occ_host is not NULL, the occupations.  Synchronises. */
+vgtb_status vgtb_get_coefficients(vgtb_ctx *ctx, void *c_out, double *occ_host, int on_device);
+
 /* A(t_n) for n = 0 .. n-1 (host, n * 3 doubles, atomic units).  Steps past
  * the table's end use its last entry. */
 vgtb_status vgtb_set_field_table(vgtb_ctx *ctx, int64_t n, const double *a_host);
@@ -169,7 +205,8 @@ vgtb_status vgtb_set_field(vgtb_ctx *ctx, const double a_host[3]);
  * observables of D_n in the history ring, then forms D_{n+1} (the first
  * step after a density is set is a forward Euler step).  Deviation forms
  * re-Hermitise and rescale the trace of both levels after every
- * rescale_every-th step.
+ * rescale_every-th step.  A Crank-Nicolson context records the observables of
+ * C_n with A(t_n), then solves for C_{n+1} (vgtb_propagator).
  */
 vgtb_status vgtb_step(vgtb_ctx *ctx, int64_t n_steps);
 
@@ -187,14 +224,16 @@ vgtb_status vgtb_read_observables(vgtb_ctx *ctx, int64_t first, int64_t count, d
                                   double *e_host, double *trace_host, double *q_host);
 
 /* Copy D at level 0 (= D_n, current) or 1 (= D_{n-1}) to out (device or
- * host), n_k * N * N complex128.  Synchronises the stream. */
+ * host), n_k * N * N complex128.  Synchronises the stream.  A Crank-Nicolson
+ * context has level 0 only: D = sum_s f_s C_s C_s^dag, formed on the device. */
 vgtb_status vgtb_get_density(vgtb_ctx *ctx, int32_t level, void *out, int on_device);
 
 /* Reference charges Z in use (host, n_atoms doubles). */
 vgtb_status vgtb_get_reference_charges(vgtb_ctx *ctx, double *z_host);
 
 /* Checkpoint: bytes needed, save both leapfrog levels, the reference density
- * and the step index to host memory, and restore them.  Resuming continues
+ * and the step index to host memory, and restore them (Crank-Nicolson: the
+ * coefficients, occupations and previous SCC shift).  Resuming continues
  * bit-identically to an uninterrupted run. */
 vgtb_status vgtb_state_size(const vgtb_ctx *ctx, size_t *bytes);
 vgtb_status vgtb_save_state(vgtb_ctx *ctx, void *host_buf, size_t bytes);
@@ -281,7 +320,11 @@ typedef enum {
   VGTB_K_SMALL = 7,     /* small N, FP64, no SCC: up to 64 whole steps in one
                            launch (the other classes then stay at zero except
                            REDUCE, which is the per-block history reduction)  */
-  VGTB_K_COUNT = 8
+  VGTB_K_CN_PATTERN = 8, /* Crank-Nicolson: D = sum f C C^dag on the pair pattern */
+  VGTB_K_CN_SOLVE = 9,  /* Crank-Nicolson: right-hand side S C, [A | S C] build and
+                           block elimination (diagonal-block inverses + GEMMs)  */
+  VGTB_K_CN_BACK = 10,  /* Crank-Nicolson: back substitution and C update      */
+  VGTB_K_COUNT = 11
 } vgtb_kernel;
 
 /*

@@ -249,6 +249,14 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
     msg = "unknown coupling";
     return VGTB_E_INVAL;
   }
+  if (o->propagator != VGTB_PROP_LEAPFROG && o->propagator != VGTB_PROP_CRANK_NICOLSON) {
+    msg = "unknown propagator";
+    return VGTB_E_INVAL;
+  }
+  if (o->propagator == VGTB_PROP_CRANK_NICOLSON && o->precision != VGTB_FP64) {
+    msg = "the Crank-Nicolson propagator is FP64 only";
+    return VGTB_E_INVAL;
+  }
   if (o->coupling == VGTB_COUPLING_MOMENTUM && !s->blk_ds) {
     msg = "the momentum coupling needs the overlap gradients blk_ds";
     return VGTB_E_INVAL;
@@ -285,7 +293,7 @@ struct Carver {
 
 struct Sizes {
   int na, no, n, nk, np, ni, cap, precision, npad, ng, ne;
-  bool scc, deviation, small, mom;
+  bool scc, deviation, small, mom, cn;
 };
 
 template <typename Ctx>
@@ -351,6 +359,18 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->sm_part = z.small ? cv.template take<double>((size_t)vgtb::kSmallChunk * z.nk * z.na * 5) : nullptr;
   c->ring = cv.template take<double>(3 * (size_t)vgtb::kStepRing);
   c->ctr = cv.template take<int64_t>(1);
+  if (z.cn) {
+    c->aug = cv.template take<double2>(2 * n2);
+    c->cinv = cv.template take<double2>((size_t)vgtb::kCnBlock * vgtb::kCnBlock * z.nk);
+    c->sq = cv.template take<double2>(e2 * z.np * z.nk);
+    c->cocc = cv.template take<double>((size_t)z.nk * z.n);
+    c->vprev = cv.template take<double>(z.na);
+    c->vmid = cv.template take<double>(z.na);
+    c->ring_mid = cv.template take<double>(3 * (size_t)vgtb::kStepRing);
+  } else {
+    c->aug = c->cinv = c->sq = nullptr;
+    c->cocc = c->vprev = c->vmid = c->ring_mid = nullptr;
+  }
 }
 
 // Mutable stand-in used for the size query (PairGraph members are const).
@@ -369,6 +389,8 @@ struct SizeProbe {
   double2 *m0;
   double *sm_part, *ring;
   int64_t *ctr;
+  double2 *aug, *cinv, *sq;
+  double *cocc, *vprev, *vmid, *ring_mid;
 };
 
 struct DevPtrs : SizeProbe {};
@@ -389,7 +411,8 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.precision = o->precision;
   z.npad = (z.n + 63) / 64 * 64;
   z.mom = o->coupling == VGTB_COUPLING_MOMENTUM;
-  z.small = small_path_enabled() && !z.deviation && !z.scc && !z.mom && z.n <= vgtb::kSmallN &&
+  z.cn = o->propagator == VGTB_PROP_CRANK_NICOLSON;
+  z.small = small_path_enabled() && !z.deviation && !z.scc && !z.mom && !z.cn && z.n <= vgtb::kSmallN &&
             z.ni <= vgtb::kSmallImages;
   return z;
 }
@@ -468,7 +491,52 @@ void fill_ring(vgtb_ctx *c, int64_t stp, int need) {
     for (int x = 0; x < 3; ++x) fc.a[3 * i + x] = a[x] / vgtb::kLightSpeed;
   }
   vgtb::launch_store_ring(fc, stp, vgtb::kStepRing, c->ring, c->stream);
+  if (c->cn) {
+    // Crank-Nicolson: the field of the step's midpoint, (A(t_n) + A(t_{n+1})) / 2.
+    for (int i = 0; i < vgtb::kStepRing; ++i) {
+      const double *a = c->field.data() + 3 * std::min<int64_t>(stp + i, nf - 1);
+      const double *b = c->field.data() + 3 * std::min<int64_t>(stp + i + 1, nf - 1);
+      for (int x = 0; x < 3; ++x) fc.a[3 * i + x] = 0.5 * (a[x] + b[x]) / vgtb::kLightSpeed;
+    }
+    vgtb::launch_store_ring(fc, stp, vgtb::kStepRing, c->ring_mid, c->stream);
+  }
   c->ring_lo = stp;
+}
+
+// One Crank-Nicolson step of the coefficients (Eq. 5): observables of C_n,
+// SCC shift, H at the midpoint, W = S C_n, the solve of
+// (S + i dt/2 H) X = W, and C_{n+1} = 2 X - C_n.
+void enqueue_step_cn(vgtb_ctx *c, hipStream_t s) {
+  const int n = c->n, nk = c->nk, ns = c->ns;
+  const double jscale = -1.0 / (c->volume * nk);
+  const vgtb::StepSource src{c->ring, c->ctr}, mid{c->ring_mid, c->ctr};
+  double2 *cc = c->dlev[0];
+  double2 *dp = c->dlev[1];
+  timed(c, VGTB_K_CN_PATTERN, [&] { vgtb::launch_cn_pattern(c->g, cc, c->cocc, n, ns, nk, dp, s); });
+  timed(c, VGTB_K_OBSERVE, [&] {
+    vgtb::launch_observe(c->g, dp, n, c->kpts_dev, nk, src, c->spk, c->h0k, c->ppk, c->part, s);
+  });
+  timed(c, VGTB_K_REDUCE, [&] {
+    vgtb::launch_reduce(c->part, nk, c->na, c->kw_dev, jscale, c->scc ? c->gamma : nullptr, c->z,
+                        c->v, c->qbuf, c->rowpart, c->hist, c->hist_cap, c->ctr, c->flag, s);
+    if (c->scc) vgtb::launch_cn_vmid(c->v, c->vprev, c->vmid, c->na, !c->have_vprev, s);
+  });
+  c->have_vprev = true;
+  timed(c, VGTB_K_ASSEMBLE, [&] {
+    vgtb::launch_assemble(c->g, c->kpts_dev, nk, mid, c->spk, c->scc ? c->vmid : nullptr, c->hq,
+                          c->h0k, c->ppk, s);
+  });
+  timed(c, VGTB_K_SPMM, [&] {
+    vgtb::launch_spmm(c->g, cc, nullptr, n, nk, c->sq, nullptr, c->w, 0, 0, nullptr, c->spmm_variant, s);
+  });
+  timed(c, VGTB_K_CN_SOLVE, [&] {
+    vgtb::launch_cn_build(c->g, c->w, c->hq, c->spk, 0.5 * c->dt, n, ns, nk, c->aug, s);
+    vgtb::launch_cn_eliminate(c->aug, c->cinv, n, ns, nk, s);
+  });
+  timed(c, VGTB_K_CN_BACK, [&] {
+    vgtb::launch_cn_back(c->aug, n, ns, nk, s);
+    vgtb::launch_cn_update(c->aug, cc, n, ns, nk, c->ctr, s);
+  });
 }
 
 // The launches of one step at the current parity, on stream s.  With
@@ -700,7 +768,15 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->ring = dp.ring;
   c->ctr = dp.ctr;
   c->small_path = z.small;
-  c->use_graphs = graphs_enabled();
+  c->use_graphs = graphs_enabled() && !z.cn;
+  c->cn = z.cn;
+  c->aug = dp.aug;
+  c->cinv = dp.cinv;
+  c->sq = dp.sq;
+  c->cocc = dp.cocc;
+  c->vprev = dp.vprev;
+  c->vmid = dp.vmid;
+  c->ring_mid = dp.ring_mid;
 
   hipStream_t st_ = c->stream;
 #define CREATE_HIP(expr)                                                              \
@@ -735,6 +811,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   // S_k on the pair graph (Eq. 7), dense S_k, then S_k^-1 by Cholesky.
   vgtb::launch_pair_bloch_s(c->g, dp.kpts_dev, z.nk, dp.spk, st_);
   if (z.mom) vgtb::launch_pair_bloch_momentum(c->g, dp.kpts_dev, z.nk, dp.h0k, dp.ppk, st_);
+  if (z.cn) vgtb::launch_cn_permute_pairs(c->g, dp.spk, dp.sq, z.nk, st_);
   const size_t n2 = (size_t)z.n * z.n * z.nk;
   vgtb::launch_fill_zero(dp.sinv, n2, st_);
   vgtb::launch_scatter_pairs(c->g, dp.kpts_dev, z.nk, dp.spk, 0, dp.sinv, z.n, st_);
@@ -818,8 +895,21 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
     width = std::max(width, e[n - 1] - e[0]);
   }
   HIP_TRY(c, hipMemcpyAsync(c->occ, occ.data(), sizeof(double) * occ.size(), hipMemcpyHostToDevice, s));
-  double2 *dtarget = c->dlev[0];
+  double2 *dtarget = c->dlev[c->cn ? 1 : 0];
   vgtb::launch_density_from_vectors(c->y, c->occ, dtarget, n, nk, s);
+  if (c->cn) {
+    // Coefficients: the occupied vectors (the largest occupied count over k).
+    int ns = 1;
+    for (int k = 0; k < nk; ++k) {
+      int cnt = 0;
+      for (int t = 0; t < n; ++t) cnt += occ[(size_t)k * n + t] > 0.0 ? 1 : 0;
+      ns = std::max(ns, cnt);
+    }
+    vgtb::launch_cn_from_vectors(c->y, c->dlev[0], n, ns, nk, s);
+    HIP_TRY(c, hipMemcpyAsync(c->cocc, c->occ, sizeof(double) * occ.size(), hipMemcpyDeviceToDevice, s));
+    c->ns = ns;
+    c->have_vprev = false;
+  }
   HIP_TRY(c, hipGetLastError());
   c->cur = 0;
   if (c->precision != VGTB_FP64) {
@@ -852,6 +942,7 @@ vgtb_status vgtb_ground_state(vgtb_ctx *c, double *min_gap) {
 vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
   vgtb_status st = check_ready(c);
   if (st != VGTB_OK) return st;
+  if (c->cn) return fail(c, VGTB_E_STATE, "a Crank-Nicolson context holds coefficients: use vgtb_set_coefficients");
   if (!d) return fail(c, VGTB_E_INVAL, "null density");
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   HIP_TRY(c, hipMemcpyAsync(c->dlev[0], d, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
@@ -869,6 +960,61 @@ vgtb_status vgtb_set_density(vgtb_ctx *c, const void *d, int on_device) {
   c->have_density = true;
   c->have_prev = false;
   c->step = 0;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_set_coefficients(vgtb_ctx *c, const void *cf, const double *occ, int32_t ns,
+                                  int on_device) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (!c->cn) return fail(c, VGTB_E_STATE, "coefficients need a Crank-Nicolson context");
+  if (!cf || !occ) return fail(c, VGTB_E_INVAL, "null coefficients or occupations");
+  if (ns < 1 || ns > c->n) return fail(c, VGTB_E_INVAL, "n_states must be in 1 .. N");
+  const int n = c->n, nk = c->nk;
+  std::vector<double> f((size_t)nk * n, 0.0);
+  for (int k = 0; k < nk; ++k)
+    for (int t = 0; t < ns; ++t) {
+      const double v = occ[(size_t)k * ns + t];
+      if (!std::isfinite(v) || v < 0.0) return fail(c, VGTB_E_INVAL, "occupations must be finite and >= 0");
+      f[(size_t)k * n + t] = v;
+    }
+  hipStream_t s = c->stream;
+  // Columns past n_states stay zero: the sparse product reads every column.
+  vgtb::launch_fill_zero(c->dlev[0], (size_t)n * n * nk, s);
+  HIP_TRY(c, hipMemcpy2DAsync(c->dlev[0], sizeof(double2) * n, cf, sizeof(double2) * ns,
+                              sizeof(double2) * ns, (size_t)n * nk,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->cocc, f.data(), sizeof(double) * f.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->ns = ns;
+  c->cur = 0;
+  c->have_density = true;
+  c->have_prev = false;
+  c->have_vprev = false;
+  c->step = 0;
+  return VGTB_OK;
+}
+
+int32_t vgtb_num_states(const vgtb_ctx *c) { return (c && c->cn) ? c->ns : -1; }
+
+vgtb_status vgtb_get_coefficients(vgtb_ctx *c, void *out, double *occ, int on_device) {
+  vgtb_status st = check_ready(c);
+  if (st != VGTB_OK) return st;
+  if (!c->cn) return fail(c, VGTB_E_STATE, "coefficients need a Crank-Nicolson context");
+  if (!c->have_density) return fail(c, VGTB_E_STATE, "no coefficients set");
+  if (!out) return fail(c, VGTB_E_INVAL, "null output");
+  const int n = c->n, nk = c->nk, ns = c->ns;
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipMemcpy2DAsync(out, sizeof(double2) * ns, c->dlev[0], sizeof(double2) * n,
+                              sizeof(double2) * ns, (size_t)n * nk,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  std::vector<double> f((size_t)nk * n);
+  HIP_TRY(c, hipMemcpyAsync(f.data(), c->cocc, sizeof(double) * f.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (occ)
+    for (int k = 0; k < nk; ++k)
+      for (int t = 0; t < ns; ++t) occ[(size_t)k * ns + t] = f[(size_t)k * n + t];
   return VGTB_OK;
 }
 
@@ -916,6 +1062,20 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
       c->have_prev = true;
       c->step += ns;
       done += ns;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return VGTB_OK;
+  }
+  if (c->cn) {
+    if (c->ctr_step != c->step) {
+      vgtb::launch_set_counter(c->ctr, c->step, s);
+      c->ctr_step = c->step;
+    }
+    for (int64_t it = 0; it < n_steps; ++it) {
+      fill_ring(c, c->step, 1);
+      enqueue_step_cn(c, s);
+      c->step += 1;
+      c->ctr_step += 1;
     }
     HIP_TRY(c, hipGetLastError());
     return VGTB_OK;
@@ -997,9 +1157,19 @@ vgtb_status vgtb_get_density(vgtb_ctx *c, int32_t level, void *out, int on_devic
   if (st != VGTB_OK) return st;
   if (!c->have_density) return fail(c, VGTB_E_STATE, "no density set");
   if (level != 0 && level != 1) return fail(c, VGTB_E_INVAL, "level must be 0 or 1");
-  if (level == 1 && !c->have_prev) return fail(c, VGTB_E_STATE, "no previous level yet");
+  if (level == 1 && (c->cn || !c->have_prev)) return fail(c, VGTB_E_STATE, "no previous level");
   if (!out) return fail(c, VGTB_E_INVAL, "null output");
   const size_t bytes = sizeof(double2) * (size_t)c->n * c->n * c->nk;
+  if (c->cn) {
+    // D = sum_s f_s C_s C_s^dag through the eigenvector-layout density kernel.
+    vgtb::launch_cn_to_vectors(c->dlev[0], c->y, c->n, c->ns, c->nk, c->stream);
+    double2 *dst = on_device ? static_cast<double2 *>(out) : c->w;
+    vgtb::launch_density_from_vectors(c->y, c->cocc, dst, c->n, c->nk, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    if (!on_device) HIP_TRY(c, hipMemcpyAsync(out, c->w, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return VGTB_OK;
+  }
   const double2 *src = c->dlev[level == 0 ? c->cur : (c->cur ^ 1)];
   HIP_TRY(c, hipMemcpyAsync(out, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1023,10 +1193,16 @@ struct StateHeader {
 constexpr uint64_t kStateMagic = 0x7667746273743031ull;
 }  // namespace
 
+// Crank-Nicolson layout: header (have_prev = V_{n-1} set, pad = n_states),
+// coefficients (the full nk * N * N buffer), occupations (nk * N), V_{n-1},
+// Z.  Leapfrog: header, both levels, reference density, Z.
 vgtb_status vgtb_state_size(const vgtb_ctx *c, size_t *bytes) {
   if (!c || !bytes) return fail(nullptr, VGTB_E_INVAL, "null argument");
   const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
-  *bytes = sizeof(StateHeader) + 3 * n2 + sizeof(double) * c->na;
+  if (c->cn)
+    *bytes = sizeof(StateHeader) + n2 + sizeof(double) * ((size_t)c->nk * c->n + 2 * (size_t)c->na);
+  else
+    *bytes = sizeof(StateHeader) + 3 * n2 + sizeof(double) * c->na;
   return VGTB_OK;
 }
 
@@ -1039,6 +1215,19 @@ vgtb_status vgtb_save_state(vgtb_ctx *c, void *buf, size_t bytes) {
   if (!c->have_density) return fail(c, VGTB_E_STATE, "no density set");
   const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   char *p = static_cast<char *>(buf);
+  if (c->cn) {
+    StateHeader h{kStateMagic + 1, c->step, c->n, c->nk, c->na, c->precision, c->have_vprev ? 1 : 0, c->ns};
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    const size_t fo = sizeof(double) * (size_t)c->nk * c->n;
+    HIP_TRY(c, hipMemcpyAsync(p, c->dlev[0], n2, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(p + n2, c->cocc, fo, hipMemcpyDeviceToHost, c->stream));
+    if (c->scc) HIP_TRY(c, hipMemcpyAsync(p + n2 + fo, c->vprev, sizeof(double) * c->na, hipMemcpyDeviceToHost, c->stream));
+    else std::memset(p + n2 + fo, 0, sizeof(double) * c->na);
+    std::memcpy(p + n2 + fo + sizeof(double) * c->na, c->z_host.data(), sizeof(double) * c->na);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return VGTB_OK;
+  }
   StateHeader h{kStateMagic, c->step, c->n, c->nk, c->na, c->precision, c->have_prev ? 1 : 0,
                 c->m0_active ? 1 : 0};
   std::memcpy(p, &h, sizeof(h));
@@ -1060,10 +1249,27 @@ vgtb_status vgtb_load_state(vgtb_ctx *c, const void *buf, size_t bytes) {
   if (!buf || bytes < need) return fail(c, VGTB_E_INVAL, "state buffer too small");
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != kStateMagic || h.n != c->n || h.nk != c->nk || h.na != c->na || h.precision != c->precision)
+  if (h.magic != kStateMagic + (c->cn ? 1 : 0) || h.n != c->n || h.nk != c->nk || h.na != c->na ||
+      h.precision != c->precision)
     return fail(c, VGTB_E_INVAL, "state does not match this context");
   const size_t n2 = sizeof(double2) * (size_t)c->n * c->n * c->nk;
   const char *p = static_cast<const char *>(buf) + sizeof(h);
+  if (c->cn) {
+    if (h.pad < 1 || h.pad > c->n) return fail(c, VGTB_E_INVAL, "state does not match this context");
+    const size_t fo = sizeof(double) * (size_t)c->nk * c->n;
+    HIP_TRY(c, hipMemcpyAsync(c->dlev[0], p, n2, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->cocc, p + n2, fo, hipMemcpyHostToDevice, c->stream));
+    if (c->scc) HIP_TRY(c, hipMemcpyAsync(c->vprev, p + n2 + fo, sizeof(double) * c->na, hipMemcpyHostToDevice, c->stream));
+    std::memcpy(c->z_host.data(), p + n2 + fo + sizeof(double) * c->na, sizeof(double) * c->na);
+    HIP_TRY(c, hipMemcpyAsync(c->z, c->z_host.data(), sizeof(double) * c->na, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->step = h.step;
+    c->ns = h.pad;
+    c->have_vprev = h.have_prev != 0;
+    c->have_density = true;
+    c->have_prev = false;
+    return VGTB_OK;
+  }
   c->cur = 0;
   HIP_TRY(c, hipMemcpyAsync(c->dlev[0], p, n2, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->dlev[1], p + n2, n2, hipMemcpyHostToDevice, c->stream));
@@ -1176,7 +1382,7 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   vgtb_tuning t{};
   t.spmm_variant = c->spmm_variant;
   t.gemm_tile = c->gemm_tile;
-  if (c->small_path) {   // neither kernel runs on this path
+  if (c->small_path || c->cn) {   // no tuned variant on these paths
     if (out) *out = t;
     return VGTB_OK;
   }

@@ -158,6 +158,31 @@ void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s);
 void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
                                  int nk, hipStream_t s);
 
+// ---- launchers (crank_nicolson.hip) -----------------------------------------
+// Coefficients C (nk * n * n, columns s < ns used), augmented [A | R] (nk * n * 2n),
+// diagonal-block inverses inv (nk * kCnBlock^2).
+constexpr int kCnBlock = 64;
+void launch_cn_permute_pairs(const PairGraph &g, const double2 *spk, double2 *sq, int nk,
+                             hipStream_t s);
+void launch_cn_pattern(const PairGraph &g, const double2 *c, const double *occ, int n, int ns,
+                       int nk, double2 *d, hipStream_t s);
+void launch_cn_vmid(const double *v, double *vprev, double *vmid, int na, bool first,
+                    hipStream_t s);
+// [A | R]: A = S + i tau H on the pair pattern (zero elsewhere), R = W[:, :ns].
+void launch_cn_build(const PairGraph &g, const double2 *w, const double2 *hq, const double2 *spk,
+                     double tau, int n, int ns, int nk, double2 *aug, hipStream_t s);
+void launch_cn_eliminate(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s);
+void launch_cn_back(double2 *aug, int n, int ns, int nk, hipStream_t s);
+// C = 2 X - C with X the R columns; ctr (may be null) advanced by one.
+void launch_cn_update(const double2 *aug, double2 *c, int n, int ns, int nk, int64_t *ctr,
+                      hipStream_t s);
+void launch_cn_from_vectors(const double2 *evec, double2 *c, int n, int ns, int nk, hipStream_t s);
+void launch_cn_to_vectors(const double2 *c, double2 *evec, int n, int ns, int nk, hipStream_t s);
+// C = beta C + alpha A B (M x K by K x N, row-major, per-batch strides).
+void launch_zgemm_strided(const double2 *a, int lda, size_t sa, const double2 *b, int ldb,
+                          size_t sb, double2 *c, int ldc, size_t sc, int m, int n, int k,
+                          double alpha, bool beta_one, int batch, hipStream_t s);
+
 // ---- launchers (gemm_mfma.hip, gemm_bf16x3.hip) ------------------------------
 // tile: workgroup tile shape (0 = the size rule; see the definitions).
 void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int batch,
@@ -231,6 +256,17 @@ struct vgtb_ctx {
   int64_t *ctr = nullptr;      // device step counter
   double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density
   bool m0_active = false;
+  // Crank-Nicolson propagation of the coefficients (C in dlev[0], the sampled
+  // density in dlev[1], S C in w)
+  bool cn = false;
+  int ns = 0;                  // coefficient vectors per k
+  bool have_vprev = false;     // V_{n-1} of the SCC extrapolation is set
+  double2 *aug = nullptr;      // nk * n * 2n, [S + i tau H | S C] and the solve
+  double2 *cinv = nullptr;     // nk * kCnBlock^2, diagonal-block inverses
+  double2 *sq = nullptr;       // nk * n_pairs * norb^2, S_k pair blocks (grouped order)
+  double *cocc = nullptr;      // nk * n, occupations of the coefficient vectors
+  double *vprev = nullptr, *vmid = nullptr;   // na each
+  double *ring_mid = nullptr;  // kStepRing * 3, midpoint A/c of the steps in flight
 
   // per-kernel event timing (vgtb_profile_*)
   struct EvPair { int id; hipEvent_t a, b; };

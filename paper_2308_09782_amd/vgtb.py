@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "VGTB_OK", 1: "VGTB_E_INVAL", 2: "VGTB_E_STATE", 3: "VGTB_E_N
                 4: "VGTB_E_UNSTABLE", 5: "VGTB_E_NOMEM", 6: "VGTB_E_DEVICE", 7: "VGTB_E_NONFINITE"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 COUPLINGS = {"peierls": 0, "momentum": 1}
+PROPAGATORS = {"leapfrog": 0, "crank_nicolson": 1}
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = [
@@ -30,10 +31,10 @@ EXPORTED = [
     "vgtb_state_size", "vgtb_save_state", "vgtb_load_state", "vgtb_step_index",
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
     "vgtb_spectrum", "vgtb_autotune", "vgtb_server_create", "vgtb_server_run",
-    "vgtb_server_destroy",
+    "vgtb_server_destroy", "vgtb_set_coefficients", "vgtb_num_states", "vgtb_get_coefficients",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
-           "assemble": 6, "small": 7}
+           "assemble": 6, "small": 7, "cn_pattern": 8, "cn_solve": 9, "cn_back": 10}
 
 
 class VgtbError(RuntimeError):
@@ -56,7 +57,7 @@ class VgtbSystem(ctypes.Structure):
 class VgtbOptions(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rescale_every", ctypes.c_int32), ("history_capacity", ctypes.c_int32),
-                ("coupling", ctypes.c_int32)]
+                ("coupling", ctypes.c_int32), ("propagator", ctypes.c_int32)]
 
 
 class VgtbTuning(ctypes.Structure):
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_spectrum": [vp, i64, vp, ctypes.c_double, i64, vp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, vp, vp],
         "vgtb_autotune": [vp, i32, ctypes.POINTER(VgtbTuning)],
+        "vgtb_set_coefficients": [vp, vp, vp, i32, ctypes.c_int],
+        "vgtb_get_coefficients": [vp, vp, vp, ctypes.c_int],
         "vgtb_server_create": [vp, sz, i32, ctypes.POINTER(vp)],
         "vgtb_server_run": [vp, i32, ctypes.POINTER(VgtbRequest), ctypes.POINTER(VgtbRequestStats),
                             ctypes.POINTER(VgtbServerStats)],
@@ -130,6 +133,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     lib.vgtb_step_index.argtypes = [vp]
     lib.vgtb_step_index.restype = i64
+    lib.vgtb_num_states.argtypes = [vp]
+    lib.vgtb_num_states.restype = i32
     lib.vgtb_last_error.argtypes = [vp]
     lib.vgtb_last_error.restype = ctypes.c_char_p
     lib.vgtb_destroy.argtypes = [vp]
@@ -191,13 +196,15 @@ def make_system_struct(system):
 
 
 def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
-                 history_capacity: int = 1024, coupling: str = "peierls") -> VgtbOptions:
+                 history_capacity: int = 1024, coupling: str = "peierls",
+                 propagator: str = "leapfrog") -> VgtbOptions:
     o = VgtbOptions()
     o.dt = float(dt)
     o.precision = PRECISIONS[precision]
     o.rescale_every = int(rescale_every)
     o.history_capacity = int(history_capacity)
     o.coupling = COUPLINGS[coupling]
+    o.propagator = PROPAGATORS[propagator]
     return o
 
 
@@ -228,7 +235,8 @@ class Propagator:
     """One propagation context: device arena, stream and the C handle."""
 
     def __init__(self, system, dt: float, precision: str = "fp64", rescale_every: int = 50,
-                 history_capacity: int = 1024, device: str = "cuda:0", coupling: str = "peierls"):
+                 history_capacity: int = 1024, device: str = "cuda:0", coupling: str = "peierls",
+                 propagator: str = "leapfrog"):
         torch = _torch()
         self._torch = torch
         self.lib = load_library()
@@ -238,7 +246,8 @@ class Propagator:
         self.n = self.n_atoms * self.norb
         self.n_k = int(np.asarray(system.kpts).shape[0])
         self.precision = precision
-        self.options = make_options(dt, precision, rescale_every, history_capacity, coupling)
+        self.options = make_options(dt, precision, rescale_every, history_capacity, coupling,
+                                    propagator)
         s, keep = make_system_struct(system)
         with torch.cuda.device(self.device):
             size = ctypes.c_size_t(0)
@@ -288,6 +297,35 @@ class Propagator:
             a = np.ascontiguousarray(d, dtype=np.complex128)
             self._check_shape(a.shape)
             _check(self.lib.vgtb_set_density(self.ctx, a.ctypes.data, 0), self.ctx)
+
+    def set_coefficients(self, c, occ):
+        """Crank-Nicolson contexts: n_k x N x n_states coefficients and n_k x n_states occupations."""
+        torch = self._torch
+        occ = np.ascontiguousarray(occ, dtype=np.float64)
+        if isinstance(c, torch.Tensor):
+            t = c.to(device=self.device, dtype=torch.complex128).contiguous()
+            shape, ptr, on_dev = tuple(t.shape), t.data_ptr(), 1
+        else:
+            a = np.ascontiguousarray(c, dtype=np.complex128)
+            shape, ptr, on_dev = a.shape, a.ctypes.data, 0
+        if len(shape) != 3 or shape[:2] != (self.n_k, self.n) or occ.shape != (self.n_k, shape[2]):
+            raise ValueError(f"coefficients must be ({self.n_k}, {self.n}, n_states) with occupations "
+                             f"({self.n_k}, n_states); got {shape} and {occ.shape}")
+        _check(self.lib.vgtb_set_coefficients(self.ctx, ptr, occ.ctypes.data, int(shape[2]), on_dev),
+               self.ctx)
+
+    @property
+    def num_states(self) -> int:
+        return int(self.lib.vgtb_num_states(self.ctx))
+
+    def get_coefficients(self):
+        """(coefficients n_k x N x n_states on the device, occupations n_k x n_states)."""
+        torch = self._torch
+        ns = self.num_states
+        out = torch.empty((self.n_k, self.n, max(ns, 1)), dtype=torch.complex128, device=self.device)
+        occ = np.zeros((self.n_k, max(ns, 1)))
+        _check(self.lib.vgtb_get_coefficients(self.ctx, out.data_ptr(), occ.ctypes.data, 1), self.ctx)
+        return out, occ
 
     def _check_shape(self, shape):
         if tuple(shape) != (self.n_k, self.n, self.n):

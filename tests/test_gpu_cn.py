@@ -1,0 +1,172 @@
+"""Crank-Nicolson propagation of the coefficients (Eq. 5) on the GPU, through
+the C ABI, against the FP64 oracle's same scheme.
+
+Bars: the density D = sum f C C^dag within 1e-10 relative per k (the
+coefficients themselves where both sides start from the same ones), the
+current within 1e-10 of max|J|, E and q.  Cases: the 8-atom kick (one panel),
+the 64-atom SCC pulse (N = 256: four elimination panels) in both couplings,
+ragged N = 52 and N = 148 (three panels, the last partial) from caller-set
+coefficients with ragged state counts, a checkpoint resumed bit for bit, and
+S-unitarity of the 512-atom workload (sampled columns of C^dag S C).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import vgtb_synth as vs
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2308_09782_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.load_library()
+
+
+def _rel_max(a, b):
+    return max(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) for k in range(len(b)))
+
+
+def _check_hist(h, ref, j_tol=1e-10):
+    jmax = np.abs(ref["J"]).max()
+    assert jmax > 0
+    assert np.abs(h["J"] - ref["J"]).max() <= j_tol * jmax
+    assert np.abs(h["E"] - ref["E"]).max() < 1e-11 * np.abs(ref["E"]).max()
+    assert np.abs(h["q"] - ref["q"]).max() < 1e-10
+    assert np.abs(h["trace"] - ref["trace"]).max() < 1e-10 * np.abs(ref["trace"]).max()
+
+
+def _from_ground_state(sysm, atab, dt, n, coupling="peierls"):
+    c0, occ, z, _ = oracle.ground_state_coefficients(sysm)
+    ref, st = oracle.propagate_crank_nicolson(sysm, c0, occ, atab, dt, n, z=z, coupling=coupling)
+    with pkg.Propagator(sysm, dt, "fp64", history_capacity=n, coupling=coupling,
+                        propagator="crank_nicolson") as p:
+        p.ground_state()
+        assert p.num_states == c0[0].shape[1]
+        assert np.allclose(p.reference_charges(), z, atol=1e-12)
+        p.set_field_table(atab)
+        p.step(n)
+        h = p.read_observables(0, n)
+        d = p.get_density(0).cpu().numpy()
+    _check_hist(h, ref)
+    want = [oracle.density_from_coefficients(c, f) for c, f in zip(st.c, st.occ)]
+    assert _rel_max(d, want) < 1e-10
+
+
+def _from_coefficients(sysm, atab, dt, n, n_s, seed, z=None):
+    rng = np.random.default_rng(seed)
+    c0, occ, zg, _ = oracle.ground_state_coefficients(sysm)
+    n_orb = sysm.n_orb
+    start = []
+    for c in c0:
+        x = np.zeros((n_orb, n_s), complex)
+        m = min(n_s, c.shape[1])
+        x[:, :m] = c[:, :m]
+        start.append(x + 0.05 * (rng.normal(size=x.shape) + 1j * rng.normal(size=x.shape)))
+    f = rng.uniform(0.2, 2.0, size=(sysm.n_k, n_s))
+    z = zg if z is None else z
+    ref, st = oracle.propagate_crank_nicolson(sysm, start, f, atab, dt, n, z=z)
+    sysm_z = dataclasses.replace(sysm, z_ref=z)
+    with pkg.Propagator(sysm_z, dt, "fp64", history_capacity=n, propagator="crank_nicolson") as p:
+        p.set_coefficients(np.stack(start), f)
+        assert p.num_states == n_s
+        p.set_field_table(atab)
+        p.step(n)
+        h = p.read_observables(0, n)
+        cg, fg = p.get_coefficients()
+        cg = cg.cpu().numpy()
+    assert np.array_equal(fg, f)
+    _check_hist(h, ref)
+    assert _rel_max(cg, st.c) < 1e-10
+
+
+def test_kick_8_atoms_1000_steps():
+    c = vs.CONFIGS["si8_k64"]
+    sysm = vs.config_system("si8_k64")
+    sysm = sysm.with_kpts(sysm.kpts[::8])
+    _from_ground_state(sysm, vs.kick_table(1, c["a0"]), c["dt"], 1000)
+
+
+@pytest.mark.parametrize("coupling", ["peierls", "momentum"])
+def test_scc_pulse_64_atoms(coupling):
+    c = vs.CONFIGS["asi64_k8_scc"]
+    sysm = vs.config_system("asi64_k8_scc")
+    full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
+    _from_ground_state(sysm, full[1500:1701], c["dt"], 200, coupling)
+
+
+def test_ragged_52_scc_from_coefficients():
+    sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
+    atab = vs.sin2_pulse_table(201, 0.2, 0.3, 40.0, 2.0)
+    _from_coefficients(sysm, atab, 0.2, 200, 7, 1)
+
+
+def test_ragged_148_three_panels():
+    sysm = vs.random_cell(37, (1, 1, 1), seed=9, gamma_u=0.25)
+    _from_coefficients(sysm, vs.kick_table(1, 0.05), 0.2, 60, 75, 2)
+
+
+def test_checkpoint_resume_is_bit_exact():
+    sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
+    atab = vs.sin2_pulse_table(101, 0.2, 0.3, 20.0, 2.0)
+    with pkg.Propagator(sysm, 0.2, "fp64", history_capacity=100, propagator="crank_nicolson") as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.step(40)
+        blob = p.save_state()
+        p.step(30)
+        ja = p.read_observables(40, 30)["J"]
+        ca = p.get_coefficients()[0].cpu().numpy()
+        p.load_state(blob)
+        assert p.step_index == 40
+        p.step(30)
+        jb = p.read_observables(40, 30)["J"]
+        cb = p.get_coefficients()[0].cpu().numpy()
+    assert np.array_equal(ja, jb)
+    assert np.array_equal(ca, cb)
+
+
+def test_rejects_density_calls():
+    sysm = vs.random_cell(13, (1, 1, 1), seed=3)
+    with pkg.Propagator(sysm, 0.2, "fp64", history_capacity=4, propagator="crank_nicolson") as p:
+        with pytest.raises(pkg.VgtbError) as ei:
+            p.set_density(np.zeros((1, 52, 52), complex))
+        assert ei.value.status == 2
+        p.ground_state()
+        with pytest.raises(pkg.VgtbError) as ei:
+            p.get_density(1)
+        assert ei.value.status == 2
+    with pkg.Propagator(sysm, 0.2, "fp64", history_capacity=4) as p:
+        with pytest.raises(pkg.VgtbError) as ei:
+            p.set_coefficients(np.zeros((1, 52, 3), complex), np.ones((1, 3)))
+        assert ei.value.status == 2
+
+
+def test_full_size_s_unitarity():
+    # The 512-atom workload (N = 2048, 8 k, 32 elimination panels) on its pulse:
+    # C^dag S C stays the identity on sampled columns, and Tr(D S) = N_el.
+    c = vs.CONFIGS["asi512_k8_scc"]
+    sysm = vs.config_system("asi512_k8_scc")
+    full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
+    n = 8
+    with pkg.Propagator(sysm, c["dt"], "fp64", history_capacity=n, propagator="crank_nicolson") as p:
+        p.ground_state()
+        p.set_field_table(full[2000:])
+        p.step(n)
+        h = p.read_observables(0, n)
+        cf, occ = p.get_coefficients()
+        cols = [0, 1, 511, 1023]
+        cs = cf[:, :, cols].cpu().numpy()
+    assert np.abs(h["trace"] - sysm.n_electrons).max() < 1e-10 * sysm.n_electrons
+    assert np.all(np.isfinite(h["J"]))
+    for ik in (0, 5):
+        s = oracle.overlap_k(sysm, sysm.kpts[ik])
+        g = cs[ik].conj().T @ s @ cs[ik]
+        assert np.abs(g - np.eye(len(cols))).max() < 1e-11

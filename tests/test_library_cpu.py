@@ -25,7 +25,7 @@ def _lib():
 def test_header_symbols_exported(repo_root):
     lib = _lib()
     header = open(os.path.join(repo_root, "include", "vgtb.h")).read()
-    declared = set(re.findall(r"^\s*(?:vgtb_status|int64_t|const char \*|void)\s*\*?\s*(vgtb_\w+)\s*\(",
+    declared = set(re.findall(r"^\s*(?:vgtb_status|int64_t|int32_t|const char \*|void)\s*\*?\s*(vgtb_\w+)\s*\(",
                               header, flags=re.M))
     assert declared == set(pkg.EXPORTED), declared ^ set(pkg.EXPORTED)
     for name in declared:
@@ -114,3 +114,18 @@ def test_rejects_momentum_coupling_without_gradients_and_bad_gradients():
     _expect_inval(s, bad, match="coupling")
     # the same system is accepted with either coupling
     assert pkg.vgtb_workspace_size(s, opts) > pkg.vgtb_workspace_size(s, pkg.make_options(0.2))
+
+
+def test_crank_nicolson_options_validated_and_sized():
+    _lib()
+    s = vs.config_system("asi64_k8_scc")
+    _expect_inval(s, pkg.make_options(0.2, "fp32", propagator="crank_nicolson"), match="FP64 only")
+    _expect_inval(s, pkg.make_options(0.2, "bf16x3", propagator="crank_nicolson"), match="FP64 only")
+    bad = pkg.make_options(0.2)
+    bad.propagator = 3
+    _expect_inval(s, bad, match="propagator")
+    # the augmented system [S + i dt/2 H | S C] adds 2 N^2 complex per k
+    lf = pkg.vgtb_workspace_size(s, pkg.make_options(0.2))
+    cn = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, propagator="crank_nicolson"))
+    n = s.n_orb
+    assert cn - lf >= 2 * 16 * n * n * s.n_k
