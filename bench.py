@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 run over the same steps (speed-up and current error)")
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--propagator", default="leapfrog", choices=["leapfrog", "crank_nicolson"],
+                    help="density leapfrog (Eq. 6, 13) or Crank-Nicolson on the coefficients "
+                         "(Eq. 5; FP64 only)")
     ap.add_argument("--coupling", default="peierls", choices=["peierls", "momentum"],
                     help="field coupling: Peierls phase on the H0 blocks, or the momentum "
                          "matrix of the overlap gradients (Eq. 12)")
@@ -71,7 +74,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls"):
+def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls", propagator="leapfrog"):
     """The FP64 oracle as it stands, on a bounded sample of the same workload."""
     import oracle
     from threadpoolctl import threadpool_info
@@ -84,10 +87,18 @@ def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls"):
         a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
         d0.append(1e-3 * 0.5 * (a + a.conj().T))
     z = np.full(sysm.n_atoms, 4.0)
-    state = oracle.make_state(sub, d0, z)
-    t0 = time.perf_counter()
-    oracle.propagate(sub, None, atab, dt, n_steps, state=state, coupling=coupling)
-    el = time.perf_counter() - t0
+    if propagator == "crank_nicolson":
+        ns = n // 2
+        c0 = [1e-2 * (rng.normal(size=(n, ns)) + 1j * rng.normal(size=(n, ns))) for _ in range(n_k_sample)]
+        cstate = oracle.make_coefficient_state(sub, c0, np.full((n_k_sample, ns), 2.0), z)
+        t0 = time.perf_counter()
+        oracle.propagate_crank_nicolson(sub, None, None, atab, dt, n_steps, state=cstate, coupling=coupling)
+        el = time.perf_counter() - t0
+    else:
+        state = oracle.make_state(sub, d0, z)
+        t0 = time.perf_counter()
+        oracle.propagate(sub, None, atab, dt, n_steps, state=state, coupling=coupling)
+        el = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return {
         "value": n_k_sample * n_steps / el,
@@ -121,11 +132,11 @@ def counter_traffic(precision, workload):
 
 
 def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload, tune=True,
-             coupling="peierls"):
+             coupling="peierls", propagator="leapfrog"):
     """Ground state, warmup, then `steps` timed steps of one precision form."""
     total = warmup + steps
     prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total + min(steps, 20), 1),
-                         coupling=coupling)
+                         coupling=coupling, propagator=propagator)
     t_init = time.perf_counter()
     gap = prop.ground_state()
     t_init = time.perf_counter() - t_init
@@ -152,11 +163,26 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
         events[i + 1].record()
     torch.cuda.synchronize()
     step_ms = np.array([events[i].elapsed_time(events[i + 1]) for i in range(n_lat)])
+    prop_ns = prop.num_states
     prop.close()
 
     n, nk = sysm.n_orb, sysm.n_k
     gemm_ms, gemm_n = prof["gemm"]
-    if gemm_n:
+    if propagator == "crank_nicolson":
+        # The solve of (S + i dt/2 H) X = S C: factorisation (8/3) N^3 and the
+        # forward and back substitution over n_s right-hand sides 8 N^2 n_s, per k.
+        ns = prop_ns
+        solve_ms = prof["cn_solve"][0]
+        launches = max(prof["cn_solve"][1], 1)
+        avg_s = solve_ms / launches / 1e3
+        flops_per_launch = (8.0 / 3.0 * n ** 3 + 8.0 * n * n * ns) * nk
+        achieved = flops_per_launch / avg_s / 1e12
+        roof = {"bound": "mfma", "kernel": f"Crank-Nicolson solve (FP64, all {nk} k-points, "
+                                           f"{ns} states)",
+                "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_s * 1e3}
+    elif gemm_n:
         gemm_avg_s = gemm_ms / gemm_n / 1e3
         flops_per_launch = 8.0 * n ** 3 * nk
         achieved = flops_per_launch / gemm_avg_s / 1e12
@@ -347,8 +373,11 @@ def main():
     total = args.warmup + args.steps
     # Warmup and timed steps sit in the middle of the pulse, where A is large.
     offset = min(2000, max(0, atab.shape[0] - total))
+    if args.propagator == "crank_nicolson":
+        args.precision = "fp64"
     head = run_form(vg, torch, sysm, atab, dt, args.precision, args.warmup, args.steps, offset,
-                    args.workload, tune=not args.no_autotune, coupling=args.coupling)
+                    args.workload, tune=not args.no_autotune, coupling=args.coupling,
+                    propagator=args.propagator)
     ref = None
     if args.precision != "fp64" and not args.no_fp64_compare:
         ref = run_form(vg, torch, sysm, atab, dt, "fp64", args.warmup, args.steps, offset,
@@ -372,7 +401,7 @@ def main():
         "config": {"workload": f"{args.workload}: {sysm.n_atoms}-atom a-Si, {n} orbitals, "
                                f"{nk} k-points (2x2x2), SCC, sin^2 pulse, dt={dt}",
                    "n_orb": n, "n_k": nk, "n_atoms": sysm.n_atoms, "precision": args.precision,
-                   "coupling": args.coupling,
+                   "coupling": args.coupling, "propagator": args.propagator,
                    "parallelism": "single GPU, all k-points batched"},
         "roofline": head["roofline"],
         "step_latency_ms": head["step_latency_ms"],
@@ -392,7 +421,7 @@ def main():
         out["j_err_steps"] = total
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysm, atab[offset:], dt, args.cpu_sample_k, args.cpu_sample_steps,
-                                           args.coupling)
+                                           args.coupling, args.propagator)
     print(json.dumps(out), flush=True)
     return 0
 

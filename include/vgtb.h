@@ -321,9 +321,10 @@ typedef enum {
                            launch (the other classes then stay at zero except
                            REDUCE, which is the per-block history reduction)  */
   VGTB_K_CN_PATTERN = 8, /* Crank-Nicolson: D = sum f C C^dag on the pair pattern */
-  VGTB_K_CN_SOLVE = 9,  /* Crank-Nicolson: right-hand side S C, [A | S C] build and
-                           block elimination (diagonal-block inverses + GEMMs)  */
-  VGTB_K_CN_BACK = 10,  /* Crank-Nicolson: back substitution and C update      */
+  VGTB_K_CN_SOLVE = 9,  /* Crank-Nicolson: [S + i dt/2 H | S C] build and the
+                           recursive block elimination (leaf-block inverses +
+                           GEMMs)                                               */
+  VGTB_K_CN_UPDATE = 10, /* Crank-Nicolson: C(t + dt) = 2 X - C(t)             */
   VGTB_K_COUNT = 11
 } vgtb_kernel;
 

@@ -6,14 +6,13 @@
 // solved as X = (S + i tau H)^-1 S C and C(t + dt) = 2 X - C(t).  The matrix
 // A = S + i tau H has the positive-definite Hermitian part S, so Gaussian
 // elimination needs no pivoting (every leading block is invertible).  It is
-// done by blocks of kCnBlock rows on the augmented matrix [A | S C]:
-//   for each diagonal block j:  Z_j = A_jj^-1 [A_j,>j | R_j]   (in place)
-//                               [A_>j,>j | R_>j] -= A_>j,j Z_j
-//   then, right-looking back substitution over the R columns:
-//                               R_<j -= Z_<j,j X_j
-// after which the R columns hold X.  The diagonal blocks are inverted in LDS
-// (Gauss-Jordan, one workgroup per k-point); every other flop is a strided
-// complex FP64 GEMM on the matrix cores.
+// done recursively on the augmented matrix [A | S C] (cn_solve): halve the
+// block, solve the top half against everything to its right, form the Schur
+// complement, solve the bottom half, and back-substitute into the top half;
+// after which the S C columns hold X.  The kCnBlock x kCnBlock blocks at the
+// leaves are inverted in registers (Gauss-Jordan, one workgroup per k-point);
+// every other flop is a strided complex FP64 GEMM on the matrix cores, half of
+// them with a depth of N/2.
 //
 // Observables need D = sum_n f_n C_n C_n^dag (the definition after Eq. 6) only
 // on the pair pattern; k_cn_pattern samples it there, and the density-form
@@ -21,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "vgtb_internal.h"
 
@@ -164,64 +164,110 @@ __global__ __launch_bounds__(WM *WN * 64) void k_zgemm_strided(
       }
 }
 
-constexpr int kGemmBM = 64, kGemmBN = 64;
-
-void gemm_strided(const double2 *a, int lda, size_t sa, const double2 *b, int ldb, size_t sb,
-                  double2 *c, int ldc, size_t sc, int m, int n, int k, double alpha, bool beta_one,
-                  int batch, hipStream_t s) {
-  if (m <= 0 || n <= 0 || k <= 0) return;
-  const int tm = (m + kGemmBM - 1) / kGemmBM, tn = (n + kGemmBN - 1) / kGemmBN;
-  hipLaunchKernelGGL((k_zgemm_strided<kGemmBM, kGemmBN, 16, 2, 2>), dim3(tm * tn, batch), dim3(256),
+template <int BM, int BN, int WM, int WN>
+void gemm_tile(const double2 *a, int lda, size_t sa, const double2 *b, int ldb, size_t sb, double2 *c,
+               int ldc, size_t sc, int m, int n, int k, double alpha, bool beta_one, int batch,
+               hipStream_t s) {
+  const int tm = (m + BM - 1) / BM, tn = (n + BN - 1) / BN;
+  hipLaunchKernelGGL((k_zgemm_strided<BM, BN, 16, WM, WN>), dim3(tm * tn, batch), dim3(WM * WN * 64),
                      0, s, a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one ? 1 : 0, tm, tn);
 }
 
+// Tile shape of the large products (trailing update, back substitution):
+// VGTB_CN_TILE = 1: 64 x 64 (4 waves), 2: 128 x 64 (8), 3: 128 x 128 (16).
+int cn_tile() {
+  static const int t = [] {
+    const char *e = std::getenv("VGTB_CN_TILE");
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= 1 && v <= 3) ? v : 2;
+  }();
+  return t;
+}
+
+void gemm_strided(const double2 *a, int lda, size_t sa, const double2 *b, int ldb, size_t sb,
+                  double2 *c, int ldc, size_t sc, int m, int n, int k, double alpha, bool beta_one,
+                  int batch, hipStream_t s, bool small_m = false) {
+  if (m <= 0 || n <= 0 || k <= 0) return;
+  const int tile = small_m ? 1 : cn_tile();
+  if (tile == 3 && m > 64)
+    gemm_tile<128, 128, 4, 4>(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one, batch, s);
+  else if (tile == 2 && m > 64)
+    gemm_tile<128, 64, 4, 2>(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one, batch, s);
+  else
+    gemm_tile<64, 64, 2, 2>(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one, batch, s);
+}
+
 // Inverse of the nb x nb diagonal block at (j0, j0) of each k's augmented
-// matrix, by Gauss-Jordan elimination without pivoting in LDS; written to
-// inv[k] (kCnBlock x kCnBlock, identity outside nb x nb).
-__global__ __launch_bounds__(256) void k_blk_inv(const double2 *__restrict__ aug, int ld, size_t sa,
-                                                 int j0, int nb, double2 *__restrict__ inv) {
+// matrix, by Gauss-Jordan elimination without pivoting; written to inv[k]
+// (kCnBlock x kCnBlock, identity outside nb x nb).  The block lives in
+// registers: thread t of kInvThreads owns column t % B and rows t / B + W r (four
+// rows each, sixteen wavefronts: while one waits, the others issue).  Each pivot step
+// publishes the old pivot row and column through LDS (double-buffered, so one
+// barrier per step).  With b = 0 on the pivot row and column (else a_ij),
+// c = -1 on the pivot row (else a_ip) and t_j = 1/a_pp at j = p (else
+// a_pj/a_pp), every entry takes the same update a_ij <- b - c t_j, which is
+//   a_pp <- 1/a_pp,  a_pj <- a_pj/a_pp,  a_ip <- -a_ip/a_pp,
+//   a_ij <- a_ij - a_ip a_pj / a_pp,
+// written with selects only (no branches, no indexed register arrays).
+constexpr int kInvThreads = 1024;
+__global__ __launch_bounds__(kInvThreads) void k_blk_inv(const double2 *__restrict__ aug, int ld,
+                                                         size_t sa, int j0, int nb,
+                                                         double2 *__restrict__ inv) {
   constexpr int B = kCnBlock;
-  constexpr int PER = B * B / 256;
-  __shared__ double2 a[B][B + 1];
+  constexpr int W = kInvThreads / B;   // row groups
+  constexpr int R = B / W;       // rows per thread
+  __shared__ double2 rowb[2][B], colb[2][B];
   const int k = blockIdx.x, tid = threadIdx.x;
+  const int j = tid % B, w = tid / B;
   const double2 *src = aug + (size_t)k * sa + (size_t)j0 * ld + j0;
-  for (int e = tid; e < B * B; e += 256) {
-    const int i = e / B, j = e % B;
-    a[i][j] = (i < nb && j < nb) ? src[(size_t)i * ld + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  double ar[R], ai[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = w + W * r;
+    const bool in = i < nb && j < nb;
+    const double2 v = in ? src[(size_t)i * ld + j] : make_double2(0.0, 0.0);
+    ar[r] = in ? v.x : (i == j ? 1.0 : 0.0);
+    ai[r] = in ? v.y : 0.0;
   }
-  __syncthreads();
   for (int p = 0; p < nb; ++p) {
-    const double2 d = a[p][p];
-    const double den = d.x * d.x + d.y * d.y;
-    const double2 piv = make_double2(d.x / den, -d.y / den);
-    double2 nv[PER];
+    const int buf = p & 1;
+    const int rp = p / W;
+    if (w == p % W) {
+      double xr = ar[0], xi = ai[0];
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int e = tid + 256 * r;
-      const int i = e / B, j = e % B;
-      const double2 aij = a[i][j], aip = a[i][p], apj = a[p][j];
-      if (i == p && j == p) {
-        nv[r] = piv;
-      } else if (i == p) {
-        nv[r] = cmul(apj, piv);
-      } else if (j == p) {
-        const double2 t = cmul(aip, piv);
-        nv[r] = make_double2(-t.x, -t.y);
-      } else {
-        const double2 t = cmul(aip, cmul(apj, piv));
-        nv[r] = make_double2(aij.x - t.x, aij.y - t.y);
+      for (int r = 1; r < R; ++r) {
+        xr = (r == rp) ? ar[r] : xr;
+        xi = (r == rp) ? ai[r] : xi;
       }
+      rowb[buf][j] = make_double2(xr, xi);
     }
-    __syncthreads();
+    if (j == p) {
 #pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int e = tid + 256 * r;
-      a[e / B][e % B] = nv[r];
+      for (int r = 0; r < R; ++r) colb[buf][w + W * r] = make_double2(ar[r], ai[r]);
     }
     __syncthreads();
+    const double2 d = colb[buf][p];
+    const double den = 1.0 / (d.x * d.x + d.y * d.y);
+    const double pr = d.x * den, pi = -d.y * den;         // 1 / a_pp
+    const double2 rv = rowb[buf][j];
+    const bool jp = (j == p);
+    const double tr = jp ? pr : rv.x * pr - rv.y * pi;    // t_j
+    const double ti = jp ? pi : rv.x * pi + rv.y * pr;
+    double2 cv[R];   // this thread's rows of the pivot column, all loads in flight at once
+#pragma unroll
+    for (int r = 0; r < R; ++r) cv[r] = colb[buf][w + W * r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ip = (w + W * r == p);
+      const double cr = ip ? -1.0 : cv[r].x, ci = ip ? 0.0 : cv[r].y;
+      const double br = (ip || jp) ? 0.0 : ar[r], bi = (ip || jp) ? 0.0 : ai[r];
+      ar[r] = br - (cr * tr - ci * ti);
+      ai[r] = bi - (cr * ti + ci * tr);
+    }
   }
   double2 *dst = inv + (size_t)k * B * B;
-  for (int e = tid; e < B * B; e += 256) dst[e] = a[e / B][e % B];
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[(size_t)(w + W * r) * B + j] = make_double2(ar[r], ai[r]);
 }
 
 // [A | R] of each k: zeros in A (the pattern is scattered next), R = W[:, :ns].
@@ -267,22 +313,25 @@ __global__ void k_cn_update(const double2 *__restrict__ aug, int ld, double2 *__
     *ctr += 1;
 }
 
-// D on the pair pattern: D[I mu][J nu] = sum_s f_s C[I mu][s] conj(C[J nu][s]),
-// one workgroup per (pair, k), the state sum split over its threads.
+// D on the pair pattern: D[I mu][J nu] = sum_s f_s C[I mu][s] conj(C[J nu][s]).
+// One wavefront per (pair, k), four pairs per workgroup; each lane sums every
+// 64th state (coalesced rows of C), then a shuffle reduction.
 template <int NO>
 __global__ __launch_bounds__(256) void k_cn_pattern(PairGraph g, const double2 *__restrict__ c,
                                                     const double *__restrict__ occ, int n, int ns,
                                                     double2 *__restrict__ d) {
   constexpr int E2 = NO * NO;
-  __shared__ double red[4][2 * E2];
-  const int p = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.y;
+  if (p >= g.n_pairs) return;   // uniform per wavefront
   const int I = g.pair_row[p], J = g.pair_col[p];
   const double2 *ck = c + (size_t)k * n * n;
   const double *fk = occ + (size_t)k * n;
-  double2 acc[E2];
+  double accr[E2], acci[E2];
 #pragma unroll
-  for (int e = 0; e < E2; ++e) acc[e] = make_double2(0.0, 0.0);
-  for (int s = tid; s < ns; s += 256) {
+  for (int e = 0; e < E2; ++e) accr[e] = acci[e] = 0.0;
+  for (int s = lane; s < ns; s += 64) {
     const double f = fk[s];
     double2 ci[NO], cj[NO];
 #pragma unroll
@@ -296,25 +345,20 @@ __global__ __launch_bounds__(256) void k_cn_pattern(PairGraph g, const double2 *
 #pragma unroll
       for (int nu = 0; nu < NO; ++nu) {
         // ci * conj(cj)
-        acc[mu * NO + nu].x += ci[mu].x * cj[nu].x + ci[mu].y * cj[nu].y;
-        acc[mu * NO + nu].y += ci[mu].y * cj[nu].x - ci[mu].x * cj[nu].y;
+        accr[mu * NO + nu] += ci[mu].x * cj[nu].x + ci[mu].y * cj[nu].y;
+        acci[mu * NO + nu] += ci[mu].y * cj[nu].x - ci[mu].x * cj[nu].y;
       }
   }
-  const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
   for (int e = 0; e < E2; ++e) {
-    const double xr = wave_reduce(acc[e].x), xi = wave_reduce(acc[e].y);
-    if (lane == 0) {
-      red[wave][2 * e] = xr;
-      red[wave][2 * e + 1] = xi;
-    }
+    accr[e] = wave_reduce(accr[e]);
+    acci[e] = wave_reduce(acci[e]);
   }
-  __syncthreads();
-  if (tid < E2) {
-    const int e = tid;
-    const double xr = (red[0][2 * e] + red[1][2 * e]) + (red[2][2 * e] + red[3][2 * e]);
-    const double xi = (red[0][2 * e + 1] + red[1][2 * e + 1]) + (red[2][2 * e + 1] + red[3][2 * e + 1]);
-    d[(size_t)k * n * n + (size_t)(I * NO + e / NO) * n + (J * NO + e % NO)] = make_double2(xr, xi);
+  if (lane == 0) {
+#pragma unroll
+    for (int e = 0; e < E2; ++e)
+      d[(size_t)k * n * n + (size_t)(I * NO + e / NO) * n + (J * NO + e % NO)] =
+          make_double2(accr[e], acci[e]);
   }
 }
 
@@ -379,10 +423,11 @@ void launch_cn_permute_pairs(const PairGraph &g, const double2 *spk, double2 *sq
 
 void launch_cn_pattern(const PairGraph &g, const double2 *c, const double *occ, int n, int ns, int nk,
                        double2 *d, hipStream_t s) {
+  const dim3 grid(blocks(g.n_pairs, 4), nk);
   if (g.norb == 4)
-    hipLaunchKernelGGL(k_cn_pattern<4>, dim3(g.n_pairs, nk), dim3(256), 0, s, g, c, occ, n, ns, d);
+    hipLaunchKernelGGL(k_cn_pattern<4>, grid, dim3(256), 0, s, g, c, occ, n, ns, d);
   else
-    hipLaunchKernelGGL(k_cn_pattern<1>, dim3(g.n_pairs, nk), dim3(256), 0, s, g, c, occ, n, ns, d);
+    hipLaunchKernelGGL(k_cn_pattern<1>, grid, dim3(256), 0, s, g, c, occ, n, ns, d);
 }
 
 void launch_cn_vmid(const double *v, double *vprev, double *vmid, int na, bool first, hipStream_t s) {
@@ -402,33 +447,49 @@ void launch_cn_build(const PairGraph &g, const double2 *w, const double2 *hq, co
     hipLaunchKernelGGL(k_cn_scatter<1>, grid, dim3(256), 0, s, g, aug, ld, n, hq, spk, tau);
 }
 
-void launch_cn_eliminate(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s) {
-  const int ld = 2 * n;
-  const size_t sa = (size_t)n * ld;
-  const size_t si = (size_t)kCnBlock * kCnBlock;
-  for (int j0 = 0; j0 < n; j0 += kCnBlock) {
-    const int nb = std::min(kCnBlock, n - j0);
-    hipLaunchKernelGGL(k_blk_inv, dim3(nk), dim3(256), 0, s, aug, ld, sa, j0, nb, inv);
-    // Z = A_jj^-1 [A_j,>j | R_j], in place (M = nb <= the tile's 64 rows).
-    double2 *row = aug + (size_t)j0 * ld + (j0 + nb);
-    gemm_strided(inv, kCnBlock, si, row, ld, sa, row, ld, sa, nb, (n - j0 - nb) + ns, nb, 1.0, false,
-                 nk, s);
-    const int m = n - j0 - nb;
-    if (m > 0)
-      gemm_strided(aug + (size_t)(j0 + nb) * ld + j0, ld, sa, row, ld, sa,
-                   aug + (size_t)(j0 + nb) * ld + (j0 + nb), ld, sa, m, m + ns, nb, -1.0, true, nk, s);
-  }
+namespace {
+
+// Rows split of a solve of m rows: the first part a whole number of blocks,
+// at least half of them.
+int cn_split(int m) {
+  const int nb = (m + kCnBlock - 1) / kCnBlock;
+  return kCnBlock * ((nb + 1) / 2);
 }
 
-void launch_cn_back(double2 *aug, int n, int ns, int nk, hipStream_t s) {
+// A^-1 B in place for the m x m diagonal block A at (r0, r0) of every k's
+// augmented matrix and B = all columns to its right (width n + ns - r0 - m):
+//   m <= kCnBlock: B <- A^-1 B with A^-1 from k_blk_inv;
+//   else, A = [A11 A12; A21 A22] split at h:
+//     [A12 | B1] <- A11^-1 [A12 | B1]            (recursion)
+//     [A22 | B2] -= A21 [A12 | B1]               (Schur complement, K = h)
+//     B2 <- A22^-1 B2                            (recursion)
+//     B1 -= A12 B2                               (K = m - h)
+// Most of the work is in the two products, whose depth K is half the block.
+void cn_solve(double2 *aug, double2 *inv, int r0, int m, int n, int ns, int nk, hipStream_t s) {
   const int ld = 2 * n;
   const size_t sa = (size_t)n * ld;
-  const int last = ((n - 1) / kCnBlock) * kCnBlock;
-  for (int j0 = last; j0 > 0; j0 -= kCnBlock) {
-    const int nb = std::min(kCnBlock, n - j0);
-    gemm_strided(aug + j0, ld, sa, aug + (size_t)j0 * ld + n, ld, sa, aug + n, ld, sa, j0, ns, nb,
-                 -1.0, true, nk, s);
+  const int w = n + ns - (r0 + m);
+  auto at = [&](int r, int c) { return aug + (size_t)r * ld + c; };
+  if (m <= kCnBlock) {
+    hipLaunchKernelGGL(k_blk_inv, dim3(nk), dim3(kInvThreads), 0, s, aug, ld, sa, r0, m, inv);
+    // In place: the product's tile holds all m rows of each column it owns.
+    gemm_strided(inv, kCnBlock, (size_t)kCnBlock * kCnBlock, at(r0, r0 + m), ld, sa, at(r0, r0 + m),
+                 ld, sa, m, w, m, 1.0, false, nk, s, true);
+    return;
   }
+  const int h = cn_split(m);
+  cn_solve(aug, inv, r0, h, n, ns, nk, s);
+  gemm_strided(at(r0 + h, r0), ld, sa, at(r0, r0 + h), ld, sa, at(r0 + h, r0 + h), ld, sa, m - h,
+               (m - h) + w, h, -1.0, true, nk, s);
+  cn_solve(aug, inv, r0 + h, m - h, n, ns, nk, s);
+  gemm_strided(at(r0, r0 + h), ld, sa, at(r0 + h, r0 + m), ld, sa, at(r0, r0 + m), ld, sa, h, w,
+               m - h, -1.0, true, nk, s);
+}
+
+}  // namespace
+
+void launch_cn_solve(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s) {
+  cn_solve(aug, inv, 0, n, n, ns, nk, s);
 }
 
 void launch_cn_update(const double2 *aug, double2 *c, int n, int ns, int nk, int64_t *ctr,

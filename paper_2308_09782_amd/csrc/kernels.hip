@@ -1201,19 +1201,19 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
 template <int NO, bool DELTA, int OUT>
 static void spmm_launch(int threads, hipStream_t s, const PairGraph &g, const double2 *d,
                         const double2 *d0, int n, const double2 *hq, const double2 *c0, void *w,
-                        int np, int nk, float2 *w32, int cpt) {
+                        int np, int nk, float2 *w32, int cpt, int ncols) {
   const int ng = g.n_groups;
   if (g.group_size == 8 && cpt == 1)
-    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 1>), dim3(blocks_for(n, threads), ng, nk),
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 1>), dim3(blocks_for(ncols, threads), ng, nk),
                        dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
   else if (g.group_size == 4 && cpt == 2)
-    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 2>), dim3(blocks_for(n, 2 * threads), ng, nk),
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 2>), dim3(blocks_for(ncols, 2 * threads), ng, nk),
                        dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
   else if (g.group_size == 4 && cpt == 1)
-    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 1>), dim3(blocks_for(n, threads), ng, nk),
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 1>), dim3(blocks_for(ncols, threads), ng, nk),
                        dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
   else
-    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 2>), dim3(blocks_for(n, 2 * threads), ng, nk),
+    hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 2>), dim3(blocks_for(ncols, 2 * threads), ng, nk),
                        dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
 }
 
@@ -1231,9 +1231,9 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource 
 template <bool DELTA, int OUT, int CB>
 static void spmm_mfma_launch_cb(hipStream_t s, const PairGraph &g, const double2 *d, int n,
                                 const double2 *hq, const double2 *c0, void *w, int np, int nk,
-                                float2 *w32) {
-  const int nw = std::max(1, std::min(4, (n + 16 * CB - 1) / (16 * CB)));
-  dim3 grid(blocks_for(n, 16 * CB * nw), g.n_groups, nk);
+                                float2 *w32, int ncols) {
+  const int nw = std::max(1, std::min(4, (ncols + 16 * CB - 1) / (16 * CB)));
+  dim3 grid(blocks_for(ncols, 16 * CB * nw), g.n_groups, nk);
   if (g.group_size == 16)
     hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 16, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq,
                        c0, w, np, nk, w32);
@@ -1248,26 +1248,27 @@ static void spmm_mfma_launch_cb(hipStream_t s, const PairGraph &g, const double2
 template <bool DELTA, int OUT>
 static void spmm_mfma_launch(hipStream_t s, const PairGraph &g, const double2 *d, int n,
                              const double2 *hq, const double2 *c0, void *w, int np, int nk,
-                             float2 *w32, int cb) {
-  if (cb == 4) spmm_mfma_launch_cb<DELTA, OUT, 4>(s, g, d, n, hq, c0, w, np, nk, w32);
-  else if (cb == 2) spmm_mfma_launch_cb<DELTA, OUT, 2>(s, g, d, n, hq, c0, w, np, nk, w32);
-  else spmm_mfma_launch_cb<DELTA, OUT, 1>(s, g, d, n, hq, c0, w, np, nk, w32);
+                             float2 *w32, int cb, int ncols) {
+  if (cb == 4) spmm_mfma_launch_cb<DELTA, OUT, 4>(s, g, d, n, hq, c0, w, np, nk, w32, ncols);
+  else if (cb == 2) spmm_mfma_launch_cb<DELTA, OUT, 2>(s, g, d, n, hq, c0, w, np, nk, w32, ncols);
+  else spmm_mfma_launch_cb<DELTA, OUT, 1>(s, g, d, n, hq, c0, w, np, nk, w32, ncols);
 }
 
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, int variant, hipStream_t s) {
+                 float2 *w32, int variant, hipStream_t s, int ncols) {
+  if (ncols <= 0 || ncols > n) ncols = n;
   if (g.norb == 4 && variant < 0) {
     const int cb = -variant;
-    if (!d0) spmm_mfma_launch<false, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
-    else if (out_format == 0) spmm_mfma_launch<true, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
-    else if (out_format == 1) spmm_mfma_launch<true, 1>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
-    else spmm_mfma_launch<true, 2>(s, g, d, n, hq, c0, w, np, nk, w32, cb);
+    if (!d0) spmm_mfma_launch<false, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
+    else if (out_format == 0) spmm_mfma_launch<true, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
+    else if (out_format == 1) spmm_mfma_launch<true, 1>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
+    else spmm_mfma_launch<true, 2>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
     return;
   }
   const int cpt = variant == 2 ? 2 : 1;
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
-#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt)
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt, ncols)
   if (g.norb == 4) {
     if (!d0) VG_SPMM(4, false, 0);
     else if (out_format == 0) VG_SPMM(4, true, 0);

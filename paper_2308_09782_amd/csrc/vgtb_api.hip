@@ -527,16 +527,13 @@ void enqueue_step_cn(vgtb_ctx *c, hipStream_t s) {
                           c->h0k, c->ppk, s);
   });
   timed(c, VGTB_K_SPMM, [&] {
-    vgtb::launch_spmm(c->g, cc, nullptr, n, nk, c->sq, nullptr, c->w, 0, 0, nullptr, c->spmm_variant, s);
+    vgtb::launch_spmm(c->g, cc, nullptr, n, nk, c->sq, nullptr, c->w, 0, 0, nullptr, c->spmm_variant, s, ns);
   });
   timed(c, VGTB_K_CN_SOLVE, [&] {
     vgtb::launch_cn_build(c->g, c->w, c->hq, c->spk, 0.5 * c->dt, n, ns, nk, c->aug, s);
-    vgtb::launch_cn_eliminate(c->aug, c->cinv, n, ns, nk, s);
+    vgtb::launch_cn_solve(c->aug, c->cinv, n, ns, nk, s);
   });
-  timed(c, VGTB_K_CN_BACK, [&] {
-    vgtb::launch_cn_back(c->aug, n, ns, nk, s);
-    vgtb::launch_cn_update(c->aug, cc, n, ns, nk, c->ctr, s);
-  });
+  timed(c, VGTB_K_CN_UPDATE, [&] { vgtb::launch_cn_update(c->aug, cc, n, ns, nk, c->ctr, s); });
 }
 
 // The launches of one step at the current parity, on stream s.  With

@@ -119,10 +119,11 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource 
 // out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np)
 // + complex64 copy w32.  variant: -1, -2, -4 = FP64 matrix cores with that
 // many 16-column slices per wave (four orbitals per atom only); 1, 2 = vector
-// FMAs with that many columns per thread.
+// FMAs with that many columns per thread.  ncols (0 = n): only the first
+// ncols columns of W are formed (at least those; the rest are left as they were).
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, int variant, hipStream_t s);
+                 float2 *w32, int variant, hipStream_t s, int ncols = 0);
 // ctr (may be null): advanced by one when the update has run.
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, int64_t *ctr, hipStream_t s);
@@ -171,8 +172,8 @@ void launch_cn_vmid(const double *v, double *vprev, double *vmid, int na, bool f
 // [A | R]: A = S + i tau H on the pair pattern (zero elsewhere), R = W[:, :ns].
 void launch_cn_build(const PairGraph &g, const double2 *w, const double2 *hq, const double2 *spk,
                      double tau, int n, int ns, int nk, double2 *aug, hipStream_t s);
-void launch_cn_eliminate(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s);
-void launch_cn_back(double2 *aug, int n, int ns, int nk, hipStream_t s);
+// X = A^-1 R in the R columns of [A | R] (recursive block elimination).
+void launch_cn_solve(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s);
 // C = 2 X - C with X the R columns; ctr (may be null) advanced by one.
 void launch_cn_update(const double2 *aug, double2 *c, int n, int ns, int nk, int64_t *ctr,
                       hipStream_t s);

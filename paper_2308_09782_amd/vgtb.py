@@ -34,7 +34,7 @@ EXPORTED = [
     "vgtb_server_destroy", "vgtb_set_coefficients", "vgtb_num_states", "vgtb_get_coefficients",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
-           "assemble": 6, "small": 7, "cn_pattern": 8, "cn_solve": 9, "cn_back": 10}
+           "assemble": 6, "small": 7, "cn_pattern": 8, "cn_solve": 9, "cn_update": 10}
 
 
 class VgtbError(RuntimeError):
