@@ -337,8 +337,9 @@ typedef enum {
  *     atom), or vector FMAs with 1 or 2 columns per thread (variant 1, 2;
  *     row groups of at most 8 atoms);
  *   - the dense product S^-1 W: workgroup tiles 1 = 32x32, 2 = 64x64,
- *     3 = 128x64 (FP64 and FP32 forms); 1 = 64x64, 2 = 128x128 (3xBF16; the
- *     latter when the padded size is a multiple of 128),
+ *     3 = 128x64 (FP64 and FP32 forms); 1 = 64x64, and 128x128 as 2 = 16
+ *     wavefronts of 32x32, 3 = 8 of 64x32, 4 = 8 of 32x64, 5 = 4 of 64x64
+ *     (3xBF16; the 128x128 shapes when the padded size is a multiple of 128),
  * each launched `reps` times after one warm-up launch, and keeps the fastest
  * of each for the following steps.  Only scratch buffers are written: the
  * densities, history and step index are unchanged.  The variants differ in
@@ -353,8 +354,8 @@ typedef struct {
   int32_t n_spmm, n_gemm;        /* number of candidates timed                  */
   int32_t spmm_candidates[8];
   double spmm_ms[8];             /* average launch time of each candidate (ms)  */
-  int32_t gemm_candidates[4];
-  double gemm_ms[4];
+  int32_t gemm_candidates[8];
+  double gemm_ms[8];
 } vgtb_tuning;
 
 vgtb_status vgtb_autotune(vgtb_ctx *ctx, int32_t reps, vgtb_tuning *out_host);

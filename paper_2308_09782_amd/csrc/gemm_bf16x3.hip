@@ -193,8 +193,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
   // wavefront still loads whole 64-byte row segments from global memory.
 #define AROW(L) (((L) & 15) | ((((L) >> 6) & 7) << 4))
 #define ACOL(L) (((L) >> 4) & 3)
-  u32x4 ra[LD], rb[LD];
-#define VG_LOAD128(k0)                                                                         \
+  // Global loads run ahead of the LDS writes by PF stages: the loads of stage
+  // kt+1+PF are issued during stage kt and written to LDS during stage kt+PF.
+  // PF = 2 needs a second register set, which sixteen wavefronts (128
+  // registers each) cannot hold; they use PF = 1.
+  constexpr int PF = (WGM * WGN >= 16) ? 1 : 2;
+  u32x4 ra0[LD], rb0[LD], ra1[LD], rb1[LD];
+#define VG_LOAD128(ra, rb, k0)                                                                 \
   do {                                                                                         \
     _Pragma("unroll") for (int i = 0; i < LD; ++i) {                                           \
       const int L = tid + i * NT2;                                                             \
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
                                                ((size_t)((k0) / 8 + ((L >> 7) & 3)) * np + bn + (L & 127)) * 8); \
     }                                                                                          \
   } while (0)
-#define VG_STORE128(buf)                                                                       \
+#define VG_STORE128(ra, rb, buf)                                                               \
   do {                                                                                         \
     _Pragma("unroll") for (int i = 0; i < LD; ++i) {                                           \
       const int L = tid + i * NT2;                                                             \
@@ -215,13 +220,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
 #define VG_READB(dst, buf, pb)                                                                 \
   _Pragma("unroll") for (int b = 0; b < TN; ++b) dst[b] = Bs[buf][pb][lg][wn0 + b * 16 + lr]
 
-  const int nkt = np / BK;
-  VG_LOAD128(0);
-  VG_STORE128(0);
-  __syncthreads();
-  if (nkt > 1) VG_LOAD128(BK);
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int cur = kt & 1;
+  const int nkt = np / BK;   // even: np is a multiple of 128
+  // One stage: the twelve partial products of LDS buffer cur; between the
+  // first group and the rest, LDS buffer cur^1 receives stage kt+1 from (ra, rb)
+  // and (ra, rb) starts loading stage kt+1+PF.
+  auto stage = [&](int kt, int cur, u32x4 (&ra)[LD], u32x4 (&rb)[LD]) {
     u32x4 fa[TM][4], nf2[TM], nf3[TM], fb0[TN], fb1[TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
@@ -243,8 +246,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
         ci[a][b] = mma(fa[a][3], fb0[b], ci[a][b]);
       }
     if (kt + 1 < nkt) {
-      VG_STORE128(cur ^ 1);
-      if (kt + 2 < nkt) VG_LOAD128((kt + 2) * BK);
+      VG_STORE128(ra, rb, cur ^ 1);
+      if (kt + 1 + PF < nkt) VG_LOAD128(ra, rb, (kt + 1 + PF) * BK);
     }
     VG_READB(fb0, cur, 2);
     // B plane 1 (re_lo): Re += Ar_hi Br_lo;  Im += Ai_hi Br_lo
@@ -275,6 +278,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
         ci[a][b] = mma(fa[a][0], fb1[b], ci[a][b]);
       }
     __syncthreads();
+  };
+
+  VG_LOAD128(ra0, rb0, 0);
+  VG_STORE128(ra0, rb0, 0);
+  __syncthreads();
+  if (nkt > 1) VG_LOAD128(ra0, rb0, BK);                 // stage 1, stored during stage 0
+  if (PF == 2 && nkt > 2) VG_LOAD128(ra1, rb1, 2 * BK);  // stage 2, stored during stage 1
+  for (int kt = 0; kt < nkt; kt += 2) {
+    stage(kt, 0, ra0, rb0);
+    if (PF == 2) stage(kt + 1, 1, ra1, rb1);
+    else stage(kt + 1, 1, ra0, rb0);
   }
 #undef VG_LOAD128
 #undef VG_STORE128
@@ -297,15 +311,25 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
 
 }  // namespace
 
-// tile: 1 = 64 x 64 (four wavefronts), 2 = 128 x 128 (sixteen; np a multiple
-// of 128 only); 0 = 128 x 128 where allowed from np = 512 up.
+// tile: 1 = 64 x 64 (four wavefronts); 128 x 128 (np a multiple of 128 only)
+// with 2 = sixteen wavefronts of 32 x 32, 3 = eight of 64 x 32, 4 = eight of
+// 32 x 64, 5 = four of 64 x 64 (fewer LDS fragment reads per matrix
+// instruction, fewer wavefronts to cover stalls); 0 = 2 where allowed from
+// np = 512 up, else 1.
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                          hipStream_t s, int tile) {
   if (tile == 0) tile = (np % BM2 == 0 && np >= 512) ? 2 : 1;
-  if (tile == 2 && np % BM2 == 0) {
+  if (tile >= 2 && tile <= 5 && np % BM2 == 0) {
     const int tm = np / BM2, tn = np / BN2;
-    hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 4>), dim3(tm * tn, batch), dim3(64 * 16), 0, s, a, b,
-                       y, n, np, batch, tm, tn);
+    const dim3 grid(tm * tn, batch);
+    if (tile == 2)
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn);
+    else if (tile == 3)
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn);
+    else if (tile == 4)
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn);
+    else
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn);
   } else {
     const int tm = np / BM, tn = np / BN;
     hipLaunchKernelGGL(k_cgemm_bf16x3, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,

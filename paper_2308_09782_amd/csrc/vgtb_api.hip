@@ -1431,7 +1431,7 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   std::vector<int> gv;
   if (fmt == 2) {
     gv.push_back(1);
-    if (c->np % 128 == 0) gv.push_back(2);
+    if (c->np % 128 == 0) gv.insert(gv.end(), {2, 3, 4, 5});
   } else {
     gv = {1, 2, 3};
   }
@@ -1451,8 +1451,10 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
                                   tile);
     }, ms);
     if (st != VGTB_OK) break;
-    t.gemm_candidates[t.n_gemm] = tile;
-    t.gemm_ms[t.n_gemm++] = ms;
+    if (t.n_gemm < 8) {
+      t.gemm_candidates[t.n_gemm] = tile;
+      t.gemm_ms[t.n_gemm++] = ms;
+    }
     if (ms < best) {
       best = ms;
       t.gemm_tile = tile;

@@ -64,7 +64,7 @@ class VgtbTuning(ctypes.Structure):
     _fields_ = [("spmm_variant", ctypes.c_int32), ("gemm_tile", ctypes.c_int32),
                 ("n_spmm", ctypes.c_int32), ("n_gemm", ctypes.c_int32),
                 ("spmm_candidates", ctypes.c_int32 * 8), ("spmm_ms", ctypes.c_double * 8),
-                ("gemm_candidates", ctypes.c_int32 * 4), ("gemm_ms", ctypes.c_double * 4)]
+                ("gemm_candidates", ctypes.c_int32 * 8), ("gemm_ms", ctypes.c_double * 8)]
 
 
 class VgtbRequest(ctypes.Structure):

@@ -48,7 +48,7 @@ def _check_tuning(t, precision, norb, np_mult_128):
     want_spmm = ({-1, -2, -4} if norb == 4 else set()) | {1, 2}
     assert set(t["spmm_ms"]) == want_spmm
     if precision == "bf16x3":
-        assert set(t["gemm_ms"]) == ({1, 2} if np_mult_128 else {1})
+        assert set(t["gemm_ms"]) == ({1, 2, 3, 4, 5} if np_mult_128 else {1})
     else:
         assert set(t["gemm_ms"]) == {1, 2, 3}
 
