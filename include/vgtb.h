@@ -157,9 +157,10 @@ vgtb_status vgtb_create(const vgtb_system *sys, const vgtb_options *opt, void *d
  * electrons equally), form D_k(0) = sum_n f_n c_n c_n^dag on the device and
  * make it the current density (step index 0).  If z_ref was NULL, the
  * Mulliken charges of this density become Z.  min_gap_host (may be NULL)
- * receives the smallest HOMO-LUMO gap over k.  Returns VGTB_E_UNSTABLE if
- * |dt| times the largest spectral width over k is >= 1 (the density is
- * still set).  Synchronises the stream.
+ * receives the smallest HOMO-LUMO gap over k.  Leapfrog contexts: returns
+ * VGTB_E_UNSTABLE if |dt| times the largest spectral width over k is >= 1
+ * (the density is still set).  Synchronises the stream.  A Crank-Nicolson context keeps the
+ * occupied vectors C_nk (and their occupations) as its state instead.
  */
 vgtb_status vgtb_ground_state(vgtb_ctx *ctx, double *min_gap_host);
 
@@ -345,8 +346,8 @@ typedef enum {
  * densities, history and step index are unchanged.  The variants differ in
  * summation order only.  Needs a density (VGTB_E_STATE otherwise), reps >= 1
  * (VGTB_E_INVAL).  out_host may be NULL.  Synchronises the stream.  For a
- * context on the small-system path (whole steps per launch) nothing is timed
- * (n_spmm = n_gemm = 0).
+ * context on the small-system path (whole steps per launch) or with the
+ * Crank-Nicolson propagator nothing is timed (n_spmm = n_gemm = 0).
  */
 typedef struct {
   int32_t spmm_variant;          /* chosen sparse-product variant               */

@@ -170,3 +170,16 @@ def test_full_size_s_unitarity():
         s = oracle.overlap_k(sysm, sysm.kpts[ik])
         g = cs[ik].conj().T @ s @ cs[ik]
         assert np.abs(g - np.eye(len(cols))).max() < 1e-11
+
+
+def test_large_step_is_stable():
+    # |dt| times the spectral width above 1: the leapfrog context refuses it,
+    # Crank-Nicolson takes it and still matches its oracle.
+    sysm = vs.config_system("si8_k64")
+    sysm = sysm.with_kpts(sysm.kpts[::16])
+    dt = 2.0
+    with pkg.Propagator(sysm, dt, "fp64", history_capacity=4) as p:
+        with pytest.raises(pkg.VgtbError) as ei:
+            p.ground_state()
+        assert ei.value.status == 4
+    _from_ground_state(sysm, vs.kick_table(1, 0.05), dt, 200)
