@@ -30,7 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOAD = "asi512_k8_scc"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
 
 
 def parse():
@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3", "fp16x3"],
                     help="form measured as the headline value (reduced forms propagate the "
                          "deviation from the ground state)")
     ap.add_argument("--no-fp64-compare", action="store_true",
@@ -110,7 +110,8 @@ def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls", propag
     }
 
 
-KERNEL_SOURCES = {"fp64": "gemm_mfma.hip", "fp32": "gemm_mfma.hip", "bf16x3": "gemm_bf16x3.hip"}
+KERNEL_SOURCES = {"fp64": "gemm_mfma.hip", "fp32": "gemm_mfma.hip", "bf16x3": "gemm_bf16x3.hip",
+                  "fp16x3": "gemm_bf16x3.hip"}
 
 
 def counter_traffic(precision, workload):
@@ -192,8 +193,8 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
                 "traffic": counter_traffic(precision, workload) if coupling == "peierls" else None,
                 "flops_per_launch": flops_per_launch,
                 "avg_launch_ms": gemm_avg_s * 1e3}
-        if precision == "bf16x3":
-            # three bf16 products per real product: the matrix cores execute 3x the flops
+        if precision in ("bf16x3", "fp16x3"):
+            # three 16-bit products per real product: the matrix cores execute 3x the flops
             roof["mfma_issued_frac"] = 3.0 * achieved / peak
     else:
         # Small systems: whole blocks of steps per launch, FP64 vector arithmetic in LDS.
@@ -366,7 +367,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.accuracy:
-        forms = ["fp64"] + [p for p in ("bf16x3", "fp32") if p != "fp64"]
+        forms = ["fp64", "bf16x3", "fp16x3", "fp32"]
         print(json.dumps(accuracy_run(vg, torch, sysm, atab, dt, forms, cfg["n_steps"],
                                       args.workload)), flush=True)
         return 0
@@ -396,7 +397,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32 products, f64 state",
-                  "bf16x3": "bf16x3 products, f64 state"}[args.precision],
+                  "bf16x3": "bf16x3 products, f64 state",
+                  "fp16x3": "fp16x3 products, f64 state"}[args.precision],
         "data": "synthetic (seeded a-Si supercell, sp3 Slater-Koster blocks, sin^2 pulse)",
         "config": {"workload": f"{args.workload}: {sysm.n_atoms}-atom a-Si, {n} orbitals, "
                                f"{nk} k-points (2x2x2), SCC, sin^2 pulse, dt={dt}",

@@ -1,9 +1,12 @@
-// Batched complex GEMM Y = A * B with every operand split into two bf16
-// parts (x = x_hi + x_lo, x_hi = bf16(x), x_lo = bf16(x - x_hi)) and the
-// product formed as A_hi B_hi + A_hi B_lo + A_lo B_hi with FP32 accumulation
-// on the gfx950 bf16 matrix cores (v_mfma_f32_16x16x32_bf16): the reduced-
-// precision form of the dense product S_k^-1 W of Eq. 6.  The dropped
-// A_lo B_lo term and the split leave about 2^-17 relative error per product.
+// Batched complex GEMM Y = A * B with every operand split into two 16-bit
+// parts (x = x_hi + x_lo, x_hi = r(x), x_lo = r(x - x_hi)) and the product
+// formed as A_hi B_hi + A_hi B_lo + A_lo B_hi with FP32 accumulation on the
+// gfx950 matrix cores: the reduced-precision form of the dense product S_k^-1 W
+// of Eq. 6.  Element type E = 0: bf16 (v_mfma_f32_16x16x32_bf16; the split and
+// the dropped A_lo B_lo term leave about 2^-17 relative error per product);
+// E = 1: fp16 (v_mfma_f32_16x16x32_f16) on operands scaled by powers of two
+// sa[k], sb[k] into fp16's range, about 2^-21; the epilogue divides by
+// sa[k] sb[k] (exact).
 //
 // Operand storage (bf16 planes, p = re_hi, re_lo, im_hi, im_lo; np = padded N,
 // a multiple of 64, zero-filled beyond N):
@@ -21,23 +24,37 @@ namespace vgtb {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 packed bf16
 
+// Sign flip of eight packed 16-bit values (bf16 and fp16 keep the sign in bit 15).
 __device__ inline u32x4 negate8(u32x4 u) { return u ^ 0x80008000u; }
+template <int E>
 __device__ inline v4f mma(u32x4 a, u32x4 b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  if constexpr (E == 0)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+// 1 / (sa[k] sb[k]) for the fp16 form (powers of two), 1 for bf16.
+__device__ inline float unscale(const float *sa, const float *sb, int k) {
+  return sa ? 1.0f / (sa[k] * sb[k]) : 1.0f;
 }
 
 constexpr int BM = 64, BN = 64, BK = 32;   // workgroup tile; 4 wavefronts of 32x32
 constexpr int NT = 256;
 constexpr int APAD = 40;                    // bf16 per LDS row of A (32 + 8 pad)
 
+template <int E>
 __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict__ A,
                                                      const uint16_t *__restrict__ B,
                                                      float2 *__restrict__ Y, int n, int np,
-                                                     int batch_count, int tiles_m, int tiles_n) {
+                                                     int batch_count, int tiles_m, int tiles_n,
+                                                     const float *__restrict__ sa,
+                                                     const float *__restrict__ sb) {
   // LDS: A [plane][row][k] (padded rows), B [plane][k/8][col][8].
   __shared__ u32x4 As[4][BM][APAD / 8];
   __shared__ u32x4 Bs[4][BK / 8][BN];
@@ -107,19 +124,19 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
       for (int b = 0; b < 2; ++b) {
         v4f r = cr[a][b], m = ci[a][b];
         // Re += ar br - ai bi
-        r = mma(fa[a][0], fb[b][0], r);
-        r = mma(fa[a][0], fb[b][1], r);
-        r = mma(fa[a][1], fb[b][0], r);
-        r = mma(nih, fb[b][2], r);
-        r = mma(nih, fb[b][3], r);
-        r = mma(nil, fb[b][2], r);
+        r = mma<E>(fa[a][0], fb[b][0], r);
+        r = mma<E>(fa[a][0], fb[b][1], r);
+        r = mma<E>(fa[a][1], fb[b][0], r);
+        r = mma<E>(nih, fb[b][2], r);
+        r = mma<E>(nih, fb[b][3], r);
+        r = mma<E>(nil, fb[b][2], r);
         // Im += ar bi + ai br
-        m = mma(fa[a][0], fb[b][2], m);
-        m = mma(fa[a][0], fb[b][3], m);
-        m = mma(fa[a][1], fb[b][2], m);
-        m = mma(fa[a][2], fb[b][0], m);
-        m = mma(fa[a][2], fb[b][1], m);
-        m = mma(fa[a][3], fb[b][0], m);
+        m = mma<E>(fa[a][0], fb[b][2], m);
+        m = mma<E>(fa[a][0], fb[b][3], m);
+        m = mma<E>(fa[a][1], fb[b][2], m);
+        m = mma<E>(fa[a][2], fb[b][0], m);
+        m = mma<E>(fa[a][2], fb[b][1], m);
+        m = mma<E>(fa[a][3], fb[b][0], m);
         cr[a][b] = r;
         ci[a][b] = m;
       }
@@ -127,6 +144,7 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
   }
 
   float2 *Yb = Y + (size_t)batch * n * n;
+  const float us = unscale(sa, sb, batch);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -135,7 +153,8 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
       for (int j = 0; j < 4; ++j) {
         const int row = bm + wm0 + a * 16 + 4 * lg + j;
         const int col = bn + wn0 + b * 16 + lr;
-        if (row < n && col < n) Yb[(size_t)row * n + col] = make_float2(cr[a][b][j], ci[a][b][j]);
+        if (row < n && col < n)
+          Yb[(size_t)row * n + col] = make_float2(us * cr[a][b][j], us * ci[a][b][j]);
       }
 #undef VG_LOAD64
 }
@@ -151,12 +170,14 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
 //    the next plane's B fragments are read while the current plane's MFMAs run.
 constexpr int BM2 = 128, BN2 = 128;
 
-template <int WGM, int WGN>
+template <int E, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint16_t *__restrict__ A,
                                                                      const uint16_t *__restrict__ B,
                                                                      float2 *__restrict__ Y, int n,
                                                                      int np, int batch_count,
-                                                                     int tiles_m, int tiles_n) {
+                                                                     int tiles_m, int tiles_n,
+                                                                     const float *__restrict__ sa,
+                                                                     const float *__restrict__ sb) {
   constexpr int NT2 = 64 * WGM * WGN;
   constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
   constexpr int LD = 2048 / NT2;             // u32x4 per thread per operand and stage
@@ -240,10 +261,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
-        cr[a][b] = mma(fa[a][0], fb0[b], cr[a][b]);
-        ci[a][b] = mma(fa[a][2], fb0[b], ci[a][b]);
-        cr[a][b] = mma(fa[a][1], fb0[b], cr[a][b]);
-        ci[a][b] = mma(fa[a][3], fb0[b], ci[a][b]);
+        cr[a][b] = mma<E>(fa[a][0], fb0[b], cr[a][b]);
+        ci[a][b] = mma<E>(fa[a][2], fb0[b], ci[a][b]);
+        cr[a][b] = mma<E>(fa[a][1], fb0[b], cr[a][b]);
+        ci[a][b] = mma<E>(fa[a][3], fb0[b], ci[a][b]);
       }
     if (kt + 1 < nkt) {
       VG_STORE128(ra, rb, cur ^ 1);
@@ -255,8 +276,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
-        cr[a][b] = mma(fa[a][0], fb1[b], cr[a][b]);
-        ci[a][b] = mma(fa[a][2], fb1[b], ci[a][b]);
+        cr[a][b] = mma<E>(fa[a][0], fb1[b], cr[a][b]);
+        ci[a][b] = mma<E>(fa[a][2], fb1[b], ci[a][b]);
       }
     VG_READB(fb1, cur, 3);
     // B plane 2 (im_hi): Re -= Ai_hi Bi_hi + Ai_lo Bi_hi;  Im += Ar_hi Bi_hi + Ar_lo Bi_hi
@@ -264,18 +285,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
-        cr[a][b] = mma(nf2[a], fb0[b], cr[a][b]);
-        ci[a][b] = mma(fa[a][0], fb0[b], ci[a][b]);
-        cr[a][b] = mma(nf3[a], fb0[b], cr[a][b]);
-        ci[a][b] = mma(fa[a][1], fb0[b], ci[a][b]);
+        cr[a][b] = mma<E>(nf2[a], fb0[b], cr[a][b]);
+        ci[a][b] = mma<E>(fa[a][0], fb0[b], ci[a][b]);
+        cr[a][b] = mma<E>(nf3[a], fb0[b], cr[a][b]);
+        ci[a][b] = mma<E>(fa[a][1], fb0[b], ci[a][b]);
       }
     // B plane 3 (im_lo): Re -= Ai_hi Bi_lo;  Im += Ar_hi Bi_lo
 #pragma unroll
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
-        cr[a][b] = mma(nf2[a], fb1[b], cr[a][b]);
-        ci[a][b] = mma(fa[a][0], fb1[b], ci[a][b]);
+        cr[a][b] = mma<E>(nf2[a], fb1[b], cr[a][b]);
+        ci[a][b] = mma<E>(fa[a][0], fb1[b], ci[a][b]);
       }
     __syncthreads();
   };
@@ -297,6 +318,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
 #undef ACOL
 
   float2 *Yb = Y + (size_t)batch * n * n;
+  const float us = unscale(sa, sb, batch);
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -305,36 +327,48 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint1
       for (int j = 0; j < 4; ++j) {
         const int row = bm + wm0 + a * 16 + 4 * lg + j;
         const int col = bn + wn0 + b * 16 + lr;
-        if (row < n && col < n) Yb[(size_t)row * n + col] = make_float2(cr[a][b][j], ci[a][b][j]);
+        if (row < n && col < n)
+          Yb[(size_t)row * n + col] = make_float2(us * cr[a][b][j], us * ci[a][b][j]);
       }
 }
-
-}  // namespace
 
 // tile: 1 = 64 x 64 (four wavefronts); 128 x 128 (np a multiple of 128 only)
 // with 2 = sixteen wavefronts of 32 x 32, 3 = eight of 64 x 32, 4 = eight of
 // 32 x 64, 5 = four of 64 x 64 (fewer LDS fragment reads per matrix
 // instruction, fewer wavefronts to cover stalls); 0 = 2 where allowed from
 // np = 512 up, else 1.
-void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
-                         hipStream_t s, int tile) {
+template <int E>
+static void launch_e(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
+                     hipStream_t s, int tile, const float *sa, const float *sb) {
   if (tile == 0) tile = (np % BM2 == 0 && np >= 512) ? 2 : 1;
   if (tile >= 2 && tile <= 5 && np % BM2 == 0) {
     const int tm = np / BM2, tn = np / BN2;
     const dim3 grid(tm * tn, batch);
     if (tile == 2)
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn);
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
     else if (tile == 3)
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn);
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
     else if (tile == 4)
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn);
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
     else
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn);
+      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
   } else {
     const int tm = np / BM, tn = np / BN;
-    hipLaunchKernelGGL(k_cgemm_bf16x3, dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
-                       tm, tn);
+    hipLaunchKernelGGL((k_cgemm_bf16x3<E>), dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
+                       tm, tn, sa, sb);
   }
+}
+
+}  // namespace
+
+void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
+                         hipStream_t s, int tile) {
+  launch_e<0>(a, b, y, n, np, batch, s, tile, nullptr, nullptr);
+}
+
+void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
+                        const float *sa, const float *sb, hipStream_t s, int tile) {
+  launch_e<1>(a, b, y, n, np, batch, s, tile, sa, sb);
 }
 
 }  // namespace vgtb

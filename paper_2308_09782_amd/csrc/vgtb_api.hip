@@ -239,7 +239,7 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
   }
   if (!(std::fabs(vol) > 0.0) || !std::isfinite(vol)) { msg = "degenerate cell"; return VGTB_E_INVAL; }
   if (!std::isfinite(o->dt) || o->dt == 0.0) { msg = "dt must be finite and nonzero"; return VGTB_E_INVAL; }
-  if (o->precision < VGTB_FP64 || o->precision > VGTB_BF16X3) {
+  if (o->precision < VGTB_FP64 || o->precision > VGTB_FP16X3) {
     msg = "unknown precision";
     return VGTB_E_INVAL;
   }
@@ -345,7 +345,15 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->sinv_lo = cv.template take<char>(lo);
     c->w_lo = cv.template take<char>(lo);
     c->y_lo = cv.template take<float2>(n2);
-    c->w32 = (z.precision == VGTB_BF16X3) ? cv.template take<float2>(n2) : nullptr;
+    c->w32 = (z.precision == VGTB_BF16X3 || z.precision == VGTB_FP16X3) ? cv.template take<float2>(n2)
+                                                                         : nullptr;
+    if (z.precision == VGTB_FP16X3) {
+      c->scale_a = cv.template take<float>(z.nk);
+      c->scale_w = cv.template take<float>(z.nk);
+      c->scale_part = cv.template take<float>((size_t)z.nk * vgtb::f16_scale_parts());
+    } else {
+      c->scale_a = c->scale_w = c->scale_part = nullptr;
+    }
     c->tpart = cv.template take<double>((size_t)2 * z.nk * z.na);
     c->tfac = cv.template take<double>((size_t)2 * z.nk);
     c->trace0 = cv.template take<double>(z.nk);
@@ -354,6 +362,7 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->m0 = nullptr;
     c->sinv_lo = c->w_lo = nullptr;
     c->y_lo = c->w32 = nullptr;
+    c->scale_a = c->scale_w = c->scale_part = nullptr;
     c->tpart = c->tfac = c->trace0 = nullptr;
   }
   c->sm_part = z.small ? cv.template take<double>((size_t)vgtb::kSmallChunk * z.nk * z.na * 5) : nullptr;
@@ -385,6 +394,7 @@ struct SizeProbe {
   int *info, *flag;
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
+  float *scale_a, *scale_w, *scale_part;
   double *tpart, *tfac, *trace0;
   double2 *m0;
   double *sm_part, *ring;
@@ -536,6 +546,45 @@ void enqueue_step_cn(vgtb_ctx *c, hipStream_t s) {
   timed(c, VGTB_K_CN_UPDATE, [&] { vgtb::launch_cn_update(c->aug, cc, n, ns, nk, c->ctr, s); });
 }
 
+// Operand format of the reduced product: 1 complex64, 2 bf16 planes, 3 scaled
+// fp16 planes (0: FP64, no reduced product).
+int product_format(const vgtb_ctx *c) {
+  switch (c->precision) {
+    case VGTB_FP32: return 1;
+    case VGTB_BF16X3: return 2;
+    case VGTB_FP16X3: return 3;
+    default: return 0;
+  }
+}
+
+// Deviation form W = H D - H0 D0 in FP64, written in the product's operand
+// format (fp16: as complex64 into w32, then scaled and split into planes).
+void launch_deviation_spmm(vgtb_ctx *c, const double2 *dcur, int fmt, int variant, hipStream_t s) {
+  const int n = c->n, nk = c->nk;
+  if (fmt == 3) {
+    vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w32, 1, c->np, nullptr, variant, s);
+    vgtb::launch_f16_scale(c->w32, n, nk, c->scale_part, c->scale_w, s);
+    vgtb::launch_split_w_f16(c->w32, c->scale_w, static_cast<uint16_t *>(c->w_lo), n, c->np, nk, s);
+  } else {
+    vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32, variant, s);
+  }
+}
+
+// G = (S^-1 - I) W in the reduced format, into y_lo.
+void launch_reduced_product(vgtb_ctx *c, int fmt, int tile, hipStream_t s) {
+  const int n = c->n, nk = c->nk;
+  if (fmt == 1)
+    vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo), static_cast<const float2 *>(c->w_lo),
+                           c->y_lo, n, nk, s, tile);
+  else if (fmt == 2)
+    vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
+                              static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s, tile);
+  else
+    vgtb::launch_cgemm_f16x3(static_cast<const uint16_t *>(c->sinv_lo),
+                             static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, c->scale_a,
+                             c->scale_w, s, tile);
+}
+
 // The launches of one step at the current parity, on stream s.  With
 // may_time, each launch is bracketed by profiling events when enabled
 // (never while capturing).
@@ -577,20 +626,9 @@ void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
   // Deviation form: W = H D - H0 D0 in FP64 (C0 = H0 D0 kept from the
   // reference), rounded to the product's format; S^-1 W = W + (S^-1 - I) W
   // with only the second term in reduced precision.  The state D stays FP64.
-  const int fmt = c->precision == VGTB_FP32 ? 1 : 2;
-  run(VGTB_K_SPMM, [&] {
-    vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32,
-                      c->spmm_variant, s);
-  });
-  run(VGTB_K_GEMM, [&] {
-    if (fmt == 1)
-      vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
-                             static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s, c->gemm_tile);
-    else
-      vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
-                                static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s,
-                                c->gemm_tile);
-  });
+  const int fmt = product_format(c);
+  run(VGTB_K_SPMM, [&] { launch_deviation_spmm(c, dcur, fmt, c->spmm_variant, s); });
+  run(VGTB_K_GEMM, [&] { launch_reduced_product(c, fmt, c->gemm_tile, s); });
   const float2 *wid = fmt == 1 ? static_cast<const float2 *>(c->w_lo) : c->w32;
   const double2 *m0 = c->m0_active ? c->m0 : nullptr;
   run(VGTB_K_UPDATE, [&] {
@@ -757,6 +795,9 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->w_lo = dp.w_lo;
   c->y_lo = dp.y_lo;
   c->w32 = dp.w32;
+  c->scale_a = dp.scale_a;
+  c->scale_w = dp.scale_w;
+  c->scale_part = dp.scale_part;
   c->tpart = dp.tpart;
   c->tfac = dp.tfac;
   c->trace0 = dp.trace0;
@@ -844,9 +885,15 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
     if (info[k] != 0) return bail(VGTB_E_NOT_PD, "S_k is singular at k-point " + std::to_string(k));
   if (z.deviation) {
     // S^-1 in the reduced-precision operand format; W's padding stays zero.
-    const int fmt = z.precision == VGTB_FP32 ? 1 : 2;
-    vgtb::launch_convert_operand(dp.sinv, dp.sinv_lo, z.n, z.npad, z.nk, fmt, st_);
-    if (fmt == 2) {
+    const int fmt = z.precision == VGTB_FP32 ? 1 : (z.precision == VGTB_BF16X3 ? 2 : 3);
+    if (fmt == 3) {
+      vgtb::launch_f16_scale(dp.sinv, z.n, z.nk, true, dp.scale_part, dp.scale_a, st_);
+      vgtb::launch_split_a_f16(dp.sinv, dp.scale_a, static_cast<uint16_t *>(dp.sinv_lo), z.n, z.npad,
+                               z.nk, st_);
+    } else {
+      vgtb::launch_convert_operand(dp.sinv, dp.sinv_lo, z.n, z.npad, z.nk, fmt, st_);
+    }
+    if (fmt >= 2) {
       const size_t bytes = (size_t)4 * z.npad * z.npad * z.nk * sizeof(uint16_t);
       vgtb::launch_fill_zero(static_cast<double2 *>(dp.w_lo), bytes / sizeof(double2), st_);
     }
@@ -1387,7 +1434,7 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   }
   const int n = c->n, nk = c->nk;
   const bool dev = c->precision != VGTB_FP64;
-  const int fmt = !dev ? 0 : (c->precision == VGTB_FP32 ? 1 : 2);
+  const int fmt = product_format(c);
   hipStream_t s = c->stream;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
@@ -1417,8 +1464,8 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   for (int v : sv) {
     double ms = 0.0;
     st = time_it([&] {
-      vgtb::launch_spmm(c->g, dcur, dev ? c->d0 : nullptr, n, nk, c->hq, dev ? c->c0 : nullptr,
-                        dev ? c->w_lo : c->w, fmt, c->np, c->w32, v, s);
+      if (dev) launch_deviation_spmm(c, dcur, fmt, v, s);
+      else vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, c->np, nullptr, v, s);
     }, ms);
     if (st != VGTB_OK) break;
     if (t.n_spmm < 8) {
@@ -1431,7 +1478,7 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
     }
   }
   std::vector<int> gv;
-  if (fmt == 2) {
+  if (fmt >= 2) {
     gv.push_back(1);
     if (c->np % 128 == 0) gv.insert(gv.end(), {2, 3, 4, 5});
   } else {
@@ -1442,15 +1489,8 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
     if (st != VGTB_OK) break;
     double ms = 0.0;
     st = time_it([&] {
-      if (fmt == 0)
-        vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s, tile);
-      else if (fmt == 1)
-        vgtb::launch_cgemm_f32(static_cast<const float2 *>(c->sinv_lo),
-                               static_cast<const float2 *>(c->w_lo), c->y_lo, n, nk, s, tile);
-      else
-        vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
-                                  static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s,
-                                  tile);
+      if (fmt == 0) vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s, tile);
+      else launch_reduced_product(c, fmt, tile, s);
     }, ms);
     if (st != VGTB_OK) break;
     if (t.n_gemm < 8) {

@@ -192,6 +192,22 @@ void launch_cgemm_f32(const float2 *a, const float2 *b, float2 *c, int n, int ba
                       hipStream_t s, int tile = 0);
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                          hipStream_t s, int tile = 0);
+// The same product on fp16 planes scaled per k by sa[k] (A) and sb[k] (B).
+void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
+                        const float *sa, const float *sb, hipStream_t s, int tile = 0);
+
+// ---- launchers (split_f16.hip) ------------------------------------------------
+// Power-of-two scale per k putting max(|re|, |im|) in [2^13, 2^14); part holds
+// nk * f16_scale_parts() floats.
+int f16_scale_parts();
+void launch_f16_scale(const double2 *src, int n, int nk, bool minus_identity, float *part,
+                      float *scale, hipStream_t s);
+void launch_f16_scale(const float2 *src, int n, int nk, float *part, float *scale, hipStream_t s);
+// Scaled fp16 hi/lo planes: W in the product's k-packed B layout, S^-1 - I row-major.
+void launch_split_w_f16(const float2 *w, const float *scale, uint16_t *planes, int n, int np,
+                        int nk, hipStream_t s);
+void launch_split_a_f16(const double2 *sinv, const float *scale, uint16_t *planes, int n, int np,
+                        int nk, hipStream_t s);
 
 }  // namespace vgtb
 
@@ -248,7 +264,9 @@ struct vgtb_ctx {
   void *sinv_lo = nullptr;     // S^-1 as complex64 (n) or 4 bf16 planes (np)
   void *w_lo = nullptr;        // W in the same format
   float2 *y_lo = nullptr;      // nk * n * n, G = (S^-1 - I) W
-  float2 *w32 = nullptr;       // nk * n * n, W as complex64 (bf16 form; the fp32 form uses w_lo)
+  float2 *w32 = nullptr;       // nk * n * n, W as complex64 (bf16 and fp16 forms; the fp32 form uses w_lo)
+  float *scale_a = nullptr, *scale_w = nullptr;   // fp16 form: per-k scales of S^-1 - I and W
+  float *scale_part = nullptr; // fp16 form: nk * f16_scale_parts() partial maxima
   double *tpart = nullptr;     // 2 * nk * na
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk

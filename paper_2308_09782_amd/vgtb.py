@@ -19,7 +19,7 @@ VGTB_OK, VGTB_E_INVAL, VGTB_E_STATE, VGTB_E_NOT_PD, VGTB_E_UNSTABLE, VGTB_E_NOME
     VGTB_E_DEVICE, VGTB_E_NONFINITE = range(8)
 STATUS_NAMES = {0: "VGTB_OK", 1: "VGTB_E_INVAL", 2: "VGTB_E_STATE", 3: "VGTB_E_NOT_PD",
                 4: "VGTB_E_UNSTABLE", 5: "VGTB_E_NOMEM", 6: "VGTB_E_DEVICE", 7: "VGTB_E_NONFINITE"}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 COUPLINGS = {"peierls": 0, "momentum": 1}
 PROPAGATORS = {"leapfrog": 0, "crank_nicolson": 1}
 

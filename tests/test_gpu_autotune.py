@@ -14,7 +14,7 @@ pkg = pytest.importorskip("paper_2308_09782_amd")
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-9, "bf16x3": 1e-8}
+TOL = {"fp64": 1e-12, "fp32": 1e-9, "bf16x3": 1e-8, "fp16x3": 1e-9}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -47,13 +47,13 @@ def _check_tuning(t, precision, norb, np_mult_128):
     assert all(v > 0 for v in t["gemm_ms"].values())
     want_spmm = ({-1, -2, -4} if norb == 4 else set()) | {1, 2}
     assert set(t["spmm_ms"]) == want_spmm
-    if precision == "bf16x3":
+    if precision in ("bf16x3", "fp16x3"):
         assert set(t["gemm_ms"]) == ({1, 2, 3, 4, 5} if np_mult_128 else {1})
     else:
         assert set(t["gemm_ms"]) == {1, 2, 3}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_autotune_asi64(precision):
     c = vs.CONFIGS["asi64_k8_scc"]
     sysm = vs.config_system("asi64_k8_scc")

@@ -69,7 +69,7 @@ def _same(a, b):
             assert np.array_equal(a[key][q], b[key][q]), (key, q)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3", "fp16x3"])
 def test_graph_replay_bit_identical(monkeypatch, case, precision):
     sysm, dt, full = case
     with_graphs = _run(monkeypatch, True, sysm, dt, full, precision)

@@ -60,7 +60,7 @@ def c1_reference():
     return sysm, atab, c["dt"], c["n_steps"], ref, st
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_c1_mixed_current_within_tolerance(c1_reference, precision):
     sysm, atab, dt, n, ref, st = c1_reference
     h, cur, prev = run_gpu(sysm, atab, dt, n, precision)
@@ -74,7 +74,7 @@ def test_c1_mixed_current_within_tolerance(c1_reference, precision):
     assert np.abs(h["trace"] - sysm.n_electrons).max() < 1e-9
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_c2_mixed_scc_pulse(precision):
     c = vs.CONFIGS["asi64_k8_scc"]
     sysm = vs.config_system("asi64_k8_scc")
@@ -90,7 +90,7 @@ def test_c2_mixed_scc_pulse(precision):
     assert np.abs(h["q"] - ref["q"]).max() < 1e-5
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
 def test_ragged_padding_and_arbitrary_start(precision):
     """N = 52 (bf16 planes padded to 64), non-stationary start."""
     sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
@@ -106,6 +106,23 @@ def test_ragged_padding_and_arbitrary_start(precision):
     h, cur, _ = run_gpu(sysm, atab, 0.2, 400, precision, d0=np.stack(start))
     assert j_err(h, ref) < J_TOL
     assert rho_err(cur, st.d_cur) < 1e-4
+
+
+def test_fp16_split_is_more_accurate_than_bf16():
+    # Same product, same matrix-core rate: the scaled fp16 hi/lo split carries
+    # about four more bits per part than bf16, so the current error against
+    # the oracle drops several-fold.
+    c = vs.CONFIGS["asi64_k8_scc"]
+    sysm = vs.config_system("asi64_k8_scc")
+    n = 600
+    full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
+    atab = full[1500:1500 + n]
+    d0, z, _ = oracle.ground_state(sysm)
+    ref, _ = oracle.propagate(sysm, d0, atab, c["dt"], n, z=z)
+    e_bf = j_err(run_gpu(sysm, atab, c["dt"], n, "bf16x3")[0], ref)
+    e_fp = j_err(run_gpu(sysm, atab, c["dt"], n, "fp16x3")[0], ref)
+    print(f"J err bf16x3 {e_bf:.2e}, fp16x3 {e_fp:.2e}")
+    assert e_fp < e_bf / 4
 
 
 def test_rescale_holds_trace():

@@ -129,3 +129,17 @@ def test_crank_nicolson_options_validated_and_sized():
     cn = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, propagator="crank_nicolson"))
     n = s.n_orb
     assert cn - lf >= 2 * 16 * n * n * s.n_k
+
+
+def test_fp16_split_form_validated_and_sized():
+    _lib()
+    s = vs.config_system("asi64_k8_scc")
+    bad = pkg.make_options(0.2)
+    bad.precision = 4
+    _expect_inval(s, bad, match="precision")
+    _expect_inval(s, pkg.make_options(0.2, "fp16x3", propagator="crank_nicolson"), match="FP64 only")
+    # same operand planes as the bf16 split, plus per-k scales and their partial maxima
+    bf = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, "bf16x3"))
+    fp = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, "fp16x3"))
+    assert fp > bf
+    assert fp - bf < 4096 * s.n_k + 4096
