@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3", "fp16x3"],
+    ap.add_argument("--precision", default="fp16x3", choices=["fp64", "fp32", "bf16x3", "fp16x3"],
                     help="form measured as the headline value (reduced forms propagate the "
                          "deviation from the ground state)")
     ap.add_argument("--no-fp64-compare", action="store_true",
@@ -110,8 +110,8 @@ def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls", propag
     }
 
 
-KERNEL_SOURCES = {"fp64": "gemm_mfma.hip", "fp32": "gemm_mfma.hip", "bf16x3": "gemm_bf16x3.hip",
-                  "fp16x3": "gemm_bf16x3.hip"}
+KERNEL_SOURCES = {"fp64": "gemm_mfma.hip", "fp32": "gemm_mfma.hip", "bf16x3": "gemm_split16.hip",
+                  "fp16x3": "gemm_split16.hip"}
 
 
 def counter_traffic(precision, workload):
@@ -252,6 +252,7 @@ def accuracy_run(vg, torch, sysm, atab, dt, forms, n_steps, workload):
                 et, _ = prop.spectrum(ef, dt, omegas, 1.0, subtract_mean=False)
         runs[prec] = {"J": obs["J"][:, 0], "trace": obs["trace"], "jw": jt, "ew": et,
                       "value": sysm.n_k * n_steps / el, "seconds": el}
+        print(f"accuracy run: {prec} done in {el:.1f} s", file=sys.stderr, flush=True)
     ref = runs["fp64"]
     band = np.abs(ref["ew"]) >= 0.1 * np.abs(ref["ew"]).max()
     def absorption(r):

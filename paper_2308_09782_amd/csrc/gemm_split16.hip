@@ -49,7 +49,7 @@ constexpr int NT = 256;
 constexpr int APAD = 40;                    // bf16 per LDS row of A (32 + 8 pad)
 
 template <int E>
-__global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict__ A,
+__global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict__ A,
                                                      const uint16_t *__restrict__ B,
                                                      float2 *__restrict__ Y, int n, int np,
                                                      int batch_count, int tiles_m, int tiles_n,
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT) void k_cgemm_bf16x3(const uint16_t *__restrict_
 constexpr int BM2 = 128, BN2 = 128;
 
 template <int E, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_bf16x3_128(const uint16_t *__restrict__ A,
+__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint16_t *__restrict__ A,
                                                                      const uint16_t *__restrict__ B,
                                                                      float2 *__restrict__ Y, int n,
                                                                      int np, int batch_count,
@@ -345,16 +345,16 @@ static void launch_e(const uint16_t *a, const uint16_t *b, float2 *y, int n, int
     const int tm = np / BM2, tn = np / BN2;
     const dim3 grid(tm * tn, batch);
     if (tile == 2)
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
     else if (tile == 3)
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
     else if (tile == 4)
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
     else
-      hipLaunchKernelGGL((k_cgemm_bf16x3_128<E, 2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
   } else {
     const int tm = np / BM, tn = np / BN;
-    hipLaunchKernelGGL((k_cgemm_bf16x3<E>), dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
+    hipLaunchKernelGGL((k_cgemm_split16<E>), dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
                        tm, tn, sa, sb);
   }
 }

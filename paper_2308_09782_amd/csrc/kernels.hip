@@ -307,6 +307,20 @@ __device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
   hi = to_bf16(xf);
   lo = to_bf16(xf - from_bf16(hi));
 }
+// x sc = hi + lo with hi = f16(x sc), lo = f16(x sc - hi); sc a power of two
+// chosen so that the largest |x sc| of the matrix lies in [2^13, 2^14).
+__device__ inline void split_f16(double x, float sc, uint16_t &hi, uint16_t &lo) {
+  const float xs = (float)x * sc;
+  hi = __builtin_bit_cast(uint16_t, (_Float16)xs);
+  lo = __builtin_bit_cast(uint16_t, (_Float16)(xs - (float)__builtin_bit_cast(_Float16, hi)));
+}
+// Largest |re|, |im| the lanes of a wave have written, into *dst as float bits
+// (non-negative floats order like their bit patterns).  NaNs are skipped.
+__device__ inline void wave_max_to(float m, unsigned *dst) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(dst, __float_as_uint(m));
+}
 
 // Block-sparse product W = H_k D_k (Eqs. 8-10) over the pair blocks
 //   H_k(I,J) = sum_images exp(i(k+A/c).d) H0 + 1/2 (V_I + V_J) S_k(I,J)
@@ -324,11 +338,14 @@ __device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
 //   2: four bf16 planes (re_hi, re_lo, im_hi, im_lo), k-packed with padded
 //      size np: W[r][c] at ((r/8)*np + c)*8 + r%8 of each plane; plus a
 //      complex64 copy (w32) for the identity part of S^-1 W.
+//   3: as 2 with fp16 planes of W wscale[k]; the largest |re|, |im| of each
+//      k-point also goes to wmax[k] (the caller checks that wscale[k] is the
+//      scale this maximum calls for and splits the k-point again if not).
 constexpr int kEntChunk = 8;
 
 template <int NO, int OUT>
 __device__ inline void store_rows(const double2 (&acc)[NO], int r0, int col, int k, int n, int np,
-                                  int nk, void *wout, float2 *w32) {
+                                  int nk, void *wout, float2 *w32, float sc, float &m) {
   const size_t base = (size_t)k * n * n;
   if (OUT == 0) {
     double2 *w = static_cast<double2 *>(wout);
@@ -348,8 +365,14 @@ __device__ inline void store_rows(const double2 (&acc)[NO], int r0, int col, int
     uint16_t h[4][NO];
 #pragma unroll
     for (int mu = 0; mu < NO; ++mu) {
-      split_bf16(acc[mu].x, h[0][mu], h[1][mu]);
-      split_bf16(acc[mu].y, h[2][mu], h[3][mu]);
+      if (OUT == 2) {
+        split_bf16(acc[mu].x, h[0][mu], h[1][mu]);
+        split_bf16(acc[mu].y, h[2][mu], h[3][mu]);
+      } else {
+        split_f16(acc[mu].x, sc, h[0][mu], h[1][mu]);
+        split_f16(acc[mu].y, sc, h[2][mu], h[3][mu]);
+        m = fmaxf(m, fmaxf(fabsf((float)acc[mu].x), fabsf((float)acc[mu].y)));
+      }
     }
     const size_t off = (size_t)k * np * np + ((size_t)(r0 >> 3) * np + col) * 8 + (r0 & 7);
     if (NO == 4) {
@@ -422,7 +445,9 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
                                               const double2 *__restrict__ hq,
                                               const double2 *__restrict__ c0,
                                               void *__restrict__ wout, int np, int nk,
-                                              float2 *__restrict__ w32) {
+                                              float2 *__restrict__ w32,
+                                              const float *__restrict__ wscale,
+                                              unsigned *__restrict__ wmax) {
   constexpr int E2 = NO * NO;
   constexpr int CP = kEntChunk * KG;           // pair blocks per chunk, at most
   __shared__ double2 hs[CP * E2];
@@ -503,6 +528,8 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
     }
     __syncthreads();
   }
+  const float sc = OUT == 3 ? wscale[k] : 1.0f;
+  float wm = 0.0f;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     if (col[c] >= n) continue;
@@ -519,10 +546,11 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
             out[mu].y -= cv.y;
           }
         }
-        store_rows<NO, OUT>(out, (I0 + il) * NO, col[c], k, n, np, nk, wout, w32);
+        store_rows<NO, OUT>(out, (I0 + il) * NO, col[c], k, n, np, nk, wout, w32, sc, wm);
       }
     }
   }
+  if (OUT == 3) wave_max_to(wm, wmax + k);
 }
 
 // The same product on the FP64 matrix cores (four orbitals per atom).  One
@@ -547,7 +575,9 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
                                                    int n, const double2 *__restrict__ hq,
                                                    const double2 *__restrict__ c0,
                                                    void *__restrict__ wout, int np, int nk,
-                                                   float2 *__restrict__ w32) {
+                                                   float2 *__restrict__ w32,
+                                                   const float *__restrict__ wscale,
+                                                   unsigned *__restrict__ wmax) {
   constexpr int E2 = 16;
   constexpr int CP = kEntChunk * KG;
   __shared__ double2 hs[CP * E2];
@@ -621,6 +651,8 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
     ec += kEntChunk;
   } while (ec < e1);
   const int mu = lane & 3;
+  const float sc = OUT == 3 ? wscale[k] : 1.0f;
+  float wm = 0.0f;
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     const int col = cw + cb * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
@@ -643,8 +675,14 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
         // bf16 planes: the four rows of the atom sit in lanes 4m..4m+3; lane 4m
         // gathers them and writes one 8-byte word per plane.
         uint16_t hv[4];
-        split_bf16(out.x, hv[0], hv[1]);
-        split_bf16(out.y, hv[2], hv[3]);
+        if (OUT == 2) {
+          split_bf16(out.x, hv[0], hv[1]);
+          split_bf16(out.y, hv[2], hv[3]);
+        } else {
+          split_f16(out.x, sc, hv[0], hv[1]);
+          split_f16(out.y, sc, hv[2], hv[3]);
+          if (ok) wm = fmaxf(wm, fmaxf(fabsf((float)out.x), fabsf((float)out.y)));
+        }
         uint16_t *w = static_cast<uint16_t *>(wout);
         const size_t plane = (size_t)nk * np * np;
         const size_t off = (size_t)k * np * np + ((size_t)(r >> 3) * np + col) * 8 + (r & 7);
@@ -661,6 +699,7 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  if (OUT == 3) wave_max_to(wm, wmax + k);
 }
 
 // ---- Small systems: a block of steps in one launch ---------------------------
@@ -1201,20 +1240,21 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
 template <int NO, bool DELTA, int OUT>
 static void spmm_launch(int threads, hipStream_t s, const PairGraph &g, const double2 *d,
                         const double2 *d0, int n, const double2 *hq, const double2 *c0, void *w,
-                        int np, int nk, float2 *w32, int cpt, int ncols) {
+                        int np, int nk, float2 *w32, int cpt, int ncols, const float *wscale,
+                        unsigned *wmax) {
   const int ng = g.n_groups;
   if (g.group_size == 8 && cpt == 1)
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 1>), dim3(blocks_for(ncols, threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
   else if (g.group_size == 4 && cpt == 2)
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 2>), dim3(blocks_for(ncols, 2 * threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
   else if (g.group_size == 4 && cpt == 1)
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 1>), dim3(blocks_for(ncols, threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
   else
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 2>), dim3(blocks_for(ncols, 2 * threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32);
+                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
 }
 
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource src,
@@ -1231,54 +1271,60 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource 
 template <bool DELTA, int OUT, int CB>
 static void spmm_mfma_launch_cb(hipStream_t s, const PairGraph &g, const double2 *d, int n,
                                 const double2 *hq, const double2 *c0, void *w, int np, int nk,
-                                float2 *w32, int ncols) {
+                                float2 *w32, int ncols, const float *wscale, unsigned *wmax) {
   const int nw = std::max(1, std::min(4, (ncols + 16 * CB - 1) / (16 * CB)));
   dim3 grid(blocks_for(ncols, 16 * CB * nw), g.n_groups, nk);
   if (g.group_size == 16)
     hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 16, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq,
-                       c0, w, np, nk, w32);
+                       c0, w, np, nk, w32, wscale, wmax);
   else if (g.group_size == 8)
     hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 8, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
-                       w, np, nk, w32);
+                       w, np, nk, w32, wscale, wmax);
   else
     hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 4, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
-                       w, np, nk, w32);
+                       w, np, nk, w32, wscale, wmax);
 }
 
 template <bool DELTA, int OUT>
 static void spmm_mfma_launch(hipStream_t s, const PairGraph &g, const double2 *d, int n,
                              const double2 *hq, const double2 *c0, void *w, int np, int nk,
-                             float2 *w32, int cb, int ncols) {
-  if (cb == 4) spmm_mfma_launch_cb<DELTA, OUT, 4>(s, g, d, n, hq, c0, w, np, nk, w32, ncols);
-  else if (cb == 2) spmm_mfma_launch_cb<DELTA, OUT, 2>(s, g, d, n, hq, c0, w, np, nk, w32, ncols);
-  else spmm_mfma_launch_cb<DELTA, OUT, 1>(s, g, d, n, hq, c0, w, np, nk, w32, ncols);
+                             float2 *w32, int cb, int ncols, const float *wscale, unsigned *wmax) {
+  if (cb == 4) spmm_mfma_launch_cb<DELTA, OUT, 4>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax);
+  else if (cb == 2) spmm_mfma_launch_cb<DELTA, OUT, 2>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax);
+  else spmm_mfma_launch_cb<DELTA, OUT, 1>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax);
 }
 
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, int variant, hipStream_t s, int ncols) {
+                 float2 *w32, int variant, hipStream_t s, int ncols, const float *wscale,
+                 unsigned *wmax) {
   if (ncols <= 0 || ncols > n) ncols = n;
   if (g.norb == 4 && variant < 0) {
     const int cb = -variant;
-    if (!d0) spmm_mfma_launch<false, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
-    else if (out_format == 0) spmm_mfma_launch<true, 0>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
-    else if (out_format == 1) spmm_mfma_launch<true, 1>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
-    else spmm_mfma_launch<true, 2>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols);
+#define VG_SPMM_MFMA(DL, OUT) spmm_mfma_launch<DL, OUT>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols, wscale, wmax)
+    if (!d0) VG_SPMM_MFMA(false, 0);
+    else if (out_format == 0) VG_SPMM_MFMA(true, 0);
+    else if (out_format == 1) VG_SPMM_MFMA(true, 1);
+    else if (out_format == 2) VG_SPMM_MFMA(true, 2);
+    else VG_SPMM_MFMA(true, 3);
+#undef VG_SPMM_MFMA
     return;
   }
   const int cpt = variant == 2 ? 2 : 1;
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
-#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt, ncols)
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt, ncols, wscale, wmax)
   if (g.norb == 4) {
     if (!d0) VG_SPMM(4, false, 0);
     else if (out_format == 0) VG_SPMM(4, true, 0);
     else if (out_format == 1) VG_SPMM(4, true, 1);
-    else VG_SPMM(4, true, 2);
+    else if (out_format == 2) VG_SPMM(4, true, 2);
+    else VG_SPMM(4, true, 3);
   } else {
     if (!d0) VG_SPMM(1, false, 0);
     else if (out_format == 0) VG_SPMM(1, true, 0);
     else if (out_format == 1) VG_SPMM(1, true, 1);
-    else VG_SPMM(1, true, 2);
+    else if (out_format == 2) VG_SPMM(1, true, 2);
+    else VG_SPMM(1, true, 3);
   }
 #undef VG_SPMM
 }

@@ -351,8 +351,12 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
       c->scale_a = cv.template take<float>(z.nk);
       c->scale_w = cv.template take<float>(z.nk);
       c->scale_part = cv.template take<float>((size_t)z.nk * vgtb::f16_scale_parts());
+      c->wmax = cv.template take<unsigned>(z.nk);
+      c->wflag = cv.template take<int>(z.nk);
     } else {
       c->scale_a = c->scale_w = c->scale_part = nullptr;
+      c->wmax = nullptr;
+      c->wflag = nullptr;
     }
     c->tpart = cv.template take<double>((size_t)2 * z.nk * z.na);
     c->tfac = cv.template take<double>((size_t)2 * z.nk);
@@ -363,6 +367,8 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->sinv_lo = c->w_lo = nullptr;
     c->y_lo = c->w32 = nullptr;
     c->scale_a = c->scale_w = c->scale_part = nullptr;
+    c->wmax = nullptr;
+    c->wflag = nullptr;
     c->tpart = c->tfac = c->trace0 = nullptr;
   }
   c->sm_part = z.small ? cv.template take<double>((size_t)vgtb::kSmallChunk * z.nk * z.na * 5) : nullptr;
@@ -395,6 +401,8 @@ struct SizeProbe {
   void *sinv_lo, *w_lo;
   float2 *y_lo, *w32;
   float *scale_a, *scale_w, *scale_part;
+  unsigned *wmax;
+  int *wflag;
   double *tpart, *tfac, *trace0;
   double2 *m0;
   double *sm_part, *ring;
@@ -562,9 +570,13 @@ int product_format(const vgtb_ctx *c) {
 void launch_deviation_spmm(vgtb_ctx *c, const double2 *dcur, int fmt, int variant, hipStream_t s) {
   const int n = c->n, nk = c->nk;
   if (fmt == 3) {
-    vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w32, 1, c->np, nullptr, variant, s);
-    vgtb::launch_f16_scale(c->w32, n, nk, c->scale_part, c->scale_w, s);
-    vgtb::launch_split_w_f16(c->w32, c->scale_w, static_cast<uint16_t *>(c->w_lo), n, c->np, nk, s);
+    // The planes are written with the previous step's scales; a k-point whose
+    // maximum calls for another scale is split again from the complex64 W.
+    vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, 3, c->np, c->w32, variant, s, 0,
+                      c->scale_w, c->wmax);
+    vgtb::launch_f16_scale_check(c->wmax, c->scale_w, c->wflag, nk, s);
+    vgtb::launch_split_w_f16(c->w32, c->scale_w, static_cast<uint16_t *>(c->w_lo), n, c->np, nk,
+                             c->wflag, s);
   } else {
     vgtb::launch_spmm(c->g, dcur, c->d0, n, nk, c->hq, c->c0, c->w_lo, fmt, c->np, c->w32, variant, s);
   }
@@ -798,6 +810,8 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->scale_a = dp.scale_a;
   c->scale_w = dp.scale_w;
   c->scale_part = dp.scale_part;
+  c->wmax = dp.wmax;
+  c->wflag = dp.wflag;
   c->tpart = dp.tpart;
   c->tfac = dp.tfac;
   c->trace0 = dp.trace0;
@@ -888,6 +902,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
     const int fmt = z.precision == VGTB_FP32 ? 1 : (z.precision == VGTB_BF16X3 ? 2 : 3);
     if (fmt == 3) {
       vgtb::launch_f16_scale(dp.sinv, z.n, z.nk, true, dp.scale_part, dp.scale_a, st_);
+      vgtb::launch_f16_scale_init(dp.wmax, dp.scale_w, z.nk, st_);
       vgtb::launch_split_a_f16(dp.sinv, dp.scale_a, static_cast<uint16_t *>(dp.sinv_lo), z.n, z.npad,
                                z.nk, st_);
     } else {

@@ -117,13 +117,15 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource 
                      const double2 *ppk, hipStream_t s);
 // W = H D (d0 == null) or W = H D - C0 (d0 != null marks the deviation form);
 // out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np)
-// + complex64 copy w32.  variant: -1, -2, -4 = FP64 matrix cores with that
+// + complex64 copy w32, 3 fp16 planes of W wscale[k] + w32, with the largest
+// |re|, |im| of each k-point raised into wmax[k] (float bits; zero it first).  variant: -1, -2, -4 = FP64 matrix cores with that
 // many 16-column slices per wave (four orbitals per atom only); 1, 2 = vector
 // FMAs with that many columns per thread.  ncols (0 = n): only the first
 // ncols columns of W are formed (at least those; the rest are left as they were).
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
                  const double2 *hq, const double2 *c0, void *w, int out_format, int np,
-                 float2 *w32, int variant, hipStream_t s, int ncols = 0);
+                 float2 *w32, int variant, hipStream_t s, int ncols = 0,
+                 const float *wscale = nullptr, unsigned *wmax = nullptr);
 // ctr (may be null): advanced by one when the update has run.
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, int64_t *ctr, hipStream_t s);
@@ -184,7 +186,7 @@ void launch_zgemm_strided(const double2 *a, int lda, size_t sa, const double2 *b
                           size_t sb, double2 *c, int ldc, size_t sc, int m, int n, int k,
                           double alpha, bool beta_one, int batch, hipStream_t s);
 
-// ---- launchers (gemm_mfma.hip, gemm_bf16x3.hip) ------------------------------
+// ---- launchers (gemm_mfma.hip, gemm_split16.hip) ------------------------------
 // tile: workgroup tile shape (0 = the size rule; see the definitions).
 void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int batch,
                       hipStream_t s, int tile = 0);
@@ -202,10 +204,15 @@ void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, 
 int f16_scale_parts();
 void launch_f16_scale(const double2 *src, int n, int nk, bool minus_identity, float *part,
                       float *scale, hipStream_t s);
-void launch_f16_scale(const float2 *src, int n, int nk, float *part, float *scale, hipStream_t s);
-// Scaled fp16 hi/lo planes: W in the product's k-packed B layout, S^-1 - I row-major.
+// Sets scale[k] to the scale the maximum wmax[k] (float bits, as the sparse
+// product leaves it) calls for, flag[k] to whether it changed, and zeroes wmax.
+void launch_f16_scale_check(unsigned *wmax, float *scale, int *flag, int nk, hipStream_t s);
+// wmax = 0, scale = 1 for every k (before the first sparse product).
+void launch_f16_scale_init(unsigned *wmax, float *scale, int nk, hipStream_t s);
+// Scaled fp16 hi/lo planes: W in the product's k-packed B layout (only the
+// k-points with flag[k] != 0 when flag is given), S^-1 - I row-major.
 void launch_split_w_f16(const float2 *w, const float *scale, uint16_t *planes, int n, int np,
-                        int nk, hipStream_t s);
+                        int nk, const int *flag, hipStream_t s);
 void launch_split_a_f16(const double2 *sinv, const float *scale, uint16_t *planes, int n, int np,
                         int nk, hipStream_t s);
 
@@ -267,6 +274,8 @@ struct vgtb_ctx {
   float2 *w32 = nullptr;       // nk * n * n, W as complex64 (bf16 and fp16 forms; the fp32 form uses w_lo)
   float *scale_a = nullptr, *scale_w = nullptr;   // fp16 form: per-k scales of S^-1 - I and W
   float *scale_part = nullptr; // fp16 form: nk * f16_scale_parts() partial maxima
+  unsigned *wmax = nullptr;    // fp16 form: per-k largest |re|, |im| of W (float bits)
+  int *wflag = nullptr;        // fp16 form: per-k, W's scale changed at this step
   double *tpart = nullptr;     // 2 * nk * na
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk
