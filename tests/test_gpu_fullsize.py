@@ -62,7 +62,7 @@ def _one_step(sysm, d0, a, precision):
     return cols, rows
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3", "bf16x3", "fp32"])
 def test_first_step_sampled_columns(c3, precision):
     sysm, d0, a, ref = c3
     cols, rows = _one_step(sysm, d0, a, precision)
@@ -78,7 +78,7 @@ def test_first_step_sampled_columns(c3, precision):
         assert np.array_equal(rows[ik], np.conj(cols[ik].T))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3", "bf16x3"])
 def test_ground_state_properties_full_size(precision):
     sysm = vs.config_system("asi512_k8_scc")
     n = 20

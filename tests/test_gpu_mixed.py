@@ -139,16 +139,20 @@ def test_rescale_holds_trace():
     assert drift_off.max() >= drift_on[50::50].max()
 
 
-def test_mixed_checkpoint_resume_bitwise():
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+def test_mixed_checkpoint_resume_bitwise(precision):
+    # fp16x3: the resumed context starts from scale 1, so its first step splits W
+    # again with the scale W's maximum calls for; the planes, and so every later
+    # step, must be those of the uninterrupted run.
     sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
     atab = vs.sin2_pulse_table(400, 0.2, 0.1, 60.0, 0.3)
-    h, full, _ = run_gpu(sysm, atab, 0.2, 300, "bf16x3", rescale_every=50)
-    with pkg.Propagator(sysm, 0.2, "bf16x3", rescale_every=50, history_capacity=300) as p:
+    h, full, _ = run_gpu(sysm, atab, 0.2, 300, precision, rescale_every=50)
+    with pkg.Propagator(sysm, 0.2, precision, rescale_every=50, history_capacity=300) as p:
         p.ground_state()
         p.set_field_table(atab)
         p.step(130)
         blob = p.save_state()
-    with pkg.Propagator(sysm, 0.2, "bf16x3", rescale_every=50, history_capacity=300) as p:
+    with pkg.Propagator(sysm, 0.2, precision, rescale_every=50, history_capacity=300) as p:
         p.ground_state()
         p.set_field_table(atab)
         p.load_state(blob)

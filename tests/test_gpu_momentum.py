@@ -72,13 +72,14 @@ def test_kick_8_atoms_fp64_1000_steps():
     _compare(sysm, vs.kick_table(1, c["a0"]), c["dt"], 1000)
 
 
-def test_scc_pulse_64_atoms_fp64_and_bf16x3():
+def test_scc_pulse_64_atoms_fp64_and_split_forms():
     c = vs.CONFIGS["asi64_k8_scc"]
     sysm = vs.config_system("asi64_k8_scc")
     full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
     atab = full[1500:1900]
     _compare(sysm, atab, c["dt"], 400)
     _compare(sysm, atab, c["dt"], 400, precision="bf16x3", j_tol=1e-5, rho_tol=None)
+    _compare(sysm, atab, c["dt"], 400, precision="fp16x3", j_tol=1e-5, rho_tol=None)
 
 
 def test_ragged_nonstationary_start():

@@ -95,7 +95,7 @@ def asi64_case():
     return sysm, c["dt"], full[1500:1560], 60
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3", 1e-8)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3", 1e-8), ("fp16x3", 1e-8)])
 def test_variants_agree_asi64(monkeypatch, asi64_case, precision, tol):
     sysm, dt, atab, n = asi64_case
     base_h, base_d, _ = _run(monkeypatch, VARIANTS[0], sysm, dt, atab, n, precision=precision)
