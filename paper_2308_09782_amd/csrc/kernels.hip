@@ -913,51 +913,61 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_steps(const double *_
 }
 
 // Leapfrog (Eq. 13) in the form D_out = D_base - i fac (Y - Y^dag), Y = S^-1 H D,
-// so that dD/dt = -i (Y - Y^dag) is anti-Hermitian bit for bit.  32x32 tiles;
-// the transposed partner tile of Y is staged through LDS.
+// so that dD/dt = -i (Y - Y^dag) is anti-Hermitian bit for bit.  One workgroup
+// takes the pair of 32x32 tiles (I, J), (J, I) with I <= J: both tiles of Y are
+// staged in LDS once and both tiles of D_out are written from them, so every
+// element of Y (and W) is read once per step.  D_out may be D_base (each
+// element is read and written by the same thread).
 // SPLIT: the product is Y = W + G with G = (S^-1 - I) W computed separately;
 // both are complex64 and are summed in FP64 here.
 // m0 (may be null): a constant term -i X0 added as fac * m0, where
 // X0 = S^-1 H0 D0 - D0 H0 S^-1 is the part of dD/dt the deviation form leaves
 // out when the reference density D0 is not stationary.
+// Y at rows r0 + ty + 8q, column c0 + tx (q = 0..3) into v; zero outside n.
 template <typename YT, bool SPLIT>
-__global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
-                                                const float2 *__restrict__ wsplit,
-                                                const double2 *__restrict__ m0,
-                                                const double2 *dbase, double2 *dout, int n,
-                                                double fac, int64_t *ctr) {
-  __shared__ double2 tt[32][33];
-  const int k = blockIdx.z;
-  const size_t base = (size_t)k * n * n;
-  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+__device__ inline void update_load(const YT *__restrict__ y, const float2 *__restrict__ wsplit,
+                                   size_t base, int n, int r0, int c0, double2 (&v)[4]) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int row = bj + r, c = bi + tx;
-    double2 t = make_double2(0.0, 0.0);
-    if (row < n && c < n) {
-      const YT v = y[base + (size_t)row * n + c];
-      t = make_double2((double)v.x, (double)v.y);
-      if (SPLIT) {
-        const float2 wv = wsplit[base + (size_t)row * n + c];
-        t.x += (double)wv.x;
-        t.y += (double)wv.y;
-      }
+  const int c = c0 + tx;
+  YT yv[4];
+  float2 wv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = r0 + ty + 8 * q;
+    const bool in = row < n && c < n;
+    const size_t idx = base + (size_t)(in ? row : 0) * n + (in ? c : 0);
+    yv[q] = y[idx];
+    if (SPLIT) wv[q] = wsplit[idx];
+    if (!in) {
+      yv[q].x = 0;
+      yv[q].y = 0;
+      if (SPLIT) wv[q] = make_float2(0.0f, 0.0f);
     }
-    tt[r][tx] = t;
   }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int i = bi + r, j = bj + tx;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = make_double2((double)yv[q].x, (double)yv[q].y);
+    if (SPLIT) {
+      v[q].x += (double)wv[q].x;
+      v[q].y += (double)wv[q].y;
+    }
+  }
+}
+
+// Rows r0.., columns c0.. of D_out from `own` (this tile of Y) and `other`
+// (the tile at the mirrored position: other[c][r] = Y[c0 + c][r0 + r]).
+__device__ inline void update_store(const double2 (*own)[33], const double2 (*other)[33],
+                                    const double2 *__restrict__ m0, const double2 *dbase,
+                                    double2 *dout, size_t base, int n, int r0, int c0, double fac) {
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int i = r0 + r, j = c0 + tx;
     if (i < n && j < n) {
       const size_t idx = base + (size_t)i * n + j;
-      const YT yr = y[idx];
-      double2 yv = make_double2((double)yr.x, (double)yr.y);
-      if (SPLIT) {
-        const float2 wv = wsplit[idx];
-        yv.x += (double)wv.x;
-        yv.y += (double)wv.y;
-      }
-      const double2 yt = tt[tx][r];            // Y[j][i]
+      const double2 yv = own[r][tx];
+      const double2 yt = other[tx][r];         // Y[j][i]
       const double xr = yv.x - yt.x;           // X = Y - conj(Y^T)
       const double xi = yv.y + yt.y;
       const double2 b = dbase[idx];
@@ -970,6 +980,38 @@ __global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
       dout[idx] = o;
     }
   }
+}
+
+template <typename YT, bool SPLIT>
+__global__ __launch_bounds__(256) void k_update(const YT *__restrict__ y,
+                                                const float2 *__restrict__ wsplit,
+                                                const double2 *__restrict__ m0,
+                                                const double2 *dbase, double2 *dout, int n,
+                                                double fac, int64_t *ctr) {
+  __shared__ double2 ta[32][33], tb[32][33];   // Y(I, J), Y(J, I)
+  const int k = blockIdx.z;
+  const size_t base = (size_t)k * n * n;
+  // Pair p = tj (tj + 1) / 2 + ti with ti <= tj.
+  const int p = blockIdx.x;
+  int tj = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+  while ((tj + 1) * (tj + 2) / 2 <= p) ++tj;
+  while (tj * (tj + 1) / 2 > p) --tj;
+  const int ti = p - tj * (tj + 1) / 2;
+  const int bi = ti * 32, bj = tj * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  double2 va[4], vb[4];
+  // All global loads of both tiles are issued before the first LDS write.
+  update_load<YT, SPLIT>(y, wsplit, base, n, bi, bj, va);
+  if (ti != tj) update_load<YT, SPLIT>(y, wsplit, base, n, bj, bi, vb);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ta[ty + 8 * q][tx] = va[q];
+  if (ti != tj) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tb[ty + 8 * q][tx] = vb[q];
+  }
+  __syncthreads();
+  update_store(ta, ti != tj ? tb : ta, m0, dbase, dout, base, n, bi, bj, fac);
+  if (ti != tj) update_store(tb, ta, m0, dbase, dout, base, n, bj, bi, fac);
   // The step is done once this kernel has run: advance the device step index
   // (no other thread of this kernel reads it).
   if (ctr != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
@@ -1329,23 +1371,29 @@ void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
 #undef VG_SPMM
 }
 
+// Tile pairs (I <= J) of 32x32 tiles: one workgroup each.
+static int update_pairs(int n) {
+  const int t = blocks_for(n, 32);
+  return t * (t + 1) / 2;
+}
+
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, int64_t *ctr, hipStream_t s) {
-  dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
+  dim3 grid(update_pairs(n), 1, nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
                      (const double2 *)nullptr, dbase, dout, n, fac, ctr);
 }
 
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
                          double2 *dout, int n, int nk, double fac, int64_t *ctr, hipStream_t s) {
-  dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
+  dim3 grid(update_pairs(n), 1, nk);
   hipLaunchKernelGGL((k_update<float2, true>), grid, dim3(256), 0, s, g, w, m0, dbase, dout, n, fac,
                      ctr);
 }
 
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s) {
-  dim3 grid(blocks_for(n, 32), blocks_for(n, 32), nk);
+  dim3 grid(update_pairs(n), 1, nk);
   hipLaunchKernelGGL((k_update<double2, false>), grid, dim3(256), 0, s, y, (const float2 *)nullptr,
                      (const double2 *)nullptr, dbase, dout, n, 1.0, (int64_t *)nullptr);
 }
