@@ -68,6 +68,11 @@ def parse():
     ap.add_argument("--accuracy", action="store_true",
                     help="instead of timing: run the workload's full step count in the reduced "
                          "forms and in FP64 and report the current and spectrum errors")
+    ap.add_argument("--kick", type=float, default=None, metavar="A0",
+                    help="drive the workload's system with a delta kick A(t >= 0) = A0 x "
+                         "instead of its own drive (accuracy runs: absorption over the whole grid)")
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="step count of the accuracy runs (default: the workload's)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(read N, write N): the reference kernel for hardware byte counters")
@@ -259,13 +264,20 @@ def accuracy_run(vg, torch, sysm, atab, dt, forms, n_steps, workload):
         return 4.0 * np.pi * np.real(r["jw"][band] / r["ew"][band]) / omegas[band]
     a_ref = absorption(ref)
     jmax = np.abs(ref["J"]).max()
+
+    def peaks(a, m=3):
+        """The m largest local maxima of the absorption in the band (their omega, Ha)."""
+        w = omegas[band]
+        idx = [i for i in range(1, a.size - 1) if a[i] >= a[i - 1] and a[i] > a[i + 1]]
+        return sorted(float(w[i]) for i in sorted(idx, key=lambda i: -a[i])[:m])
     out = {"metric": f"accuracy of the reduced forms against FP64, full {n_steps}-step run",
            "workload": workload, "steps": n_steps, "dt": dt,
            "omega_band_ha": [float(omegas[band].min()), float(omegas[band].max())],
            "fp64": {"k_steps_per_s": ref["value"], "seconds": ref["seconds"],
                     "trace_drift": float(np.abs(ref["trace"] - sysm.n_electrons).max()),
                     "peak_omega_ha": float(omegas[np.argmax(np.abs(ref["jw"]))]),
-                    "absorption_peak_omega_ha": float(omegas[band][np.argmax(a_ref)])}}
+                    "absorption_peak_omega_ha": float(omegas[band][np.argmax(a_ref)]),
+                    "absorption_peaks_ha": peaks(a_ref)}}
     for prec in forms:
         if prec == "fp64":
             continue
@@ -281,6 +293,7 @@ def accuracy_run(vg, torch, sysm, atab, dt, forms, n_steps, workload):
             "peak_height_rel_err": float(abs(abs(r["jw"][ip]) - abs(ref["jw"][ip])) / abs(ref["jw"][ip])),
             "absorption_err_in_band": float(np.abs(a - a_ref).max() / np.abs(a_ref).max()),
             "absorption_peak_omega_ha": float(omegas[band][np.argmax(a)]),
+            "absorption_peaks_ha": peaks(a),
         }
     return out
 
@@ -357,7 +370,9 @@ def main():
     cfg = vs.CONFIGS[args.workload]
     sysm = vs.config_system(args.workload)
     dt = cfg["dt"]
-    if cfg["drive"] == "pulse":
+    if args.kick is not None:
+        atab = vs.kick_table(1, args.kick)
+    elif cfg["drive"] == "pulse":
         atab = vs.sin2_pulse_table(cfg["n_steps"], dt, cfg["omega"], cfg["t_fs"] * vs.FS_AU, cfg["a_peak"])
     else:
         atab = vs.kick_table(1, cfg["a0"])
@@ -369,8 +384,9 @@ def main():
         del src, dst
     if args.accuracy:
         forms = ["fp64", "bf16x3", "fp16x3", "fp32"]
-        print(json.dumps(accuracy_run(vg, torch, sysm, atab, dt, forms, cfg["n_steps"],
-                                      args.workload)), flush=True)
+        label = args.workload + (f", kick A0 = {args.kick}" if args.kick is not None else "")
+        print(json.dumps(accuracy_run(vg, torch, sysm, atab, dt, forms,
+                                      args.accuracy_steps or cfg["n_steps"], label)), flush=True)
         return 0
     total = args.warmup + args.steps
     # Warmup and timed steps sit in the middle of the pulse, where A is large.
