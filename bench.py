@@ -9,8 +9,9 @@ Peierls assembly of the pair blocks, block-sparse H D and dense S^-1 (H D)
 on the matrix cores, and the leapfrog update.  Inputs are seeded synthetic stand-ins of
 the paper's a-Si structure (no dataset is read).
 
-Prints one JSON line: k-steps/s of the 3xBF16 deviation form over the timed
-steps, the same steps in plain FP64 (speed-up and the current's deviation
+Prints one JSON line: k-steps/s of the FP16X3 deviation form (three fp16
+matrix-core products of power-of-two scaled hi/lo splits; --precision selects
+another form) over the timed steps, the same steps in plain FP64 (speed-up and the current's deviation
 from the FP64 run), the roofline of the dominant kernel (event-timed inside
 the library on the stream it runs on), and the FP64 CPU oracle timed on a
 bounded sample on this host.

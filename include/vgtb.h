@@ -342,7 +342,8 @@ typedef enum {
  *   - the dense product S^-1 W: workgroup tiles 1 = 32x32, 2 = 64x64,
  *     3 = 128x64 (FP64 and FP32 forms); 1 = 64x64, and 128x128 as 2 = 16
  *     wavefronts of 32x32, 3 = 8 of 64x32, 4 = 8 of 32x64, 5 = 4 of 64x64
- *     (3xBF16; the 128x128 shapes when the padded size is a multiple of 128),
+ *     (3xBF16 and FP16X3; the 128x128 shapes when the padded size is a
+ *     multiple of 128),
  * each launched `reps` times after one warm-up launch, and keeps the fastest
  * of each for the following steps.  Only scratch buffers are written: the
  * densities, history and step index are unchanged.  The variants differ in
