@@ -8,7 +8,7 @@
 // sa[k], sb[k] into fp16's range, about 2^-21; the epilogue divides by
 // sa[k] sb[k] (exact).
 //
-// Operand storage (bf16 planes, p = re_hi, re_lo, im_hi, im_lo; np = padded N,
+// Operand storage (16-bit planes, p = re_hi, re_lo, im_hi, im_lo; np = padded N,
 // a multiple of 64, zero-filled beyond N):
 //   A: plane p, batch k: row-major np x np            (A[i][kk] at i*np + kk)
 //   B: plane p, batch k: k-packed (np/8) x np x 8     (B[kk][j] at ((kk/8)*np + j)*8 + kk%8)
@@ -26,7 +26,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 packed bf16
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 packed 16-bit values
 
 // Sign flip of eight packed 16-bit values (bf16 and fp16 keep the sign in bit 15).
 __device__ inline u32x4 negate8(u32x4 u) { return u ^ 0x80008000u; }
@@ -46,7 +46,7 @@ __device__ inline float unscale(const float *sa, const float *sb, int k) {
 
 constexpr int BM = 64, BN = 64, BK = 32;   // workgroup tile; 4 wavefronts of 32x32
 constexpr int NT = 256;
-constexpr int APAD = 40;                    // bf16 per LDS row of A (32 + 8 pad)
+constexpr int APAD = 40;                    // 16-bit values per LDS row of A (32 + 8 pad)
 
 template <int E>
 __global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict__ A,
