@@ -125,6 +125,46 @@ def test_fp16_split_is_more_accurate_than_bf16():
     assert e_fp < e_bf / 4
 
 
+def test_fp16x3_exactly_stationary_when_w_vanishes():
+    # No SCC shift and A = 0: H equals H0 and D stays D(0), so W = H D - H0 D(0)
+    # is exactly zero (the same kernel forms both products); its maximum is zero,
+    # the split keeps scale 1, and the density must stay D(0) bit for bit.
+    sysm = vs.diamond_supercell(1, (2, 2, 2), seed=1001)
+    assert sysm.gamma is None
+    n = 30
+    with pkg.Propagator(sysm, 0.2, "fp16x3", history_capacity=n) as p:
+        p.ground_state()
+        d_init = p.get_density(0).cpu().numpy()
+        p.set_field_table(vs.kick_table(1, 0.0))
+        p.step(n)
+        h = p.read_observables(0, n)
+        d_end = p.get_density(0).cpu().numpy()
+        d_prev = p.get_density(1).cpu().numpy()
+    assert np.array_equal(d_end, d_init)
+    assert np.array_equal(d_prev, d_init)
+    assert np.abs(h["J"]).max() < 1e-13
+
+
+def test_fp16x3_scale_follows_w_across_a_sudden_kick():
+    # 40 steps at A = 0 keep W at rounding level; then A jumps to 0.02 and W's
+    # maximum grows by many orders of magnitude in one step, so its per-k scale
+    # changes and the planes are split again from the complex64 W.  The whole
+    # trajectory must stay within the bar of the FP64 oracle.
+    sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
+    d0, z, _ = oracle.ground_state(sysm)
+    sysm = dataclasses.replace(sysm, z_ref=z)
+    n, quiet = 300, 40
+    atab = np.zeros((n, 3))
+    atab[quiet:, 0] = 0.02
+    ref, st = oracle.propagate(sysm, d0, atab, 0.2, n, z=z)
+    h, cur, _ = run_gpu(sysm, atab, 0.2, n, "fp16x3")
+    err = j_err(h, ref)
+    print(f"fp16x3 quiet-then-kick: J err {err:.2e}, rho err {rho_err(cur, st.d_cur):.2e}")
+    assert np.abs(ref["J"][:quiet]).max() < 1e-9 * np.abs(ref["J"]).max()
+    assert err < J_TOL
+    assert rho_err(cur, st.d_cur) < 1e-6
+
+
 def test_rescale_holds_trace():
     sysm = vs.config_system("asi64_k8_scc")
     c = vs.CONFIGS["asi64_k8_scc"]
