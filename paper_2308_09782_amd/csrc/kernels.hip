@@ -339,8 +339,8 @@ __device__ inline void wave_max_to(float m, unsigned *dst) {
 //      size np: W[r][c] at ((r/8)*np + c)*8 + r%8 of each plane; plus a
 //      complex64 copy (w32) for the identity part of S^-1 W.
 //   3: as 2 with fp16 planes of W wscale[k]; the largest |re|, |im| of each
-//      k-point also goes to wmax[k] (the caller checks that wscale[k] is the
-//      scale this maximum calls for and splits the k-point again if not).
+//      k-point also goes to its slots of wmax (the caller checks that wscale[k]
+//      is the scale this maximum calls for and splits the k-point again if not).
 constexpr int kEntChunk = 8;
 
 template <int NO, int OUT>
@@ -550,7 +550,10 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
       }
     }
   }
-  if (OUT == 3) wave_max_to(wm, wmax + k);
+  if (OUT == 3) {
+    const int slot = ((blockIdx.y * gridDim.x + blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kMaxSlots;
+    wave_max_to(wm, wmax + ((size_t)k * kMaxSlots + slot) * kMaxStride);
+  }
 }
 
 // The same product on the FP64 matrix cores (four orbitals per atom).  One
@@ -699,7 +702,10 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if (OUT == 3) wave_max_to(wm, wmax + k);
+  if (OUT == 3) {
+    const int slot = ((blockIdx.y * gridDim.x + blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kMaxSlots;
+    wave_max_to(wm, wmax + ((size_t)k * kMaxSlots + slot) * kMaxStride);
+  }
 }
 
 // ---- Small systems: a block of steps in one launch ---------------------------

@@ -8,9 +8,9 @@
 // The scale of W is a function of the current W alone, so no value can leave
 // fp16's range whatever the size of W at a given step: the sparse product
 // writes W's planes with the scale of the previous step and raises the per-k
-// maximum; the check below sets the scale that maximum calls for, and a
-// k-point whose scale changed (rare: W changes little from step to step) is
-// split again from the complex64 W.  The planes are thus the same as a split
+// maximum (spread over kMaxSlots slots); the check below sets the scale that
+// maximum calls for, and a k-point whose scale changed (rare: W changes little
+// from step to step) is split again from the complex64 W.  The planes are thus the same as a split
 // with the current maximum's scale.  The scale of S^-1 - I comes from block
 // partial maxima once, when the context is created.
 #include <hip/hip_runtime.h>
@@ -74,16 +74,21 @@ __global__ void k_scale_check(unsigned *__restrict__ wmax, float *__restrict__ s
                               int *__restrict__ flag, int nk) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nk) return;
-  const float sc = pow2_scale(__uint_as_float(wmax[k]));
+  unsigned *wk = wmax + (size_t)k * kMaxSlots * kMaxStride;
+  unsigned m = 0u;
+  for (int i = 0; i < kMaxSlots; ++i) {
+    m = max(m, wk[i * kMaxStride]);
+    wk[i * kMaxStride] = 0u;
+  }
+  const float sc = pow2_scale(__uint_as_float(m));
   flag[k] = sc != scale[k];
   scale[k] = sc;
-  wmax[k] = 0u;
 }
 
 __global__ void k_scale_init(unsigned *__restrict__ wmax, float *__restrict__ scale, int nk) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nk) return;
-  wmax[k] = 0u;
+  for (int i = 0; i < kMaxSlots; ++i) wmax[((size_t)k * kMaxSlots + i) * kMaxStride] = 0u;
   scale[k] = 1.0f;
 }
 

@@ -351,7 +351,7 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
       c->scale_a = cv.template take<float>(z.nk);
       c->scale_w = cv.template take<float>(z.nk);
       c->scale_part = cv.template take<float>((size_t)z.nk * vgtb::f16_scale_parts());
-      c->wmax = cv.template take<unsigned>(z.nk);
+      c->wmax = cv.template take<unsigned>((size_t)z.nk * vgtb::kMaxSlots * vgtb::kMaxStride);
       c->wflag = cv.template take<int>(z.nk);
     } else {
       c->scale_a = c->scale_w = c->scale_part = nullptr;

@@ -118,7 +118,8 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource 
 // W = H D (d0 == null) or W = H D - C0 (d0 != null marks the deviation form);
 // out_format: 0 complex128, 1 complex64, 2 bf16 planes (k-packed, padded np)
 // + complex64 copy w32, 3 fp16 planes of W wscale[k] + w32, with the largest
-// |re|, |im| of each k-point raised into wmax[k] (float bits; zero it first).  variant: -1, -2, -4 = FP64 matrix cores with that
+// |re|, |im| of each k-point raised into one of its kMaxSlots slots of wmax
+// (float bits; zero them first).  variant: -1, -2, -4 = FP64 matrix cores with that
 // many 16-column slices per wave (four orbitals per atom only); 1, 2 = vector
 // FMAs with that many columns per thread.  ncols (0 = n): only the first
 // ncols columns of W are formed (at least those; the rest are left as they were).
@@ -204,10 +205,14 @@ void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, 
 int f16_scale_parts();
 void launch_f16_scale(const double2 *src, int n, int nk, bool minus_identity, float *part,
                       float *scale, hipStream_t s);
-// Sets scale[k] to the scale the maximum wmax[k] (float bits, as the sparse
-// product leaves it) calls for, flag[k] to whether it changed, and zeroes wmax.
+// Per-k maximum of W as the sparse product leaves it: kMaxSlots slots per
+// k-point (float bits), kMaxStride words apart, so that the wavefronts' atomic
+// maxima spread over many L2 lines instead of meeting on one address.
+constexpr int kMaxSlots = 64, kMaxStride = 32;
+// Sets scale[k] to the scale the maximum over k's slots of wmax calls for,
+// flag[k] to whether it changed, and zeroes the slots.
 void launch_f16_scale_check(unsigned *wmax, float *scale, int *flag, int nk, hipStream_t s);
-// wmax = 0, scale = 1 for every k (before the first sparse product).
+// wmax slots = 0, scale = 1 for every k (before the first sparse product).
 void launch_f16_scale_init(unsigned *wmax, float *scale, int nk, hipStream_t s);
 // Scaled fp16 hi/lo planes: W in the product's k-packed B layout (only the
 // k-points with flag[k] != 0 when flag is given), S^-1 - I row-major.
@@ -274,7 +279,7 @@ struct vgtb_ctx {
   float2 *w32 = nullptr;       // nk * n * n, W as complex64 (bf16 and fp16 forms; the fp32 form uses w_lo)
   float *scale_a = nullptr, *scale_w = nullptr;   // fp16 form: per-k scales of S^-1 - I and W
   float *scale_part = nullptr; // fp16 form: nk * f16_scale_parts() partial maxima
-  unsigned *wmax = nullptr;    // fp16 form: per-k largest |re|, |im| of W (float bits)
+  unsigned *wmax = nullptr;    // fp16 form: per-k slots of the largest |re|, |im| of W (float bits)
   int *wflag = nullptr;        // fp16 form: per-k, W's scale changed at this step
   double *tpart = nullptr;     // 2 * nk * na
   double *tfac = nullptr;      // 2 * nk
