@@ -356,7 +356,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(k-point sharding across GPUs is not part of this build)", file=sys.stderr)
+              "(the propagation runs on a single GPU; it is not sharded across GPUs)",
+              file=sys.stderr)
         return 2
     import torch
     import vgtb_synth as vs
