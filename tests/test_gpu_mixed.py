@@ -108,6 +108,47 @@ def test_ragged_padding_and_arbitrary_start(precision):
     assert rho_err(cur, st.d_cur) < 1e-4
 
 
+def _s_chain(n_sites, n_k, seed=11, gamma_u=0.25):
+    """One s orbital per site, n_sites sites on a line at perturbed spacing, hopping and
+    overlap decaying with distance (second neighbours included), SCC on."""
+    rng = np.random.default_rng(seed)
+    a = 4.0
+    x = a * np.arange(n_sites) + rng.uniform(-0.4, 0.4, n_sites)
+    cell = np.diag([a * n_sites, 60.0, 60.0])
+    pos = np.stack([x, np.zeros(n_sites), np.zeros(n_sites)], axis=1)
+
+    def hop_h(d):
+        return np.array([[-0.1 * np.exp(-(np.linalg.norm(d) - a) / 2.0)]])
+
+    def hop_s(d):
+        return np.array([[0.1 * np.exp(-(np.linalg.norm(d) - a) / 2.0)]])
+
+    bi, bj, bd, bh, bs = vs.systems.build_blocks(cell, pos, 1, np.array([[-0.3]]), np.array([[1.0]]),
+                                                 hop_h, hop_s, cutoff=9.0)
+    k, w = vs.systems.gamma_mesh(cell, (n_k, 1, 1))
+    return vs.systems.TBSystem(name="s-chain", cell=cell, pos=pos, norb=1, blk_i=bi, blk_j=bj,
+                               blk_d=bd, blk_h0=bh, blk_s=bs, kpts=k, kw=w,
+                               n_electrons=float(n_sites),
+                               gamma=vs.systems.gamma_matrix(cell, pos, gamma_u), hubbard_u=gamma_u)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_one_orbital_per_atom_reduced_forms(precision):
+    # One orbital per atom takes the vector sparse product, whose 16-bit planes
+    # are written element by element; N = 40 is padded to 64.
+    sysm = _s_chain(40, 4)
+    d0, z, _ = oracle.ground_state(sysm)
+    sysm = dataclasses.replace(sysm, z_ref=z)
+    atab = vs.kick_table(1, 0.02)
+    n = 300
+    ref, st = oracle.propagate(sysm, d0, atab, 0.2, n, z=z)
+    h, cur, _ = run_gpu(sysm, atab, 0.2, n, precision)
+    err = j_err(h, ref)
+    print(f"{precision} one-orbital chain: J err {err:.2e}, rho err {rho_err(cur, st.d_cur):.2e}")
+    assert err < J_TOL
+    assert rho_err(cur, st.d_cur) < 1e-4
+
+
 def test_fp16_split_is_more_accurate_than_bf16():
     # Same product, same matrix-core rate: the scaled fp16 hi/lo split carries
     # about four more bits per part than bf16, so the current error against
