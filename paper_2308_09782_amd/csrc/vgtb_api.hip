@@ -71,6 +71,13 @@ int spmm_variant() {
   const int cb = b ? std::atoi(b) : 1;
   return -(cb == 2 || cb == 4 ? cb : 1);
 }
+// VGTB_GEMM_TILE: the dense product's tile (the values of vgtb_autotune's
+// candidates; 0 or unset: the size rule), until vgtb_autotune chooses.
+int gemm_tile_env() {
+  const char *e = std::getenv("VGTB_GEMM_TILE");
+  const int v = e ? std::atoi(e) : 0;
+  return (v >= 1 && v <= 5) ? v : 0;
+}
 // VGTB_SMALL_STEPS=0 turns off the one-launch-per-block-of-steps path of
 // small systems (kSmallN), which is otherwise taken in the FP64 form without
 // the SCC shift.
@@ -771,6 +778,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.img_ds = dp.g.img_ds;
   c->g.group_size = spmm_group_size(c->g.norb);
   c->spmm_variant = spmm_variant();
+  c->gemm_tile = gemm_tile_env();
   c->g.n_groups = z.ng;
   c->g.n_entries = z.ne;
   c->g.grp_ptr = dp.g.grp_ptr;
