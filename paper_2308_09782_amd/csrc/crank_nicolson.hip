@@ -29,10 +29,6 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 __device__ inline double wave_reduce(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

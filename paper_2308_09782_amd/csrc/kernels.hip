@@ -14,10 +14,6 @@
 namespace vgtb {
 namespace {
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -440,8 +436,7 @@ __global__ __launch_bounds__(256) void k_assemble(PairGraph g, const double *kpt
 // KG atoms per row group; CPT columns per thread (stride blockDim), which
 // reuses each H value read from LDS CPT times.
 template <int NO, bool DELTA, int OUT, int KG, int CPT>
-__global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d,
-                                              const double2 *__restrict__ d0, int n,
+__global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__restrict__ d, int n,
                                               const double2 *__restrict__ hq,
                                               const double2 *__restrict__ c0,
                                               void *__restrict__ wout, int np, int nk,
@@ -1287,22 +1282,22 @@ void launch_reduce(const double *part, int nk, int na, const double *kw, double 
 
 template <int NO, bool DELTA, int OUT>
 static void spmm_launch(int threads, hipStream_t s, const PairGraph &g, const double2 *d,
-                        const double2 *d0, int n, const double2 *hq, const double2 *c0, void *w,
+                        int n, const double2 *hq, const double2 *c0, void *w,
                         int np, int nk, float2 *w32, int cpt, int ncols, const float *wscale,
                         unsigned *wmax) {
   const int ng = g.n_groups;
   if (g.group_size == 8 && cpt == 1)
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 1>), dim3(blocks_for(ncols, threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
+                       dim3(threads), 0, s, g, d, n, hq, c0, w, np, nk, w32, wscale, wmax);
   else if (g.group_size == 4 && cpt == 2)
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 2>), dim3(blocks_for(ncols, 2 * threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
+                       dim3(threads), 0, s, g, d, n, hq, c0, w, np, nk, w32, wscale, wmax);
   else if (g.group_size == 4 && cpt == 1)
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 4, 1>), dim3(blocks_for(ncols, threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
+                       dim3(threads), 0, s, g, d, n, hq, c0, w, np, nk, w32, wscale, wmax);
   else
     hipLaunchKernelGGL((k_spmm<NO, DELTA, OUT, 8, 2>), dim3(blocks_for(ncols, 2 * threads), ng, nk),
-                       dim3(threads), 0, s, g, d, d0, n, hq, c0, w, np, nk, w32, wscale, wmax);
+                       dim3(threads), 0, s, g, d, n, hq, c0, w, np, nk, w32, wscale, wmax);
 }
 
 void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource src,
@@ -1360,7 +1355,7 @@ void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
   }
   const int cpt = variant == 2 ? 2 : 1;
   const int threads = n >= 256 ? 256 : (n > 64 ? 128 : 64);
-#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, d0, n, hq, c0, w, np, nk, w32, cpt, ncols, wscale, wmax)
+#define VG_SPMM(NO, DL, OUT) spmm_launch<NO, DL, OUT>(threads, s, g, d, n, hq, c0, w, np, nk, w32, cpt, ncols, wscale, wmax)
   if (g.norb == 4) {
     if (!d0) VG_SPMM(4, false, 0);
     else if (out_format == 0) VG_SPMM(4, true, 0);
