@@ -37,7 +37,7 @@ def sources() -> list:
 
 
 def compile_command(src: str, obj: str) -> list:
-    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
+    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c", "-Wall",
             # keep the compiler from forming packed-FP32 instructions
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             *FILE_FLAGS.get(os.path.basename(src), []),
