@@ -226,6 +226,28 @@ def test_error_paths():
     assert ei.value.status == 3                          # VGTB_E_NOT_PD
 
 
+@pytest.mark.parametrize("case", ["per-step fp64", "per-step fp16x3", "small-path fp64"])
+def test_nonfinite_density_is_reported(case):
+    # A NaN in the density reaches the trace; synchronising reports
+    # VGTB_E_NONFINITE and the context refuses further work.
+    if case.startswith("small"):
+        sysm, precision = vs.config_system("si8_k64"), "fp64"
+    else:
+        sysm, precision = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25), case.split()[1]
+    with pkg.Propagator(sysm, 0.2, precision, history_capacity=8) as p:
+        p.ground_state()
+        d = p.get_density(0).cpu().numpy()
+        d[0, 3, 3] = np.nan
+        p.set_density(d)
+        p.set_field_table(vs.kick_table(1, 0.01))
+        p.step(2)
+        with pytest.raises(pkg.VgtbError) as ei:
+            p.synchronize()
+        assert ei.value.status == 7                      # VGTB_E_NONFINITE
+        with pytest.raises(pkg.VgtbError):
+            p.step(1)
+
+
 # ---------------------------------------------------------------------------
 def test_spectrum_matches_oracle():
     """Eqs. 15-16 on the GPU vs the oracle, on a kick run's current and on a
