@@ -72,7 +72,9 @@ typedef enum {
  * every block (I, J, d), the partner (J, I, -d) with the transposed values
  * (so that H_k and S_k are Hermitian); vgtb_create checks this.
  *
- * kpts are Cartesian (1/bohr), kw their weights (sum 1).  n_electrons is the
+ * kpts are Cartesian (1/bohr), kw their weights (sum 1); every k-sum (the
+ * charges, the energy and the current of Eq. 14, whose 1/N_k is the
+ * equal-weight case) uses them.  n_electrons is the
  * electron count per k-point (f = 2 per state, Tr(D_k S_k) = n_electrons).
  * gamma (n_atoms^2, symmetric) switches on the SCC term of Eq. 10; NULL means
  * a non-SCC run.  z_ref is the per-atom reference charge Z_I of dq = q - Z;
@@ -128,6 +130,21 @@ typedef enum { VGTB_COUPLING_PEIERLS = 0, VGTB_COUPLING_MOMENTUM = 1 } vgtb_coup
  */
 typedef enum { VGTB_PROP_LEAPFROG = 0, VGTB_PROP_CRANK_NICOLSON = 1 } vgtb_propagator;
 
+/* Bits of vgtb_options.flags. */
+enum {
+  VGTB_OPT_NO_GRAPHS = 1,      /* launch every step directly (no captured two-step
+                                  graphs); same results bit for bit               */
+  VGTB_OPT_NO_SMALL_PATH = 2   /* no whole-steps-per-launch path for small FP64
+                                  non-SCC systems; same results to rounding       */
+};
+
+/*
+ * Options of one context.  Zero-initialise the struct, then set dt and
+ * history_capacity: every other zero is the default.  The kernel choices (tile_override, spmm_variant,
+ * spmm_group) change only the summation order of the products, never the
+ * method; vgtb_autotune can choose them instead.  No process-wide setting
+ * (environment variable, global) is read.
+ */
 typedef struct {
   double dt;                   /* time step (atomic time units), finite, nonzero */
   int32_t precision;           /* vgtb_precision                                 */
@@ -136,9 +153,25 @@ typedef struct {
   int32_t history_capacity;    /* observables ring length in steps (>= 1)        */
   int32_t coupling;            /* vgtb_coupling                                  */
   int32_t propagator;          /* vgtb_propagator                                */
+  int32_t tile_override;       /* dense product S^-1 W tile: 0 = size rule; FP64 and
+                                  FP32: 1 = 32x32, 2 = 64x64, 3 = 128x64; 3xBF16 and
+                                  FP16X3: 1 = 64x64, 2-5 = 128x128 with 16, 8 (64x32),
+                                  8 (32x64) or 4 wavefronts (N padded to a multiple of
+                                  128, else 64x64); Crank-Nicolson: the solve's large
+                                  products, 1 = 64x64, 2 (0) = 128x64, 3 = 128x128   */
+  int32_t spmm_variant;        /* sparse product W = H D: 0 = default (-1); -1, -2, -4
+                                  = FP64 matrix cores with 1, 2, 4 16-column slices per
+                                  wavefront (four orbitals per atom only); 1, 2 =
+                                  vector FMAs with 1, 2 columns per thread (always the
+                                  vector form for one orbital per atom)              */
+  int32_t spmm_group;          /* atoms per row group of the sparse product: 0 (= 8),
+                                  4, 8, or 16 (matrix-core variants only)            */
+  int32_t flags;               /* VGTB_OPT_* bits                                   */
 } vgtb_options;
 
-/* Bytes of device arena vgtb_create needs for this system and options. */
+/* Bytes of device arena vgtb_create needs for this system and options
+ * (VGTB_E_INVAL for an invalid system or options, with the reason in
+ * vgtb_last_error(NULL)). */
 vgtb_status vgtb_workspace_size(const vgtb_system *sys, const vgtb_options *opt,
                                 size_t *bytes);
 
@@ -154,7 +187,9 @@ vgtb_status vgtb_create(const vgtb_system *sys, const vgtb_options *opt, void *d
                         size_t arena_bytes, void *hip_stream, vgtb_ctx **out);
 
 /*
- * Ground state at A = 0: solve H0_k C = S_k C eps for every k, fill states by
+ * Ground state at A = 0, the starting point of every run in Section 3 (the
+ * field-free density before the kick or pulse), as the density matrix of the
+ * definition after Eq. 6: solve H0_k C = S_k C eps for every k, fill states by
  * aufbau with f = 2 (a degenerate group straddling the Fermi level shares its
  * electrons equally), form D_k(0) = sum_n f_n c_n c_n^dag on the device and
  * make it the current density (step index 0).  If z_ref was NULL, the
@@ -167,7 +202,8 @@ vgtb_status vgtb_create(const vgtb_system *sys, const vgtb_options *opt, void *d
 vgtb_status vgtb_ground_state(vgtb_ctx *ctx, double *min_gap_host);
 
 /*
- * Set D_k(0) from n_k * N * N complex128 values (on_device != 0: device
+ * Initial condition of Eq. 6 given by the caller (for instance a perturbed or
+ * excited density).  Set D_k(0) from n_k * N * N complex128 values (on_device != 0: device
  * pointer read on the context stream; else host).  Resets the step index to
  * 0 and forgets the previous level.  In the deviation forms this density
  * also becomes the reference D0 of the reduced-precision product.
@@ -195,18 +231,28 @@ int32_t vgtb_num_states(const vgtb_ctx *ctx);
  * or host) and, if occ_host is not NULL, the occupations.  Synchronises. */
 vgtb_status vgtb_get_coefficients(vgtb_ctx *ctx, void *c_out, double *occ_host, int on_device);
 
-/* A(t_n) for n = 0 .. n-1 (host, n * 3 doubles, atomic units).  Steps past
- * the table's end use its last entry. */
+/* The drive as the vector potential of Eq. 3, A(t) = -c int E dt (velocity
+ * gauge): A(t_n) for n = 0 .. n-1, t_n = n dt (host, n * 3 doubles, atomic
+ * units; copied).  A delta kick E0 delta(t) is the constant A = -c E0 from
+ * t = 0; a laser pulse is its A(t) sampled on the step grid.  Steps past the
+ * table's end use its last entry.  VGTB_E_INVAL for n < 1 or a non-finite
+ * entry (the table in use is then unchanged). */
 vgtb_status vgtb_set_field_table(vgtb_ctx *ctx, int64_t n, const double *a_host);
 
-/* A constant vector potential from the next step on (a one-entry table). */
+/* A constant vector potential (Eq. 3) from the next step on: a one-entry
+ * table, as for a delta kick. */
 vgtb_status vgtb_set_field(vgtb_ctx *ctx, const double a_host[3]);
 
 /*
- * Queue n_steps leapfrog steps on the context stream (asynchronous).  Step n
- * uses A(t_n), evaluates the SCC shift from the charges of D_n, records the
- * observables of D_n in the history ring, then forms D_{n+1} (the first
- * step after a density is set is a forward Euler step).  Deviation forms
+ * The time propagation: queue n_steps leapfrog steps (Eq. 13 applied to
+ * Eq. 6) on the context stream (asynchronous).  Step n uses A(t_n),
+ * evaluates the SCC shift of Eq. 10 from the Mulliken charges of D_n,
+ * records the observables of D_n (current of Eq. 14, energy, Tr(D S),
+ * charges) in the history ring, assembles H_k(t_n) from the blocks (Eqs. 8-9,
+ * or Eq. 12 in the momentum coupling), then forms D_{n+1} (the first step
+ * after a density is set is a forward Euler step).  VGTB_E_STATE before a
+ * density is set; VGTB_E_INVAL for n_steps < 0; a non-finite trace is
+ * reported by the next vgtb_synchronize.  Deviation forms
  * re-Hermitise and rescale the trace of both levels after every
  * rescale_every-th step.  A Crank-Nicolson context records the observables of
  * C_n with A(t_n), then solves for C_{n+1} (vgtb_propagator).

@@ -9,8 +9,10 @@ Readings where the paper leaves a choice open:
   * Bloch phase: exp(+i (k + A/c) . d) with d = R_J + L - R_I the full bond
     vector (Eqs. 7-8 up to a diagonal unitary gauge, identical observables).
   * Spin-unpolarised occupations f = 2, so Tr(D_k S_k) = N_el per k.
-  * Current prefactor (Eq. 14): J = -(1/(Omega N_k)) sum_k Re Tr(D_k Pi_k)
-    with Pi_k = c dH/dA = dH0/dk evaluated at k + A/c.
+  * Current prefactor (Eq. 14): J = -(1/Omega) sum_k w_k Re Tr(D_k Pi_k)
+    with Pi_k = c dH/dA = dH0/dk evaluated at k + A/c.  On the equal-weight
+    mesh w_k = 1/N_k this is Eq. 14's -(1/(Omega N_k)) sum_k; with weights the
+    current is the k-average the charges and the energy already use.
   * SCC shift of step n is evaluated from the charges of D_n.
   * Leapfrog start (Eq. 13 needs two levels): one forward Euler step.
   * Energy: E = sum_k w_k Re Tr(D_k H0_k(A)) + 1/2 dq^T gamma dq.
@@ -212,18 +214,20 @@ def density_derivative_columns(s_inv: np.ndarray, h: np.ndarray, d: np.ndarray, 
 
 
 def observables(sysm, dens, ovl, a_vec, z, coupling: str = "peierls"):
-    """Current (Eq. 14), band + SCC energy, Tr(D S) and Mulliken charges of one time level."""
-    nk = sysm.n_k
+    """Current (Eq. 14), band + SCC energy, Tr(D S) and Mulliken charges of one time level.
+
+    Every k-sum uses the weights w_k; Eq. 14's 1/N_k is the equal-weight case.
+    """
     jcur = np.zeros(3)
     e_band = 0.0
     tr = 0.0
     for w, kvec, d, s in zip(sysm.kw, sysm.kpts, dens, ovl):
         pik = current_matrix_k(sysm, kvec, a_vec, s, coupling)
         for alpha in range(3):
-            jcur[alpha] += np.real(np.trace(d @ pik[alpha]))
+            jcur[alpha] += w * np.real(np.trace(d @ pik[alpha]))
         e_band += w * np.real(np.trace(d @ field_hamiltonian_k(sysm, kvec, a_vec, s, coupling)))
         tr += w * np.real(np.trace(d @ s))
-    jcur *= -1.0 / (sysm.volume * nk)
+    jcur *= -1.0 / sysm.volume
     q = mulliken(sysm, dens, ovl)
     e = e_band
     if sysm.gamma is not None:

@@ -170,21 +170,13 @@ void gemm_tile(const double2 *a, int lda, size_t sa, const double2 *b, int ldb, 
 }
 
 // Tile shape of the large products (trailing update, back substitution):
-// VGTB_CN_TILE = 1: 64 x 64 (4 waves), 2: 128 x 64 (8), 3: 128 x 128 (16).
-int cn_tile() {
-  static const int t = [] {
-    const char *e = std::getenv("VGTB_CN_TILE");
-    const int v = e ? std::atoi(e) : 0;
-    return (v >= 1 && v <= 3) ? v : 2;
-  }();
-  return t;
-}
-
+// 1 = 64 x 64 (4 waves), 2 = 128 x 64 (8), 3 = 128 x 128 (16); the leaf
+// products (small_m) always use 64 x 64.
 void gemm_strided(const double2 *a, int lda, size_t sa, const double2 *b, int ldb, size_t sb,
                   double2 *c, int ldc, size_t sc, int m, int n, int k, double alpha, bool beta_one,
-                  int batch, hipStream_t s, bool small_m = false) {
+                  int batch, hipStream_t s, int big_tile, bool small_m = false) {
   if (m <= 0 || n <= 0 || k <= 0) return;
-  const int tile = small_m ? 1 : cn_tile();
+  const int tile = small_m ? 1 : big_tile;
   if (tile == 3 && m > 64)
     gemm_tile<128, 128, 4, 4>(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one, batch, s);
   else if (tile == 2 && m > 64)
@@ -461,7 +453,8 @@ int cn_split(int m) {
 //     B2 <- A22^-1 B2                            (recursion)
 //     B1 -= A12 B2                               (K = m - h)
 // Most of the work is in the two products, whose depth K is half the block.
-void cn_solve(double2 *aug, double2 *inv, int r0, int m, int n, int ns, int nk, hipStream_t s) {
+void cn_solve(double2 *aug, double2 *inv, int r0, int m, int n, int ns, int nk, int tile,
+              hipStream_t s) {
   const int ld = 2 * n;
   const size_t sa = (size_t)n * ld;
   const int w = n + ns - (r0 + m);
@@ -470,22 +463,22 @@ void cn_solve(double2 *aug, double2 *inv, int r0, int m, int n, int ns, int nk, 
     hipLaunchKernelGGL(k_blk_inv, dim3(nk), dim3(kInvThreads), 0, s, aug, ld, sa, r0, m, inv);
     // In place: the product's tile holds all m rows of each column it owns.
     gemm_strided(inv, kCnBlock, (size_t)kCnBlock * kCnBlock, at(r0, r0 + m), ld, sa, at(r0, r0 + m),
-                 ld, sa, m, w, m, 1.0, false, nk, s, true);
+                 ld, sa, m, w, m, 1.0, false, nk, s, tile, true);
     return;
   }
   const int h = cn_split(m);
-  cn_solve(aug, inv, r0, h, n, ns, nk, s);
+  cn_solve(aug, inv, r0, h, n, ns, nk, tile, s);
   gemm_strided(at(r0 + h, r0), ld, sa, at(r0, r0 + h), ld, sa, at(r0 + h, r0 + h), ld, sa, m - h,
-               (m - h) + w, h, -1.0, true, nk, s);
-  cn_solve(aug, inv, r0 + h, m - h, n, ns, nk, s);
+               (m - h) + w, h, -1.0, true, nk, s, tile);
+  cn_solve(aug, inv, r0 + h, m - h, n, ns, nk, tile, s);
   gemm_strided(at(r0, r0 + h), ld, sa, at(r0 + h, r0 + m), ld, sa, at(r0, r0 + m), ld, sa, h, w,
-               m - h, -1.0, true, nk, s);
+               m - h, -1.0, true, nk, s, tile);
 }
 
 }  // namespace
 
-void launch_cn_solve(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s) {
-  cn_solve(aug, inv, 0, n, n, ns, nk, s);
+void launch_cn_solve(double2 *aug, double2 *inv, int n, int ns, int nk, int tile, hipStream_t s) {
+  cn_solve(aug, inv, 0, n, n, ns, nk, (tile >= 1 && tile <= 3) ? tile : 2, s);
 }
 
 void launch_cn_update(const double2 *aug, double2 *c, int n, int ns, int nk, int64_t *ctr,
@@ -505,7 +498,7 @@ void launch_cn_to_vectors(const double2 *c, double2 *evec, int n, int ns, int nk
 void launch_zgemm_strided(const double2 *a, int lda, size_t sa, const double2 *b, int ldb, size_t sb,
                           double2 *c, int ldc, size_t sc, int m, int n, int k, double alpha,
                           bool beta_one, int batch, hipStream_t s) {
-  gemm_strided(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one, batch, s);
+  gemm_strided(a, lda, sa, b, ldb, sb, c, ldc, sc, m, n, k, alpha, beta_one, batch, s, 2);
 }
 
 }  // namespace vgtb

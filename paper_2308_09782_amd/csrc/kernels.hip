@@ -199,7 +199,8 @@ __global__ __launch_bounds__(64) void k_observe(PairGraph g, const double2 *__re
 // Reduction of the per-(k, atom) partials, in three short kernels with a
 // fixed summation order (repeated runs agree bit for bit):
 //  1. per atom I: q_I = sum_k w_k q(k,I) (Mulliken), and the atom's shares
-//     of the band energy and the current summed over k;
+//     of the band energy and the current, each summed over k with the
+//     weights w_k (Eq. 14's 1/N_k is the equal-weight mesh);
 //  2. SCC only, one wavefront per row: V_I = sum_K gamma_IK (q_K - Z_K)
 //     (Eq. 10) and the atom's share 1/2 dq_I V_I of the SCC energy;
 //  3. one workgroup: sums over atoms into the history row
@@ -218,9 +219,9 @@ __global__ __launch_bounds__(256) void k_reduce_atoms(const double *__restrict__
     const double *o = part + ((size_t)k * na + I) * 5;
     q += kw[k] * o[0];
     en += kw[k] * o[1];
-    jx += o[2];
-    jy += o[3];
-    jz += o[4];
+    jx += kw[k] * o[2];
+    jy += kw[k] * o[3];
+    jz += kw[k] * o[4];
   }
   qbuf[I] = q;
   hist_row[5 + I] = q;
@@ -882,9 +883,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_steps(const double *_
       const double *o = ps + ((size_t)k * na + I) * 5;
       q += kw[k] * o[0];
       en += kw[k] * o[1];
-      jx += o[2];
-      jy += o[3];
-      jz += o[4];
+      jx += kw[k] * o[2];
+      jy += kw[k] * o[3];
+      jz += kw[k] * o[4];
     }
     row[5 + I] = q;
     c[0] += en;

@@ -57,46 +57,14 @@ struct HostGraph {
   std::vector<int> grp_ptr, ent_j, ent_mask, ent_pp, gp_pair, gp_il;
 };
 
-// Sparse-product tuning, read when a context is created.  VGTB_SPMM_CPT = 1
-// or 2 selects vector FMAs with that many columns per thread (always the
-// vector form for one orbital per atom); otherwise the FP64 matrix cores
-// with VGTB_SPMM_CB (1 default, 2 or 4) 16-column slices per wave.
-// VGTB_SPMM_GROUP: atoms per row group, 4 or 8 (default), or 16 with the
-// matrix-core kernel.
-int spmm_variant() {
-  const char *e = std::getenv("VGTB_SPMM_CPT");
-  const int v = e ? std::atoi(e) : 0;
-  if (v == 1 || v == 2) return v;
-  const char *b = std::getenv("VGTB_SPMM_CB");
-  const int cb = b ? std::atoi(b) : 1;
-  return -(cb == 2 || cb == 4 ? cb : 1);
-}
-// VGTB_GEMM_TILE: the dense product's tile (the values of vgtb_autotune's
-// candidates; 0 or unset: the size rule), until vgtb_autotune chooses.
-int gemm_tile_env() {
-  const char *e = std::getenv("VGTB_GEMM_TILE");
-  const int v = e ? std::atoi(e) : 0;
-  return (v >= 1 && v <= 5) ? v : 0;
-}
-// VGTB_SMALL_STEPS=0 turns off the one-launch-per-block-of-steps path of
-// small systems (kSmallN), which is otherwise taken in the FP64 form without
-// the SCC shift.
-// VGTB_GRAPH=0 turns off graph replay of the per-step launches.
-bool graphs_enabled() {
-  const char *e = std::getenv("VGTB_GRAPH");
-  return !(e && std::atoi(e) == 0);
-}
-bool small_path_enabled() {
-  const char *e = std::getenv("VGTB_SMALL_STEPS");
-  return !(e && std::atoi(e) == 0);
-}
-int spmm_group_size(int orbs_per_atom) {
-  const bool mfma = orbs_per_atom == 4 && spmm_variant() < 0;
-  const char *e = std::getenv("VGTB_SPMM_GROUP");
-  const int v = e ? std::atoi(e) : 8;
-  if (v == 16 && mfma) return 16;
-  return v == 4 ? 4 : 8;
-}
+// Kernel choices of a context, from its options (no process-wide state).
+// Sparse product W = H D: spmm_variant -1, -2, -4 = FP64 matrix cores with
+// that many 16-column slices per wavefront (four orbitals per atom), 1 or 2 =
+// vector FMAs with that many columns per thread; 0 = -1 (the vector form is
+// always used for one orbital per atom).  spmm_group: atoms per row group,
+// 4 or 8 (0 = 8), or 16 with the matrix-core variants.
+int spmm_variant_of(const vgtb_options *o) { return o->spmm_variant == 0 ? -1 : o->spmm_variant; }
+int spmm_group_of(const vgtb_options *o) { return o->spmm_group == 0 ? 8 : o->spmm_group; }
 
 // Row groups of G consecutive atoms and the union of their neighbours.
 void build_groups(HostGraph &hg, int G) {
@@ -124,7 +92,8 @@ void build_groups(HostGraph &hg, int G) {
   }
 }
 
-vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
+vgtb_status build_graph(const vgtb_system *s, const vgtb_options *o, HostGraph &hg,
+                        std::string &msg) {
   const int na = s->n_atoms, no = s->orbs_per_atom, nb = s->n_blocks;
   const int e2 = no * no;
   std::vector<int> order(nb);
@@ -217,7 +186,7 @@ vgtb_status build_graph(const vgtb_system *s, HostGraph &hg, std::string &msg) {
       msg = "atom " + std::to_string(i) + " has no blocks (an on-site block is required)";
       return VGTB_E_INVAL;
     }
-  build_groups(hg, spmm_group_size(no));
+  build_groups(hg, spmm_group_of(o));
   return VGTB_OK;
 }
 
@@ -258,6 +227,30 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
   }
   if (o->propagator != VGTB_PROP_LEAPFROG && o->propagator != VGTB_PROP_CRANK_NICOLSON) {
     msg = "unknown propagator";
+    return VGTB_E_INVAL;
+  }
+  if (o->tile_override < 0 || o->tile_override > (o->precision >= VGTB_BF16X3 ? 5 : 3)) {
+    msg = "tile_override must be 0 (default), 1-3 (FP64, FP32, Crank-Nicolson) or 1-5 (3xBF16, FP16X3)";
+    return VGTB_E_INVAL;
+  }
+  {
+    const int v = o->spmm_variant, g = o->spmm_group;
+    if (v != 0 && v != -1 && v != -2 && v != -4 && v != 1 && v != 2) {
+      msg = "spmm_variant must be 0, -1, -2, -4 (matrix cores) or 1, 2 (vector FMAs)";
+      return VGTB_E_INVAL;
+    }
+    if (v < 0 && s->orbs_per_atom != 4) {
+      msg = "the matrix-core sparse product needs four orbitals per atom";
+      return VGTB_E_INVAL;
+    }
+    if (g != 0 && g != 4 && g != 8 && g != 16) { msg = "spmm_group must be 0, 4, 8 or 16"; return VGTB_E_INVAL; }
+    if (g == 16 && (v > 0 || s->orbs_per_atom != 4)) {
+      msg = "row groups of 16 atoms need the matrix-core sparse product";
+      return VGTB_E_INVAL;
+    }
+  }
+  if ((o->flags & ~(VGTB_OPT_NO_GRAPHS | VGTB_OPT_NO_SMALL_PATH)) != 0) {
+    msg = "unknown option flags";
     return VGTB_E_INVAL;
   }
   if (o->propagator == VGTB_PROP_CRANK_NICOLSON && o->precision != VGTB_FP64) {
@@ -437,7 +430,7 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.npad = (z.n + 63) / 64 * 64;
   z.mom = o->coupling == VGTB_COUPLING_MOMENTUM;
   z.cn = o->propagator == VGTB_PROP_CRANK_NICOLSON;
-  z.small = small_path_enabled() && !z.deviation && !z.scc && !z.mom && !z.cn && z.n <= vgtb::kSmallN &&
+  z.small = !(o->flags & VGTB_OPT_NO_SMALL_PATH) && !z.deviation && !z.scc && !z.mom && !z.cn && z.n <= vgtb::kSmallN &&
             z.ni <= vgtb::kSmallImages;
   return z;
 }
@@ -533,7 +526,7 @@ void fill_ring(vgtb_ctx *c, int64_t stp, int need) {
 // (S + i dt/2 H) X = W, and C_{n+1} = 2 X - C_n.
 void enqueue_step_cn(vgtb_ctx *c, hipStream_t s) {
   const int n = c->n, nk = c->nk, ns = c->ns;
-  const double jscale = -1.0 / (c->volume * nk);
+  const double jscale = -1.0 / c->volume;   // the k weights enter the sum
   const vgtb::StepSource src{c->ring, c->ctr}, mid{c->ring_mid, c->ctr};
   double2 *cc = c->dlev[0];
   double2 *dp = c->dlev[1];
@@ -556,7 +549,7 @@ void enqueue_step_cn(vgtb_ctx *c, hipStream_t s) {
   });
   timed(c, VGTB_K_CN_SOLVE, [&] {
     vgtb::launch_cn_build(c->g, c->w, c->hq, c->spk, 0.5 * c->dt, n, ns, nk, c->aug, s);
-    vgtb::launch_cn_solve(c->aug, c->cinv, n, ns, nk, s);
+    vgtb::launch_cn_solve(c->aug, c->cinv, n, ns, nk, c->gemm_tile, s);
   });
   timed(c, VGTB_K_CN_UPDATE, [&] { vgtb::launch_cn_update(c->aug, cc, n, ns, nk, c->ctr, s); });
 }
@@ -610,7 +603,7 @@ void launch_reduced_product(vgtb_ctx *c, int fmt, int tile, hipStream_t s) {
 void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
   const int n = c->n, nk = c->nk;
   const bool dev = c->precision != VGTB_FP64;
-  const double jscale = -1.0 / (c->volume * nk);
+  const double jscale = -1.0 / c->volume;   // the k weights enter the sum
   const vgtb::StepSource src{c->ring, c->ctr};
   double2 *dcur = c->dlev[c->cur];
   double2 *doth = c->dlev[c->cur ^ 1];
@@ -698,7 +691,7 @@ vgtb_status vgtb_workspace_size(const vgtb_system *s, const vgtb_options *o, siz
   if (st != VGTB_OK) return fail(nullptr, st, msg);
   if (!bytes) return fail(nullptr, VGTB_E_INVAL, "null bytes pointer");
   HostGraph hg;
-  st = build_graph(s, hg, msg);
+  st = build_graph(s, o, hg, msg);
   if (st != VGTB_OK) return fail(nullptr, st, msg);
   Carver cv(nullptr);
   SizeProbe probe;
@@ -716,7 +709,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0)
     return fail(nullptr, VGTB_E_INVAL, "arena must be 256-byte aligned");
   HostGraph hg;
-  st = build_graph(s, hg, msg);
+  st = build_graph(s, o, hg, msg);
   if (st != VGTB_OK) return fail(nullptr, st, msg);
   const Sizes z = sizes_of(s, o, hg);
   {
@@ -776,9 +769,9 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->g.img_h0 = dp.g.img_h0;
   c->g.img_s = dp.g.img_s;
   c->g.img_ds = dp.g.img_ds;
-  c->g.group_size = spmm_group_size(c->g.norb);
-  c->spmm_variant = spmm_variant();
-  c->gemm_tile = gemm_tile_env();
+  c->g.group_size = spmm_group_of(o);
+  c->spmm_variant = spmm_variant_of(o);
+  c->gemm_tile = o->tile_override;
   c->g.n_groups = z.ng;
   c->g.n_entries = z.ne;
   c->g.grp_ptr = dp.g.grp_ptr;
@@ -828,7 +821,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->ring = dp.ring;
   c->ctr = dp.ctr;
   c->small_path = z.small;
-  c->use_graphs = graphs_enabled() && !z.cn;
+  c->use_graphs = !(o->flags & VGTB_OPT_NO_GRAPHS) && !z.cn;
   c->cn = z.cn;
   c->aug = dp.aug;
   c->cinv = dp.cinv;
@@ -1109,7 +1102,7 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
   const int n = c->n, nk = c->nk;
   const bool dev = c->precision != VGTB_FP64;
   const int64_t nf = (int64_t)(c->field.size() / 3);
-  const double jscale = -1.0 / (c->volume * nk);
+  const double jscale = -1.0 / c->volume;   // the k weights enter the sum
   hipStream_t s = c->stream;
   if (c->small_path) {
     for (int64_t done = 0; done < n_steps;) {

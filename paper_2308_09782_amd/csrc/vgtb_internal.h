@@ -175,8 +175,9 @@ void launch_cn_vmid(const double *v, double *vprev, double *vmid, int na, bool f
 // [A | R]: A = S + i tau H on the pair pattern (zero elsewhere), R = W[:, :ns].
 void launch_cn_build(const PairGraph &g, const double2 *w, const double2 *hq, const double2 *spk,
                      double tau, int n, int ns, int nk, double2 *aug, hipStream_t s);
-// X = A^-1 R in the R columns of [A | R] (recursive block elimination).
-void launch_cn_solve(double2 *aug, double2 *inv, int n, int ns, int nk, hipStream_t s);
+// X = A^-1 R in the R columns of [A | R] (recursive block elimination); tile
+// of the large products: 1 = 64 x 64, 2 = 128 x 64 (0 or other: 2), 3 = 128 x 128.
+void launch_cn_solve(double2 *aug, double2 *inv, int n, int ns, int nk, int tile, hipStream_t s);
 // C = 2 X - C with X the R columns; ctr (may be null) advanced by one.
 void launch_cn_update(const double2 *aug, double2 *c, int n, int ns, int nk, int64_t *ctr,
                       hipStream_t s);

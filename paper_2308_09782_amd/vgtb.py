@@ -54,10 +54,15 @@ class VgtbSystem(ctypes.Structure):
     ]
 
 
+OPT_NO_GRAPHS, OPT_NO_SMALL_PATH = 1, 2
+
+
 class VgtbOptions(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rescale_every", ctypes.c_int32), ("history_capacity", ctypes.c_int32),
-                ("coupling", ctypes.c_int32), ("propagator", ctypes.c_int32)]
+                ("coupling", ctypes.c_int32), ("propagator", ctypes.c_int32),
+                ("tile_override", ctypes.c_int32), ("spmm_variant", ctypes.c_int32),
+                ("spmm_group", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class VgtbTuning(ctypes.Structure):
@@ -197,7 +202,10 @@ def make_system_struct(system):
 
 def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
                  history_capacity: int = 1024, coupling: str = "peierls",
-                 propagator: str = "leapfrog") -> VgtbOptions:
+                 propagator: str = "leapfrog", tile: int = 0, spmm_variant: int = 0,
+                 spmm_group: int = 0, graphs: bool = True, small_path: bool = True) -> VgtbOptions:
+    """vgtb_options; tile, spmm_variant and spmm_group are the header's kernel
+    choices (0 = default), graphs / small_path clear the VGTB_OPT_NO_* flags."""
     o = VgtbOptions()
     o.dt = float(dt)
     o.precision = PRECISIONS[precision]
@@ -205,6 +213,10 @@ def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
     o.history_capacity = int(history_capacity)
     o.coupling = COUPLINGS[coupling]
     o.propagator = PROPAGATORS[propagator]
+    o.tile_override = int(tile)
+    o.spmm_variant = int(spmm_variant)
+    o.spmm_group = int(spmm_group)
+    o.flags = (0 if graphs else OPT_NO_GRAPHS) | (0 if small_path else OPT_NO_SMALL_PATH)
     return o
 
 
@@ -236,7 +248,8 @@ class Propagator:
 
     def __init__(self, system, dt: float, precision: str = "fp64", rescale_every: int = 50,
                  history_capacity: int = 1024, device: str = "cuda:0", coupling: str = "peierls",
-                 propagator: str = "leapfrog"):
+                 propagator: str = "leapfrog", **kernel_options):
+        """kernel_options: tile, spmm_variant, spmm_group, graphs, small_path (make_options)."""
         torch = _torch()
         self._torch = torch
         self.lib = load_library()
@@ -247,7 +260,7 @@ class Propagator:
         self.n_k = int(np.asarray(system.kpts).shape[0])
         self.precision = precision
         self.options = make_options(dt, precision, rescale_every, history_capacity, coupling,
-                                    propagator)
+                                    propagator, **kernel_options)
         s, keep = make_system_struct(system)
         with torch.cuda.device(self.device):
             size = ctypes.c_size_t(0)

@@ -24,8 +24,8 @@ def _need_gpu():
     pkg.load_library()
 
 
-def _run(sysm, dt, atab, precision, n, tune):
-    with pkg.Propagator(sysm, dt, precision, history_capacity=n) as p:
+def _run(sysm, dt, atab, precision, n, tune, tile=0):
+    with pkg.Propagator(sysm, dt, precision, history_capacity=n, tile=tile) as p:
         p.ground_state()
         p.set_field_table(atab)
         tuning = None
@@ -98,20 +98,19 @@ def test_autotune_needs_a_density():
 
 
 @pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
-def test_split_product_128_tiles_bit_identical(monkeypatch, precision):
-    # The four 128 x 128 wavefront arrangements (VGTB_GEMM_TILE 2-5) feed every
+def test_split_product_128_tiles_bit_identical(precision):
+    # The four 128 x 128 wavefront arrangements (tile_override 2-5) feed every
     # accumulator the same products in the same order: the same bits.
     c = vs.CONFIGS["asi64_k8_scc"]
     sysm = vs.config_system("asi64_k8_scc")
     full = vs.sin2_pulse_table(c["n_steps"], c["dt"], c["omega"], c["t_fs"] * vs.FS_AU, c["a_peak"])
     atab = full[1500:]
     runs = {}
-    for tile in ("2", "3", "4", "5"):
-        monkeypatch.setenv("VGTB_GEMM_TILE", tile)
-        runs[tile] = _run(sysm, c["dt"], atab, precision, 30, False)
-    h2, d2, _ = runs["2"]
+    for tile in (2, 3, 4, 5):
+        runs[tile] = _run(sysm, c["dt"], atab, precision, 30, False, tile=tile)
+    h2, d2, _ = runs[2]
     assert np.abs(h2["J"]).max() > 0
-    for tile in ("3", "4", "5"):
+    for tile in (3, 4, 5):
         h, d, _ = runs[tile]
         assert np.array_equal(h2["J"], h["J"]), tile
         assert np.array_equal(d2, d), tile

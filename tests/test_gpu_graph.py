@@ -3,7 +3,7 @@
 Pairs of steps are replayed from graphs captured once per leapfrog parity;
 the forward-Euler first step, the steps that end in a rescale and odd leftovers
 are launched directly, so every run below interleaves replays with direct
-work.  Each run is repeated with graphs turned off (VGTB_GRAPH=0) and the two
+work.  Each run is repeated with graphs turned off (the VGTB_OPT_NO_GRAPHS option) and the two
 must agree bit for bit: the history (J, E, Tr, q) and both density levels.
 The runs change the field table mid-run (the device field ring is refilled),
 reload a checkpoint (the device step counter is reset) and start from a
@@ -35,10 +35,10 @@ def case():
     return sysm, c["dt"], full
 
 
-def _run(monkeypatch, graphs, sysm, dt, full, precision, start=None):
-    monkeypatch.setenv("VGTB_GRAPH", "1" if graphs else "0")
+def _run(graphs, sysm, dt, full, precision, start=None):
     out = {}
-    with pkg.Propagator(sysm, dt, precision, rescale_every=10, history_capacity=400) as p:
+    with pkg.Propagator(sysm, dt, precision, rescale_every=10, history_capacity=400,
+                        graphs=graphs) as p:
         if start is None:
             p.ground_state()
         else:
@@ -70,15 +70,15 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "bf16x3", "fp16x3"])
-def test_graph_replay_bit_identical(monkeypatch, case, precision):
+def test_graph_replay_bit_identical(case, precision):
     sysm, dt, full = case
-    with_graphs = _run(monkeypatch, True, sysm, dt, full, precision)
-    without = _run(monkeypatch, False, sysm, dt, full, precision)
+    with_graphs = _run(True, sysm, dt, full, precision)
+    without = _run(False, sysm, dt, full, precision)
     assert np.abs(with_graphs["h1"]["J"]).max() > 0
     _same(with_graphs, without)
 
 
-def test_graph_replay_nonstationary_start(monkeypatch, case):
+def test_graph_replay_nonstationary_start(case):
     sysm, dt, full = case
     rng = np.random.default_rng(4)
     with pkg.Propagator(sysm, dt, "fp64", history_capacity=1) as p:
@@ -86,6 +86,6 @@ def test_graph_replay_nonstationary_start(monkeypatch, case):
         d0 = p.get_density(0).cpu().numpy()
     a = rng.normal(size=d0.shape) + 1j * rng.normal(size=d0.shape)
     start = d0 + 0.002 * (a + np.conj(np.swapaxes(a, 1, 2)))
-    with_graphs = _run(monkeypatch, True, sysm, dt, full, "bf16x3", start=start)
-    without = _run(monkeypatch, False, sysm, dt, full, "bf16x3", start=start)
+    with_graphs = _run(True, sysm, dt, full, "bf16x3", start=start)
+    without = _run(False, sysm, dt, full, "bf16x3", start=start)
     _same(with_graphs, without)

@@ -26,9 +26,8 @@ def _need_gpu():
     pkg.load_library()
 
 
-def _run(monkeypatch, small, sysm, dt, atab, calls, cap):
-    monkeypatch.setenv("VGTB_SMALL_STEPS", "1" if small else "0")
-    with pkg.Propagator(sysm, dt, "fp64", history_capacity=cap) as p:
+def _run(small, sysm, dt, atab, calls, cap):
+    with pkg.Propagator(sysm, dt, "fp64", history_capacity=cap, small_path=small) as p:
         p.ground_state()
         p.set_field_table(atab)
         p.profile(True)
@@ -50,12 +49,12 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", ["si8_k64", "chain16"])
-def test_small_path_matches_per_step_path(monkeypatch, case):
+def test_small_path_matches_per_step_path(case):
     name, sysm, dt, atab = next(x for x in _cases() if x[0] == case)
     assert sysm.n_orb <= 40 and sysm.gamma is None
     cap = 100
-    h1, d1, p1, prof1 = _run(monkeypatch, True, sysm, dt, atab, CALLS, cap)
-    h0, d0, p0, prof0 = _run(monkeypatch, False, sysm, dt, atab, CALLS, cap)
+    h1, d1, p1, prof1 = _run(True, sysm, dt, atab, CALLS, cap)
+    h0, d0, p0, prof0 = _run(False, sysm, dt, atab, CALLS, cap)
     assert prof1["small"][1] == sum((c + 63) // 64 for c in CALLS)   # one launch per block
     assert prof1["gemm"][1] == 0 and prof0["small"][1] == 0
     for a, b in ((d1, d0), (p1, p0)):
@@ -69,14 +68,13 @@ def test_small_path_matches_per_step_path(monkeypatch, case):
     assert np.abs(h1["q"] - h0["q"]).max() < 1e-12
 
 
-def test_small_path_against_oracle_with_checkpoint(monkeypatch):
+def test_small_path_against_oracle_with_checkpoint():
     c = vs.CONFIGS["si8_k64"]
     sysm = vs.config_system("si8_k64")
     atab = vs.kick_table(1, c["a0"])
     n1, n2 = 90, 60
     d_init, z, _ = oracle.ground_state(sysm)
     ref, st = oracle.propagate(sysm, d_init, atab, c["dt"], n1 + n2, z=z)
-    monkeypatch.setenv("VGTB_SMALL_STEPS", "1")
     with pkg.Propagator(sysm, c["dt"], "fp64", history_capacity=n1 + n2) as p:
         p.ground_state()
         p.set_field_table(atab)

@@ -23,16 +23,16 @@ pytestmark = pytest.mark.gpu
 
 VARIANTS = [
     {},
-    {"VGTB_SPMM_CPT": "1"},
-    {"VGTB_SPMM_CPT": "1", "VGTB_SPMM_GROUP": "4"},
-    {"VGTB_SPMM_CPT": "2"},
-    {"VGTB_SPMM_CPT": "2", "VGTB_SPMM_GROUP": "4"},
-    {"VGTB_SPMM_CB": "2"},
-    {"VGTB_SPMM_CB": "4", "VGTB_SPMM_GROUP": "4"},
-    {"VGTB_SPMM_CB": "1", "VGTB_SPMM_GROUP": "16"},
-    {"VGTB_SPMM_CB": "2", "VGTB_SPMM_GROUP": "16"},
+    {"spmm_variant": 1},
+    {"spmm_variant": 1, "spmm_group": 4},
+    {"spmm_variant": 2},
+    {"spmm_variant": 2, "spmm_group": 4},
+    {"spmm_variant": -2},
+    {"spmm_variant": -4, "spmm_group": 4},
+    {"spmm_variant": -1, "spmm_group": 16},
+    {"spmm_variant": -2, "spmm_group": 16},
 ]
-IDS = ["default"] + ["-".join(f"{k[10:].lower()}{v}" for k, v in c.items()) for c in VARIANTS[1:]]
+IDS = ["default"] + ["-".join(f"{k[5:]}{v}" for k, v in c.items()) for c in VARIANTS[1:]]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -42,12 +42,8 @@ def _need_gpu():
     pkg.load_library()
 
 
-def _run(monkeypatch, env, sysm, dt, atab, n_steps, start=None, precision="fp64"):
-    for k in ("VGTB_SPMM_CPT", "VGTB_SPMM_CB", "VGTB_SPMM_GROUP"):
-        monkeypatch.delenv(k, raising=False)
-    for k, v in env.items():
-        monkeypatch.setenv(k, v)
-    with pkg.Propagator(sysm, dt, precision, history_capacity=n_steps) as p:
+def _run(variant, sysm, dt, atab, n_steps, start=None, precision="fp64"):
+    with pkg.Propagator(sysm, dt, precision, history_capacity=n_steps, **variant) as p:
         if start is None:
             p.ground_state()
         else:
@@ -76,10 +72,10 @@ def ragged_case():
     return sysm, np.stack(start), atab, n, ref, st
 
 
-@pytest.mark.parametrize("env", VARIANTS, ids=IDS)
-def test_variant_matches_oracle_ragged(monkeypatch, ragged_case, env):
+@pytest.mark.parametrize("variant", VARIANTS, ids=IDS)
+def test_variant_matches_oracle_ragged(ragged_case, variant):
     sysm, start, atab, n, ref, st = ragged_case
-    hist, cur, prev = _run(monkeypatch, env, sysm, 0.2, atab, n, start=start)
+    hist, cur, prev = _run(variant, sysm, 0.2, atab, n, start=start)
     for got, want in ((cur, st.d_cur), (prev, st.d_prev)):
         err = max(np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k]) for k in range(sysm.n_k))
         assert err < 1e-10
@@ -96,14 +92,14 @@ def asi64_case():
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("bf16x3", 1e-8), ("fp16x3", 1e-8)])
-def test_variants_agree_asi64(monkeypatch, asi64_case, precision, tol):
+def test_variants_agree_asi64(asi64_case, precision, tol):
     sysm, dt, atab, n = asi64_case
-    base_h, base_d, _ = _run(monkeypatch, VARIANTS[0], sysm, dt, atab, n, precision=precision)
+    base_h, base_d, _ = _run(VARIANTS[0], sysm, dt, atab, n, precision=precision)
     jmax = np.abs(base_h["J"]).max()
     assert jmax > 0
-    for env in VARIANTS[1:]:
-        h, d, _ = _run(monkeypatch, env, sysm, dt, atab, n, precision=precision)
+    for variant in VARIANTS[1:]:
+        h, d, _ = _run(variant, sysm, dt, atab, n, precision=precision)
         dj = np.abs(h["J"] - base_h["J"]).max() / jmax
         dd = max(np.linalg.norm(d[k] - base_d[k]) / np.linalg.norm(base_d[k]) for k in range(sysm.n_k))
-        assert dj < tol, (env, dj)
-        assert dd < tol, (env, dd)
+        assert dj < tol, (variant, dj)
+        assert dd < tol, (variant, dd)

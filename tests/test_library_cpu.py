@@ -144,3 +144,33 @@ def test_fp16_split_form_validated_and_sized():
     fp = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, "fp16x3"))
     assert fp > bf
     assert fp - bf < 16384 * s.n_k + 4096
+
+
+def test_kernel_choices_are_validated_options():
+    """The dense-product tile, the sparse-product variant and row group, and
+    the graph / small-path switches are per-context options; the library reads
+    no environment variable."""
+    _lib()
+    s = vs.config_system("asi64_k8_scc")
+    chain = vs.linear_chain(8)
+    _expect_inval(s, pkg.make_options(0.2, tile=4), match="tile_override")        # FP64: 1-3
+    _expect_inval(s, pkg.make_options(0.2, "fp16x3", tile=6), match="tile_override")
+    assert pkg.vgtb_workspace_size(s, pkg.make_options(0.2, "fp16x3", tile=5)) > 0
+    assert pkg.vgtb_workspace_size(s, pkg.make_options(0.2, propagator="crank_nicolson", tile=3)) > 0
+    _expect_inval(s, pkg.make_options(0.2, spmm_variant=3), match="spmm_variant")
+    _expect_inval(chain, pkg.make_options(0.2, spmm_variant=-2), match="four orbitals")
+    _expect_inval(s, pkg.make_options(0.2, spmm_group=5), match="spmm_group")
+    _expect_inval(s, pkg.make_options(0.2, spmm_variant=1, spmm_group=16), match="matrix-core")
+    bad = pkg.make_options(0.2)
+    bad.flags = 4
+    _expect_inval(s, bad, match="flags")
+    for kw in ({"spmm_variant": -4, "spmm_group": 16}, {"spmm_variant": 2, "spmm_group": 4},
+               {"graphs": False, "small_path": False}):
+        assert pkg.vgtb_workspace_size(s, pkg.make_options(0.2, **kw)) > 0
+    # the row-group size changes the stored neighbour lists, so it reaches the sizing
+    a = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, spmm_group=4))
+    b = pkg.vgtb_workspace_size(s, pkg.make_options(0.2, spmm_group=16))
+    assert a != b
+    src = "".join(open(os.path.join(os.path.dirname(pkg.LIB_PATH), "csrc", f)).read()
+                  for f in os.listdir(os.path.join(os.path.dirname(pkg.LIB_PATH), "csrc")))
+    assert "getenv" not in src

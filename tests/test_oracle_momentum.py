@@ -10,6 +10,7 @@ notes, the orthogonal-basis limit, energy conservation at constant A, and a
 brute-force matrix exponential built here from the raw blocks.
 """
 import dataclasses
+import math
 
 import numpy as np
 import scipy.linalg as sla
@@ -161,3 +162,31 @@ def test_brute_force_matrix_exponential():
         errs.append(_rel(st.d_cur[0], ref))
     assert errs[0] < 0.1
     assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_work_theorem_under_an_scc_pulse():
+    """E(t) - E(0) = Omega int J . E_field dt, E_field = -(1/c) dA/dt, in the
+    momentum coupling: dE/dt = sum_k w_k Re Tr(D_k dH/dA) . dA/dt and
+    c dH/dA = P_k + (A/c) S_k is the current matrix after Eq. 14, so this ties
+    the paramagnetic term P_k of the current to the Hamiltonian of Eq. 12.
+    Second order in dt for the leapfrog."""
+    sysm = vs.amorphous_si(1, (2, 1, 1), seed=1002, gamma_u=0.25)
+    d0, z, _ = oracle.ground_state(sysm)
+    errs = []
+    for dt in (0.2, 0.1):
+        n = int(round(120.0 / dt)) + 1
+        T = 100.0
+        atab = vs.sin2_pulse_table(n, dt, omega=0.15, duration=T, a_peak=2.0)
+        t = np.arange(n) * dt
+        env = np.where(t <= T, 1.0, 0.0)
+        dadt = env * 2.0 * (math.pi / T * np.sin(2 * math.pi * t / T) * np.cos(0.15 * (t - T / 2))
+                            - 0.15 * np.sin(math.pi * t / T) ** 2 * np.sin(0.15 * (t - T / 2)))
+        efield = -dadt / C
+        hist, _ = oracle.propagate(sysm, d0, atab, dt, n, z=z, coupling="momentum")
+        p = sysm.volume * hist["J"][:, 0] * efield
+        work = np.concatenate([[0.0], np.cumsum(0.5 * (p[1:] + p[:-1]) * dt)])
+        de = hist["E"] - hist["E"][0]
+        assert np.abs(de).max() > 1e-5
+        errs.append(np.abs(de - work).max() / np.abs(de).max())
+    assert errs[0] < 2e-2
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs

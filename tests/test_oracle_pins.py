@@ -351,6 +351,82 @@ def test_p9_linearity_passivity_and_symmetry():
     assert im.min() > -0.05 * im.max()
 
 
+def test_p9_mean_subtraction_removes_a_constant_current():
+    """Eq. 15 with the mean removed (Section 3): a constant plus a sinusoid
+    sampled over whole periods gives the transform of the sinusoid alone."""
+    dt, n, tau = 0.01, 40000, 200.0
+    om0 = 2.0 * math.pi * 19 / (n * dt)        # 19 whole periods in the n samples
+    t = np.arange(n) * dt
+    j = 0.37 + np.sin(om0 * t)
+    omegas = np.array([0.1, 0.25, om0, 0.45])
+    sig = oracle.conductivity(j, dt, omegas, e0=1.0, tau0=tau, subtract_mean=True)
+    T = t[-1]
+
+    def prim(x, w):
+        a = 1j * w - 1.0 / tau
+        return np.exp(a * x) / a
+
+    ref = np.array([(prim(T, om + om0) - prim(0, om + om0) - prim(T, om - om0) + prim(0, om - om0)) / (2j)
+                    for om in omegas])
+    assert np.abs(sig - ref).max() < 1e-5 * np.abs(ref).max()
+    # Without the subtraction the constant adds about 0.37 / (1/tau - i omega),
+    # at least 0.37 / 0.45 = 0.82 in magnitude on this grid.
+    raw = oracle.conductivity(j, dt, omegas, e0=1.0, tau0=tau, subtract_mean=False)
+    assert np.abs(raw - ref).min() > 0.5
+
+
+def test_p9_drude_dielectric_of_a_free_electron_current():
+    """Eq. 16 against the Drude form.  With S = I and no overlap gradient the
+    momentum coupling (Eq. 12) leaves a kicked ground state unchanged, so the
+    current is the constant diamagnetic one, J = -(A0/c) N_el / Omega.  With
+    E0 = -A0/c, Eq. 15 (no mean removed) tends to sigma = n_e / (1/tau0 - i w),
+    n_e = N_el / Omega, and Eq. 16 to the damped free-electron dielectric
+    function eps = 1 - w_p^2 / (w^2 + i w / tau0), w_p^2 = 4 pi n_e."""
+    import dataclasses
+    sysm = vs.primitive_diamond(kmesh=(2, 2, 2))
+    sysm = dataclasses.replace(sysm, blk_ds=np.zeros((sysm.n_blocks, 3, 4, 4)))
+    d0, z, _ = oracle.ground_state(sysm)
+    a0, dt, tau = 0.02, 0.2, 20.0
+    n = int(round(20 * tau / dt)) + 1           # exp(-20) of the filter is left at the end
+    hist, _ = oracle.propagate(sysm, d0, vs.kick_table(1, a0), dt, n, z=z, coupling="momentum")
+    jx = hist["J"][:, 0]
+    n_e = sysm.n_electrons / sysm.volume
+    assert np.abs(jx + (a0 / vs.C_LIGHT) * n_e).max() < 1e-11 * (a0 / vs.C_LIGHT) * n_e
+    omegas = np.array([0.05, 0.12, 0.3, 0.61, 1.0])
+    e0 = -a0 / vs.C_LIGHT
+    sig = oracle.conductivity(jx, dt, omegas, e0, tau0=tau, subtract_mean=False)
+    eps = oracle.dielectric(sig, omegas)
+    wp2 = 4.0 * math.pi * n_e
+    drude = 1.0 - wp2 / (omegas ** 2 + 1j * omegas / tau)
+    # The trapezoid rule is off by (dt |i w - 1/tau|)^2 / 12 relative (Euler-Maclaurin).
+    tol = (dt * np.abs(1j * omegas - 1.0 / tau)) ** 2 / 12.0 * 1.5 + 1e-8
+    assert np.all(np.abs(eps - drude) <= tol * np.abs(drude - 1.0)), (eps, drude)
+    assert np.all(eps.imag > 0.0)
+    # Well below the plasma frequency the free-electron gas screens: Re eps < 0.
+    assert eps[0].real < 0.0 and eps[-1].real > 0.0
+
+
+def test_k_weights_enter_every_k_sum():
+    """A k-point split into two copies of half its weight is the same mesh:
+    the current (Eq. 14), the charges and the energy do not change, through an
+    SCC pulse."""
+    sysm = vs.amorphous_si(1, (2, 1, 1), seed=1002, gamma_u=0.25)
+    kp = np.vstack([sysm.kpts[:1], sysm.kpts[:1], sysm.kpts[1:]])
+    kw = np.concatenate([[0.5 * sysm.kw[0]] * 2, sysm.kw[1:]])
+    split = sysm.with_kpts(kp, kw)
+    atab = vs.sin2_pulse_table(120, 0.2, 0.15, 20.0, 0.5)
+    outs = []
+    for s_ in (sysm, split):
+        d0, z, _ = oracle.ground_state(s_)
+        hist, _ = oracle.propagate(s_, d0, atab, 0.2, 120, z=z)
+        outs.append(hist)
+    a, b = outs
+    assert np.abs(a["J"]).max() > 1e-6
+    assert np.abs(a["J"] - b["J"]).max() < 1e-12 * np.abs(a["J"]).max()
+    assert np.abs(a["q"] - b["q"]).max() < 1e-11
+    assert np.abs(a["E"] - b["E"]).max() < 1e-11 * np.abs(a["E"]).max()
+
+
 def test_p10_gamma_point_real_and_zero_current():
     sysm = vs.amorphous_si(1, (1, 1, 1), seed=1002, gamma_u=None)
     d0, z, _ = oracle.ground_state(sysm)
