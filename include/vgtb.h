@@ -311,14 +311,19 @@ void vgtb_destroy(vgtb_ctx *ctx);
  * with the history capacity raised to n_steps) fits in the free part of the
  * arena (first fit); a request larger than the whole arena fails with
  * VGTB_E_NOMEM.  An admitted request is initialised on a worker thread
- * (S_k^-1 and the ground state, Section 3.1; the field table), then stepped in
- * chunks on its own stream, so the kernels of all running requests overlap.
+ * (S_k^-1 and the ground state, the field-free starting point of Section 3;
+ * the field table), then stepped in chunks on its own stream, so the kernels
+ * of all running requests overlap (its context launches every step directly,
+ * VGTB_OPT_NO_GRAPHS).
  * When its n_steps are done, J(t) (n_steps x 3, host j_out, may be NULL) and
  * sigma(omega) of the x current (Eqs. 15-16 with e0 and tau0, n_omega complex
  * values, host sigma_out, may be NULL) are written, and its slot and arena
  * range are released.  The request's system, field table and omega grid must
  * stay valid until the call returns.  stats (n entries) and summary may be
- * NULL.  Results do not depend on the other requests.
+ * NULL.  Results do not depend on the other requests.  A failing request
+ * (invalid, too large, a failed initialisation or step) gets its own status
+ * and message in stats; the others go on.  The call returns VGTB_OK once every
+ * request has finished or failed (VGTB_E_INVAL for a null server or requests).
  */
 typedef struct vgtb_server vgtb_server;
 
@@ -341,6 +346,8 @@ typedef struct {
   int32_t slot;                  /* -1 if never admitted                           */
   size_t workspace_bytes;
   double arrival_s, admitted_s, ready_s, finished_s;   /* seconds on the run clock */
+  char message[128];             /* why the request failed (NUL-terminated; empty
+                                    when status is VGTB_OK)                       */
 } vgtb_request_stats;
 
 typedef struct {

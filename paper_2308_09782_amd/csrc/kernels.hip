@@ -1184,41 +1184,6 @@ __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
 
 // Filtered Fourier transform of the current (Eq. 15) and the dielectric
 // function (Eq. 16): one wavefront per frequency, fixed-order lane sums.
-__global__ __launch_bounds__(64) void k_spectrum(const double *__restrict__ j, int nt, double dt,
-                                                 double jmean, const double *__restrict__ omega,
-                                                 double e0, double tau0, double2 *__restrict__ out) {
-  const int w = blockIdx.x, lane = threadIdx.x;
-  const double om = omega[w];
-  double re = 0.0, im = 0.0;
-  for (int t = lane; t < nt; t += 64) {
-    const double tt = t * dt;
-    const double wt = (t == 0 || t == nt - 1) ? 0.5 * dt : dt;   // trapezoid weights
-    const double g = (j[t] - jmean) * exp(-tt / tau0) * wt;
-    double sn, cs;
-    sincos(om * tt, &sn, &cs);
-    re += cs * g;
-    im += sn * g;
-  }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (lane == 0) {
-    const double sr = re / e0, si = im / e0;
-    out[2 * w] = make_double2(sr, si);
-    // epsilon = 1 + 4 pi i sigma / omega
-    out[2 * w + 1] = make_double2(1.0 - 4.0 * M_PI * si / om, 4.0 * M_PI * sr / om);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_mean(const double *__restrict__ j, int nt, double *out) {
-  __shared__ double red[4];
-  double s = 0.0;
-  for (int t = threadIdx.x; t < nt; t += 256) s += j[t];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) out[0] = (red[0] + red[1] + red[2] + red[3]) / nt;
-}
-
 inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -1426,18 +1391,6 @@ void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk,
                      const_cast<double *>(target), fac, nk, g.n_atoms, 0);
   const int nt = (int)blocks_for(n, 32);
   hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, fac, n, nt);
-}
-
-void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
-                     double tau0, bool subtract_mean, double *scratch_mean, double2 *out,
-                     hipStream_t s) {
-  double jmean = 0.0;
-  if (subtract_mean) {
-    hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, s, j, nt, scratch_mean);
-    (void)hipMemcpyAsync(&jmean, scratch_mean, sizeof(double), hipMemcpyDeviceToHost, s);
-    (void)hipStreamSynchronize(s);
-  }
-  hipLaunchKernelGGL(k_spectrum, dim3(nw), dim3(64), 0, s, j, nt, dt, jmean, omega, e0, tau0, out);
 }
 
 void launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,

@@ -326,7 +326,8 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   c->dlev[1] = cv.template take<double2>(n2);
   c->d0 = z.deviation ? cv.template take<double2>(n2) : nullptr;
   c->w = cv.template take<double2>(n2);
-  c->y = cv.template take<double2>(n2);
+  // y doubles as the spectrum's scratch between steps: at least 4096 doubles.
+  c->y = cv.template take<double2>(std::max<size_t>(n2, 2048));
   c->part = cv.template take<double>((size_t)z.nk * z.na * 5);
   c->v = cv.template take<double>(z.na);
   c->z = cv.template take<double>(z.na);
@@ -1394,26 +1395,14 @@ vgtb_status vgtb_spectrum(vgtb_ctx *c, int64_t n_t, const double *j, double dt, 
     return fail(c, VGTB_E_INVAL, "bad spectrum arguments");
   for (int64_t i = 0; i < n_w; ++i)
     if (!(std::fabs(omega[i]) > 0.0)) return fail(c, VGTB_E_INVAL, "frequencies must be nonzero");
-  // Device scratch: the FP64 product buffer (n_k * N * N complex) is unused between steps.
-  const size_t need = (size_t)n_t + (size_t)n_w + 2 + 4 * (size_t)n_w;
-  const size_t have = 2 * (size_t)c->n * c->n * c->nk;
-  if (need > have) return fail(c, VGTB_E_INVAL, "spectrum too large for the context scratch");
+  // Device scratch: the FP64 product buffer (n_k * N * N complex) is unused
+  // between steps; the trace and the grid stream through it in chunks.
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  double *dj = reinterpret_cast<double *>(c->y);
-  double *dw = dj + n_t;
-  double *dm = dw + n_w;
-  double2 *dout = reinterpret_cast<double2 *>(dm + 1 + ((n_t + n_w + 1) & 1));
-  HIP_TRY(c, hipMemcpyAsync(dj, j, sizeof(double) * n_t, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(dw, omega, sizeof(double) * n_w, hipMemcpyHostToDevice, c->stream));
-  vgtb::launch_spectrum(dj, (int)n_t, dt, dw, (int)n_w, e0, tau0, subtract_mean != 0, dm, dout, c->stream);
-  HIP_TRY(c, hipGetLastError());
-  std::vector<double2> out(2 * n_w);
-  HIP_TRY(c, hipMemcpyAsync(out.data(), dout, sizeof(double2) * 2 * n_w, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (int64_t i = 0; i < n_w; ++i) {
-    if (sigma_out) static_cast<double2 *>(sigma_out)[i] = out[2 * i];
-    if (eps_out) static_cast<double2 *>(eps_out)[i] = out[2 * i + 1];
-  }
+  const size_t cap = 2 * std::max<size_t>((size_t)c->n * c->n * c->nk, 2048);
+  const hipError_t e = vgtb::spectrum_chunked(reinterpret_cast<double *>(c->y), cap,
+                                              c->stream, n_t, j, dt, n_w, omega, e0, tau0,
+                                              subtract_mean != 0, sigma_out, eps_out);
+  if (e != hipSuccess) return fail(c, VGTB_E_DEVICE, std::string("spectrum: ") + hipGetErrorString(e));
   return VGTB_OK;
 }
 

@@ -145,10 +145,16 @@ void launch_trace_target(const PairGraph &g, const double2 *dd, int n, int nk, c
 // Both levels: D <- (target / Tr(D S)) 1/2 (D + D^dag), per k.
 void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk, const double2 *spk,
                     double *tpart, const double *target, double *fac, hipStream_t s);
-// sigma and epsilon interleaved in out (2 * nw complex); j and omega on the device.
-void launch_spectrum(const double *j, int nt, double dt, const double *omega, int nw, double e0,
-                     double tau0, bool subtract_mean, double *scratch_mean, double2 *out,
-                     hipStream_t s);
+// ---- spectrum (spectrum.hip) --------------------------------------------------
+// Eqs. 15-16 of a host current trace through a device scratch of cap doubles
+// (at least spectrum_min_scratch()): trace and frequency grid are streamed
+// in chunks; sigma_host / eps_host (host, n_w complex128 each, either may be
+// null) receive the results.  Synchronises s.
+size_t spectrum_min_scratch();
+hipError_t spectrum_chunked(double *scratch, size_t cap, hipStream_t s, int64_t n_t,
+                            const double *j_host, double dt, int64_t n_w, const double *omega_host,
+                            double e0, double tau0, bool subtract_mean, void *sigma_host,
+                            void *eps_host);
 // Steps [step, step + nsteps) of a small system (see kSmallN); per-step
 // partials [nsteps][nk][na][5] into part, then launch_reduce_steps.
 void launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,

@@ -84,7 +84,7 @@ class VgtbRequestStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("slot", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t), ("arrival_s", ctypes.c_double),
                 ("admitted_s", ctypes.c_double), ("ready_s", ctypes.c_double),
-                ("finished_s", ctypes.c_double)]
+                ("finished_s", ctypes.c_double), ("message", ctypes.c_char * 128)]
 
 
 class VgtbServerStats(ctypes.Structure):
@@ -447,10 +447,11 @@ class Server:
         self.srv = h
 
     def run(self, requests):
-        """requests: dicts with system, dt, precision, n_steps, field (n x 3), arrival_s and
-        optionally rescale_every, omegas, e0, tau0.  Returns (results, summary): per request
-        {status, J (n_steps x 3), sigma, slot, workspace_bytes, arrival_s, admitted_s, ready_s,
-        finished_s}, and the run's {makespan_s, k_steps, k_steps_per_s, peak_bytes, peak_active}."""
+        """requests: dicts with system, dt, n_steps, field (n x 3), arrival_s and optionally
+        precision (default fp16x3), rescale_every, coupling, omegas, e0, tau0.  Returns
+        (results, summary): per request {status, message, J (n_steps x 3), sigma, slot,
+        workspace_bytes, arrival_s, admitted_s, ready_s, finished_s}, and the run's
+        {makespan_s, k_steps, k_steps_per_s, peak_bytes, peak_active}."""
         n = len(requests)
         reqs = (VgtbRequest * max(n, 1))()
         stats = (VgtbRequestStats * max(n, 1))()
@@ -466,7 +467,7 @@ class Server:
             outs.append((jo, so))
             q = reqs[i]
             q.system = ctypes.cast(ctypes.pointer(s), ctypes.c_void_p)
-            q.options = make_options(r["dt"], r.get("precision", "bf16x3"),
+            q.options = make_options(r["dt"], r.get("precision", "fp16x3"),
                                      r.get("rescale_every", 50), 1, r.get("coupling", "peierls"))
             q.n_steps = int(r["n_steps"])
             q.n_field = field.shape[0]
@@ -482,7 +483,8 @@ class Server:
         results = []
         for i in range(n):
             st = stats[i]
-            results.append({"status": int(st.status), "J": outs[i][0], "sigma": outs[i][1],
+            results.append({"status": int(st.status), "message": st.message.decode(errors="replace"),
+                            "J": outs[i][0], "sigma": outs[i][1],
                             "slot": int(st.slot), "workspace_bytes": int(st.workspace_bytes),
                             "arrival_s": st.arrival_s, "admitted_s": st.admitted_s,
                             "ready_s": st.ready_s, "finished_s": st.finished_s})

@@ -270,3 +270,42 @@ def test_spectrum_matches_oracle():
     ref2 = oracle.conductivity(js, 0.05, omegas, 1.0, tau0=150.0, subtract_mean=False)
     assert np.abs(sig2 - ref2).max() < 1e-12 * np.abs(ref2).max()
     assert np.imag(eps).max() > 0
+
+
+@pytest.mark.parametrize("subtract_mean", [True, False])
+def test_spectrum_streamed_through_a_small_scratch(subtract_mean):
+    """Eqs. 15-16 for a trace and a grid far larger than the context's scratch
+    (a 1-atom chain context: 4096 doubles): the trace is cut into about 60
+    chunks and the grid into several, with ragged last chunks; the result
+    equals the oracle's transform of the whole trace."""
+    sysm = vs.linear_chain(2)
+    t = np.arange(200003) * 0.05
+    js = 0.3 + np.sin(0.31 * t) * np.exp(-t / 5000.0) + 0.2 * np.cos(1.7 * t)
+    omegas = np.linspace(0.01, 2.0, 1999)
+    with pkg.Propagator(sysm, 0.2) as p:
+        sig, eps = p.spectrum(js, 0.05, omegas, 0.7, tau0=3000.0, subtract_mean=subtract_mean)
+    ref = oracle.conductivity(js, 0.05, omegas, 0.7, tau0=3000.0, subtract_mean=subtract_mean)
+    assert np.abs(sig - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(eps - oracle.dielectric(ref, omegas)).max() < 1e-11 * np.abs(eps).max()
+
+
+def test_split_k_point_keeps_every_observable():
+    """k-weights enter every k-sum: a k-point split into two copies of half its
+    weight (a non-uniform mesh of three points) gives the same current, charges
+    and energy through an SCC pulse as the two-point mesh, and both match the
+    oracle."""
+    sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
+    kp = np.vstack([sysm.kpts[:1], sysm.kpts[:1], sysm.kpts[1:]])
+    kw = np.concatenate([[0.5 * sysm.kw[0]] * 2, sysm.kw[1:]])
+    split = sysm.with_kpts(kp, kw)
+    atab = vs.sin2_pulse_table(200, 0.2, 0.15, 30.0, 0.4)
+    a = run_gpu(sysm, atab, 0.2, 200)["hist"]
+    b = run_gpu(split, atab, 0.2, 200)["hist"]
+    jmax = np.abs(a["J"]).max()
+    assert jmax > 0
+    assert np.abs(a["J"] - b["J"]).max() < 1e-12 * jmax
+    assert np.abs(a["q"] - b["q"]).max() < 1e-11
+    assert np.abs(a["E"] - b["E"]).max() < 1e-11 * np.abs(a["E"]).max()
+    d0, z, _ = oracle.ground_state(split)
+    ref, _ = oracle.propagate(split, d0, atab, 0.2, 200, z=z)
+    assert np.abs(b["J"] - ref["J"]).max() < 1e-10 * jmax
