@@ -52,8 +52,15 @@ def parse():
                     help="field coupling: Peierls phase on the H0 blocks, or the momentum "
                          "matrix of the overlap gradients (Eq. 12)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--j-err-steps", type=int, default=1000,
+                    help="steps from the ground state over which the headline form's current is "
+                         "compared with the FP64 run's (each context keeps stepping after the "
+                         "timed and latency steps until it has taken this many)")
     ap.add_argument("--cpu-sample-k", type=int, default=4)
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--fused-update", action="store_true",
+                    help="3xBF16 / FP16X3: the dense product and the leapfrog update as one "
+                         "kernel over mirrored tile pairs (VGTB_OPT_FUSE_UPDATE)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants instead of timing them first "
                          "(vgtb_autotune)")
@@ -62,8 +69,9 @@ def parse():
                          "propagation requests and report time-to-spectrum p50/p99")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="mean arrivals per second")
-    ap.add_argument("--serve-steps", type=int, nargs=2, default=[500, 2000],
+    ap.add_argument("--serve-steps", type=int, nargs=2, default=[1000, 10000],
                     help="range of step counts per request")
+    ap.add_argument("--serve-precision", default="fp16x3", choices=["fp64", "fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-arena-gib", type=float, default=64.0)
     ap.add_argument("--accuracy", action="store_true",
@@ -80,10 +88,20 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls", propagator="leapfrog"):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_sample(sysm, atab, dt, n_k_sample, n_steps, coupling, propagator):
+    """Seconds the oracle takes for n_steps steps of the first n_k_sample k-points."""
     import oracle
-    from threadpoolctl import threadpool_info
 
     sub = sysm.with_kpts(sysm.kpts[:n_k_sample])
     rng = np.random.default_rng(0)
@@ -99,20 +117,33 @@ def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls", propag
         cstate = oracle.make_coefficient_state(sub, c0, np.full((n_k_sample, ns), 2.0), z)
         t0 = time.perf_counter()
         oracle.propagate_crank_nicolson(sub, None, None, atab, dt, n_steps, state=cstate, coupling=coupling)
-        el = time.perf_counter() - t0
-    else:
-        state = oracle.make_state(sub, d0, z)
-        t0 = time.perf_counter()
-        oracle.propagate(sub, None, atab, dt, n_steps, state=state, coupling=coupling)
-        el = time.perf_counter() - t0
+        return time.perf_counter() - t0
+    state = oracle.make_state(sub, d0, z)
+    t0 = time.perf_counter()
+    oracle.propagate(sub, None, atab, dt, n_steps, state=state, coupling=coupling)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(sysm, atab, dt, n_k_sample, n_steps, coupling="peierls", propagator="leapfrog"):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload: with
+    the BLAS thread pool at its default (every host thread) and with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    el = _oracle_sample(sysm, atab, dt, n_k_sample, n_steps, coupling, propagator)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        el1 = _oracle_sample(sysm, atab, dt, 1, 1, coupling, propagator)
     return {
         "value": n_k_sample * n_steps / el,
         "unit": "k*steps/s",
         "cores": int(threads),
         "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "host_threads": os.cpu_count(),
         "sample": f"{n_steps} steps x {n_k_sample} of {sysm.n_k} k-points of the same "
                   f"{sysm.n_orb}-orbital system (numpy/BLAS FP64, {el:.1f} s)",
+        "one_thread": {"value": 1.0 / el1, "unit": "k*steps/s", "cores": 1,
+                       "sample": f"1 step x 1 k-point, BLAS limited to one thread ({el1:.1f} s)"},
     }
 
 
@@ -139,11 +170,15 @@ def counter_traffic(precision, workload):
 
 
 def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload, tune=True,
-             coupling="peierls", propagator="leapfrog"):
-    """Ground state, warmup, then `steps` timed steps of one precision form."""
+             coupling="peierls", propagator="leapfrog", j_steps=0, fused_update=True):
+    """Ground state, warmup, then `steps` timed steps of one precision form, then
+    single-step calls for the latency, then more steps (untimed) until j_steps
+    steps have been taken; J of every step is returned."""
     total = warmup + steps
-    prop = vg.Propagator(sysm, dt, precision, history_capacity=max(total + min(steps, 20), 1),
-                         coupling=coupling, propagator=propagator)
+    n_lat = min(steps, 20)
+    span = max(total + n_lat, j_steps, 1)
+    prop = vg.Propagator(sysm, dt, precision, history_capacity=span,
+                         coupling=coupling, propagator=propagator, fused_update=fused_update)
     t_init = time.perf_counter()
     gap = prop.ground_state()
     t_init = time.perf_counter() - t_init
@@ -159,10 +194,8 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
     elapsed = time.perf_counter() - t0
     prop.synchronize()
     prof = prop.profile_read()
-    obs = prop.read_observables(0, total)
     # Latency of single-step calls, after the timed region.
     prop.profile(False)
-    n_lat = min(steps, 20)
     events = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat + 1)]
     events[0].record()
     for i in range(n_lat):
@@ -170,6 +203,9 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
         events[i + 1].record()
     torch.cuda.synchronize()
     step_ms = np.array([events[i].elapsed_time(events[i + 1]) for i in range(n_lat)])
+    if span > total + n_lat:
+        prop.step(span - total - n_lat)
+    obs = prop.read_observables(0, span)
     prop_ns = prop.num_states
     prop.close()
 
@@ -228,6 +264,7 @@ def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, worklo
         "min_gap_ha": gap,
         "trace_drift": float(np.abs(obs["trace"] - sysm.n_electrons).max()),
         "J": obs["J"],
+        "steps_taken": span,
     }
 
 
@@ -301,8 +338,10 @@ def accuracy_run(vg, torch, sysm, atab, dt, forms, n_steps, workload):
 
 def serve_run(vg, args):
     """A seeded Poisson stream of requests: a-Si/c-Si-shaped systems of 8-512 atoms,
-    meshes from Gamma to 4x4x4, sin^2 pulses with omega in [0.05, 0.3] Ha, the 3xBF16
-    form; served by vgtb_server_run with admission by arena footprint."""
+    meshes from Gamma to 4x4x4, sin^2 pulses with omega in [0.05, 0.3] Ha, 1000-10000
+    steps, the FP16X3 form by default; served by vgtb_server_run with admission by arena
+    footprint.  Every request must succeed: a failed one is reported and makes the run
+    exit non-zero."""
     import vgtb_synth as vs
     rng = np.random.default_rng(1005)
     n = args.serve_requests
@@ -326,11 +365,15 @@ def serve_run(vg, args):
         omega = float(rng.uniform(0.05, 0.30))
         dt = 0.2
         field = vs.sin2_pulse_table(steps, dt, omega, 0.5 * steps * dt, 0.05)
-        reqs.append(dict(system=cache[key], dt=dt, precision="bf16x3", n_steps=steps, field=field,
-                         arrival_s=float(arrivals[i]), omegas=omegas))
+        reqs.append(dict(system=cache[key], dt=dt, precision=args.serve_precision, n_steps=steps,
+                         field=field, arrival_s=float(arrivals[i]), omegas=omegas))
     with vg.Server(int(args.serve_arena_gib * 2 ** 30), max_active=args.serve_slots) as srv:
         res, summ = srv.run(reqs)
     ok = [x for x in res if x["status"] == 0]
+    failed = [{"request": i, "status": x["status"], "message": x["message"]}
+              for i, x in enumerate(res) if x["status"] != 0]
+    if not ok:
+        return {"metric": "serving", "requests": n, "completed": 0, "failed": failed}
     tts = np.array([x["finished_s"] - x["arrival_s"] for x in ok])
     wait = np.array([x["admitted_s"] - x["arrival_s"] for x in ok])
     mix = {}
@@ -339,9 +382,9 @@ def serve_run(vg, args):
         mix[k] = mix.get(k, 0) + 1
     return {
         "metric": "serving: time-to-spectrum p50/p99 (s) and aggregate k*steps/s",
-        "requests": n, "completed": len(ok), "rate_per_s": args.serve_rate,
+        "requests": n, "completed": len(ok), "failed": failed, "rate_per_s": args.serve_rate,
         "steps_range": list(args.serve_steps), "slots": args.serve_slots,
-        "arena_gib": args.serve_arena_gib, "dtype": "bf16x3 products, f64 state",
+        "arena_gib": args.serve_arena_gib, "dtype": f"{args.serve_precision} products, f64 state",
         "time_to_spectrum_s": {"p50": float(np.percentile(tts, 50)), "p99": float(np.percentile(tts, 99)),
                                "max": float(tts.max())},
         "admission_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
@@ -367,8 +410,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         return 1
     if args.serve:
-        print(json.dumps(serve_run(vg, args)), flush=True)
-        return 0
+        rec = serve_run(vg, args)
+        print(json.dumps(rec), flush=True)
+        return 1 if rec["failed"] else 0
     cfg = vs.CONFIGS[args.workload]
     sysm = vs.config_system(args.workload)
     dt = cfg["dt"]
@@ -395,13 +439,19 @@ def main():
     offset = min(2000, max(0, atab.shape[0] - total))
     if args.propagator == "crank_nicolson":
         args.precision = "fp64"
+    compare = args.precision != "fp64" and not args.no_fp64_compare
+    j_steps = args.j_err_steps if compare else 0
     head = run_form(vg, torch, sysm, atab, dt, args.precision, args.warmup, args.steps, offset,
                     args.workload, tune=not args.no_autotune, coupling=args.coupling,
-                    propagator=args.propagator)
+                    propagator=args.propagator, j_steps=j_steps,
+                    fused_update=args.fused_update)
+    print(f"timed {args.precision}: {head['value']:.1f} k*steps/s", file=sys.stderr, flush=True)
     ref = None
-    if args.precision != "fp64" and not args.no_fp64_compare:
+    if compare:
         ref = run_form(vg, torch, sysm, atab, dt, "fp64", args.warmup, args.steps, offset,
-                       args.workload, tune=not args.no_autotune, coupling=args.coupling)
+                       args.workload, tune=not args.no_autotune, coupling=args.coupling,
+                       j_steps=j_steps)
+        print(f"timed fp64: {ref['value']:.1f} k*steps/s", file=sys.stderr, flush=True)
 
     n, nk = sysm.n_orb, sysm.n_k
     out = {
@@ -423,6 +473,7 @@ def main():
                                f"{nk} k-points (2x2x2), SCC, sin^2 pulse, dt={dt}",
                    "n_orb": n, "n_k": nk, "n_atoms": sysm.n_atoms, "precision": args.precision,
                    "coupling": args.coupling, "propagator": args.propagator,
+                   "fused_update": args.fused_update,
                    "parallelism": "single GPU, all k-points batched"},
         "roofline": head["roofline"],
         "step_latency_ms": head["step_latency_ms"],
@@ -439,8 +490,11 @@ def main():
                                             "autotune")}
         out["speedup_vs_fp64"] = head["value"] / ref["value"]
         out["j_err_vs_fp64"] = float(np.abs(jm - jr).max() / np.abs(jr).max())
-        out["j_err_steps"] = total
+        out["j_err_steps"] = int(min(head["steps_taken"], ref["steps_taken"]))
+        out["j_err_window"] = (f"steps {offset}..{offset + out['j_err_steps'] - 1} of the pulse, "
+                               "both forms from the ground state")
     if not args.no_cpu_baseline:
+        print("timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sysm, atab[offset:], dt, args.cpu_sample_k, args.cpu_sample_steps,
                                            args.coupling, args.propagator)
     print(json.dumps(out), flush=True)

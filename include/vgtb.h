@@ -134,8 +134,12 @@ typedef enum { VGTB_PROP_LEAPFROG = 0, VGTB_PROP_CRANK_NICOLSON = 1 } vgtb_propa
 enum {
   VGTB_OPT_NO_GRAPHS = 1,      /* launch every step directly (no captured two-step
                                   graphs); same results bit for bit               */
-  VGTB_OPT_NO_SMALL_PATH = 2   /* no whole-steps-per-launch path for small FP64
+  VGTB_OPT_NO_SMALL_PATH = 2,  /* no whole-steps-per-launch path for small FP64
                                   non-SCC systems; same results to rounding       */
+  VGTB_OPT_FUSE_UPDATE = 4     /* 3xBF16 / FP16X3 on 128x128 tiles: the dense
+                                  product and the leapfrog update as one kernel over
+                                  mirrored tile pairs instead of two launches; same
+                                  results bit for bit (measured no faster)          */
 };
 
 /*

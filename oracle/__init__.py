@@ -11,10 +11,13 @@ is stated in the docstring.  All arithmetic is complex128 / float64.
 
 Pinned by tests/test_oracle_*.py (closed-form leapfrog solution, brute-force
 matrix-exponential propagation, invariants, the gauge identity, textbook sp3
-and single-orbital-chain models, SCC special cases, spectrum closed forms; for
-the momentum-matrix coupling of Eq. 12: Hermiticity, the closed-form
-diamagnetic current, the |A|^2 term as a pure phase, the orthogonal-basis limit,
-energy conservation at constant A and brute-force propagation; for the
+and single-orbital-chain models, SCC special cases and the work theorem,
+spectrum closed forms: a filtered sinusoid, the mean subtraction, and the damped
+free-electron (Drude) dielectric function for Eq. 16; a k-point split into two
+halves of its weight; for the momentum-matrix coupling of Eq. 12: Hermiticity,
+the closed-form diamagnetic current, the |A|^2 term as a pure phase, the
+orthogonal-basis limit, energy conservation at constant A, the work theorem of
+its current matrix under an SCC pulse and brute-force propagation; for the
 Crank-Nicolson propagation of the coefficients (Eq. 5): the closed-form
 Cayley-transform solution, exact S-unitarity, stationarity of the ground state
 and second-order convergence towards independent fine-step integrators).

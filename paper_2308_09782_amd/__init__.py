@@ -10,6 +10,14 @@ from .vgtb import (  # noqa: F401
     Propagator,
     Server,
     VgtbError,
+    VGTB_OK,
+    VGTB_E_INVAL,
+    VGTB_E_STATE,
+    VGTB_E_NOT_PD,
+    VGTB_E_UNSTABLE,
+    VGTB_E_NOMEM,
+    VGTB_E_DEVICE,
+    VGTB_E_NONFINITE,
     load_library,
     make_options,
     make_system_struct,

@@ -170,35 +170,24 @@ __global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict
 //    the next plane's B fragments are read while the current plane's MFMAs run.
 constexpr int BM2 = 128, BN2 = 128;
 
+// The main loop of one 128 x 128 tile (rows bm.., columns bn.. of the batch
+// entry at element offset boff): zeroes and fills the accumulators cr, ci of
+// this wavefront.  Ends with a workgroup barrier, after which LDS is free.
 template <int E, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint16_t *__restrict__ A,
-                                                                     const uint16_t *__restrict__ B,
-                                                                     float2 *__restrict__ Y, int n,
-                                                                     int np, int batch_count,
-                                                                     int tiles_m, int tiles_n,
-                                                                     const float *__restrict__ sa,
-                                                                     const float *__restrict__ sb) {
+__device__ __forceinline__ void split128_accumulate(
+    const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int np, size_t plane, size_t boff,
+    int bm, int bn, u32x4 (&As)[2][4][BM2][APAD / 8], u32x4 (&Bs)[2][4][BK / 8][BN2],
+    v4f (&cr)[BM2 / WGM / 16][BN2 / WGN / 16], v4f (&ci)[BM2 / WGM / 16][BN2 / WGN / 16]) {
   constexpr int NT2 = 64 * WGM * WGN;
   constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
   constexpr int LD = 2048 / NT2;             // u32x4 per thread per operand and stage
-  __shared__ u32x4 As[2][4][BM2][APAD / 8];
-  __shared__ u32x4 Bs[2][4][BK / 8][BN2];
-
-  const int tiles = tiles_m * tiles_n;
-  const int lin = xcd_slot(blockIdx.x + blockIdx.y * tiles, tiles * batch_count);
-  const int batch = lin / tiles;
-  int tm, tn;
-  grouped_tile(lin % tiles, tiles_m, tiles_n, 4, tm, tn);
-  const int bm = tm * BM2;
-  const int bn = tn * BN2;
-
-  const size_t plane = (size_t)batch_count * np * np;
-  const size_t boff = (size_t)batch * np * np;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // An opaque copy of the thread index: a kernel that runs this loop twice
+  // must not keep the lane offsets of the second loop live through the first.
+  int tid;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+  const int lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * (BM2 / WGM), wn0 = (wave % WGN) * (BN2 / WGN);
   const int lr = lane & 15, lg = lane >> 4;
-
-  v4f cr[TM][TN], ci[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -317,6 +306,37 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint
 #undef AROW
 #undef ACOL
 
+}
+
+template <int E, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint16_t *__restrict__ A,
+                                                                     const uint16_t *__restrict__ B,
+                                                                     float2 *__restrict__ Y, int n,
+                                                                     int np, int batch_count,
+                                                                     int tiles_m, int tiles_n,
+                                                                     const float *__restrict__ sa,
+                                                                     const float *__restrict__ sb) {
+  constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
+  __shared__ u32x4 As[2][4][BM2][APAD / 8];
+  __shared__ u32x4 Bs[2][4][BK / 8][BN2];
+
+  const int tiles = tiles_m * tiles_n;
+  const int lin = xcd_slot(blockIdx.x + blockIdx.y * tiles, tiles * batch_count);
+  const int batch = lin / tiles;
+  int tm, tn;
+  grouped_tile(lin % tiles, tiles_m, tiles_n, 4, tm, tn);
+  const int bm = tm * BM2;
+  const int bn = tn * BN2;
+
+  const size_t plane = (size_t)batch_count * np * np;
+  const size_t boff = (size_t)batch * np * np;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WGN) * (BM2 / WGM), wn0 = (wave % WGN) * (BN2 / WGN);
+  const int lr = lane & 15, lg = lane >> 4;
+
+  v4f cr[TM][TN], ci[TM][TN];
+  split128_accumulate<E, WGM, WGN>(A, B, np, plane, boff, bm, bn, As, Bs, cr, ci);
+
   float2 *Yb = Y + (size_t)batch * n * n;
   const float us = unscale(sa, sb, batch);
 #pragma unroll
@@ -330,6 +350,172 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint
         if (row < n && col < n)
           Yb[(size_t)row * n + col] = make_float2(us * cr[a][b][j], us * ci[a][b][j]);
       }
+}
+
+// The dense product fused with the leapfrog update of the deviation form
+// (Eq. 13 on Eq. 6): D_out = D_base - i fac (Y - Y^dag) (+ fac m0) with
+// Y = G + W in FP64, G = (S^-1 - I) W the reduced product.  Y - Y^dag pairs
+// element (i, j) with (j, i), so the unit of work is a pair of mirrored
+// 128 x 128 tiles: a workgroup computes G of tile (I, J) (I < J), writes it to
+// Y, computes G of tile (J, I) in registers, and then forms both tiles of
+// D_out; a diagonal tile (I, I) is a unit of its own.  Only the workgroup of a
+// unit touches its tiles of Y and D, so no workgroup waits for another.  Per
+// batch entry the T (T - 1) / 2 pairs come first, then the T diagonal tiles
+// (the dispatch then balances eight tiles per CU on a 16 x 16 tile grid); with
+// a multiple of eight batch entries each XCD takes whole batch entries.  The
+// arithmetic of every output element is that of k_update (same FP64 sums in
+// the same order), so the results are the same bits.
+//
+// Epilogue of one 16 x 16 MFMA tile (a, b) of a wavefront: own elements
+// (R0 + 4 lg + j, C0 + lr) from the registers, mirror elements
+// (C0 + 4 lg + j, R0 + lr) from Y; each is formed in FP64 and passed through
+// per-wavefront LDS buffers to the lane that needs it transposed.
+template <int E, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128_update(
+    const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float2 *__restrict__ Y,
+    const float2 *__restrict__ W, const double2 *__restrict__ m0, const double2 *dbase,
+    double2 *dout, int n, int np, int batch_count, int T, double fac, const float *__restrict__ sa,
+    const float *__restrict__ sb, int64_t *ctr) {
+  constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
+  __shared__ u32x4 As[2][4][BM2][APAD / 8];
+  __shared__ u32x4 Bs[2][4][BK / 8][BN2];
+
+  const int units = T * (T + 1) / 2, npairs = T * (T - 1) / 2;
+  const int lin = xcd_slot(blockIdx.x, units * batch_count);
+  const int batch = lin / units;
+  const int u = lin % units;
+  // Pairs in blocks of four tile rows, column-major within a block (like
+  // grouped_tile), so that the units resident together share operand panels.
+  int ti = 0, tj = 0;
+  const bool pair = u < npairs;
+  if (pair) {
+    int rem = u;
+    for (int g0 = 0; g0 < T; g0 += 4) {
+      const int g1 = min(g0 + 4, T);
+      int cnt = 0;   // pairs (I, J) with I in [g0, g1), J > I
+      for (int i = g0; i < g1; ++i) cnt += T - 1 - i;
+      if (rem >= cnt) {
+        rem -= cnt;
+        continue;
+      }
+      for (int j = g0 + 1; j < T; ++j) {
+        const int rows = min(g1, j) - g0;   // I in [g0, min(g1, j))
+        if (rem < rows) {
+          ti = g0 + rem;
+          tj = j;
+          break;
+        }
+        rem -= rows;
+      }
+      break;
+    }
+  } else {
+    ti = tj = u - npairs;
+  }
+
+  const size_t plane = (size_t)batch_count * np * np;
+  const size_t boff = (size_t)batch * np * np;
+  const size_t base = (size_t)batch * n * n;
+  float2 *Yb = Y + base;
+  const float2 *Wb = W + base;
+  const float us = unscale(sa, sb, batch);
+  // The lane-dependent indices of the stores are formed after each main loop
+  // from an opaque copy of the thread index, so that the compiler does not keep
+  // them live through the loops (the 16-wavefront tile has no registers to spare).
+  auto opaque_tid = [] {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+  };
+
+  v4f cr[TM][TN], ci[TM][TN];
+  // Tile (I, J): G to Y.
+  split128_accumulate<E, WGM, WGN>(A, B, np, plane, boff, ti * BM2, tj * BN2, As, Bs, cr, ci);
+  {
+    const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / WGN) * (BM2 / WGM), wn0 = (wave % WGN) * (BN2 / WGN);
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = ti * BM2 + wm0 + a * 16 + 4 * lg + j;
+          const int col = tj * BN2 + wn0 + b * 16 + lr;
+          if (row < n && col < n)
+            Yb[(size_t)row * n + col] = make_float2(us * cr[a][b][j], us * ci[a][b][j]);
+        }
+  }
+  // Own tile in registers: (J, I) for a pair, else (I, I) (the accumulators as they are).
+  if (pair) split128_accumulate<E, WGM, WGN>(A, B, np, plane, boff, tj * BM2, ti * BN2, As, Bs, cr, ci);
+  __syncthreads();   // every wavefront's stores to Y are visible to the workgroup; LDS is free
+  const int tid = opaque_tid(), lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * (BM2 / WGM), wn0 = (wave % WGN) * (BN2 / WGN);
+  const int lr = lane & 15, lg = lane >> 4;
+  const int obm = tj * BM2, obn = ti * BN2;   // own tile rows, columns
+  // Per wavefront: own Y values (16 x 17 doubles2, in the A stages) and mirror
+  // Y values (16 x 16, rotated by the row so that transposed reads hit
+  // distinct banks, in the B stages).
+  double2 *yob = reinterpret_cast<double2 *>(&As[0][0][0][0]) + wave * (16 * 17);
+  double2 *ymb = reinterpret_cast<double2 *>(&Bs[0][0][0][0]) + wave * (16 * 16);
+  auto ym_at = [&](int p, int q) -> double2 & { return ymb[p * 16 + ((p + q) & 15)]; };
+
+  auto out = [&](int row, int col, double2 yv, double2 yt) {
+    const size_t idx = base + (size_t)row * n + col;
+    const double xr = yv.x - yt.x;           // X = Y - conj(Y^T)
+    const double xi = yv.y + yt.y;
+    const double2 bv = dbase[idx];
+    double2 o = make_double2(bv.x + fac * xi, bv.y - fac * xr);
+    if (m0 != nullptr) {
+      const double2 mv = m0[idx];
+      o.x += fac * mv.x;
+      o.y += fac * mv.y;
+    }
+    dout[idx] = o;
+  };
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int R0 = obm + wm0 + a * 16, C0 = obn + wn0 + b * 16;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * lg + j;
+        double2 yo = make_double2(0.0, 0.0);            // own element (R0 + r, C0 + lr)
+        if (R0 + r < n && C0 + lr < n) {
+          const float2 w = Wb[(size_t)(R0 + r) * n + C0 + lr];
+          yo = make_double2((double)(us * cr[a][b][j]), (double)(us * ci[a][b][j]));
+          yo.x += (double)w.x;
+          yo.y += (double)w.y;
+        }
+        yob[r * 17 + lr] = yo;
+        double2 ym = make_double2(0.0, 0.0);            // mirror element (C0 + r, R0 + lr)
+        if (C0 + r < n && R0 + lr < n) {
+          const size_t mi = (size_t)(C0 + r) * n + R0 + lr;
+          const float2 g = Yb[mi];
+          const float2 w = Wb[mi];
+          ym = make_double2((double)g.x, (double)g.y);
+          ym.x += (double)w.x;
+          ym.y += (double)w.y;
+        }
+        ym_at(r, lr) = ym;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 4 * lg + j, c = lr;
+        // Own output (R0 + r, C0 + c), paired with Y(C0 + c, R0 + r).
+        if (R0 + r < n && C0 + c < n) out(R0 + r, C0 + c, yob[r * 17 + c], ym_at(c, r));
+        // Mirror output (C0 + r, R0 + c), paired with Y(R0 + c, C0 + r); a
+        // diagonal tile is its own mirror and writes its own outputs only.
+        if (pair && C0 + r < n && R0 + c < n) out(C0 + r, R0 + c, ym_at(r, c), yob[c * 17 + r]);
+      }
+      __syncthreads();
+    }
+  // The step is done once this kernel has run: advance the device step index
+  // (no other workgroup of this kernel reads it).
+  if (ctr != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *ctr += 1;
 }
 
 // tile: 1 = 64 x 64 (four wavefronts); 128 x 128 (np a multiple of 128 only)
@@ -359,7 +545,35 @@ static void launch_e(const uint16_t *a, const uint16_t *b, float2 *y, int n, int
   }
 }
 
+template <int E>
+static bool launch_update_e(const uint16_t *a, const uint16_t *b, float2 *y, const float2 *w,
+                            const double2 *m0, const double2 *dbase, double2 *dout, int n, int np,
+                            int batch, double fac, int64_t *ctr, hipStream_t s, int tile,
+                            const float *sa, const float *sb) {
+  if (tile == 0) tile = (np % BM2 == 0 && np >= 512) ? 2 : 1;
+  if (tile < 2 || tile > 5 || np % BM2 != 0) return false;
+  const int T = np / BM2;
+  const dim3 grid(T * (T + 1) / 2 * batch);
+#define VG_UPD(WGM, WGN)                                                                           \
+  hipLaunchKernelGGL((k_cgemm_split16_128_update<E, WGM, WGN>), grid, dim3(64 * WGM * WGN), 0, s, a, b, y, \
+                     w, m0, dbase, dout, n, np, batch, T, fac, sa, sb, ctr)
+  if (tile == 2) VG_UPD(4, 4);
+  else if (tile == 3) VG_UPD(2, 4);
+  else if (tile == 4) VG_UPD(4, 2);
+  else VG_UPD(2, 2);
+#undef VG_UPD
+  return true;
+}
+
 }  // namespace
+
+bool launch_cgemm_update_split16(int fmt, const uint16_t *a, const uint16_t *b, float2 *y,
+                                 const float2 *w, const double2 *m0, const double2 *dbase,
+                                 double2 *dout, int n, int np, int batch, double fac, int64_t *ctr,
+                                 const float *sa, const float *sb, hipStream_t s, int tile) {
+  if (fmt == 3) return launch_update_e<1>(a, b, y, w, m0, dbase, dout, n, np, batch, fac, ctr, s, tile, sa, sb);
+  return launch_update_e<0>(a, b, y, w, m0, dbase, dout, n, np, batch, fac, ctr, s, tile, nullptr, nullptr);
+}
 
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                          hipStream_t s, int tile) {

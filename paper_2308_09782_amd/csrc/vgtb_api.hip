@@ -249,7 +249,7 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
       return VGTB_E_INVAL;
     }
   }
-  if ((o->flags & ~(VGTB_OPT_NO_GRAPHS | VGTB_OPT_NO_SMALL_PATH)) != 0) {
+  if ((o->flags & ~(VGTB_OPT_NO_GRAPHS | VGTB_OPT_NO_SMALL_PATH | VGTB_OPT_FUSE_UPDATE)) != 0) {
     msg = "unknown option flags";
     return VGTB_E_INVAL;
   }
@@ -641,9 +641,20 @@ void enqueue_step(vgtb_ctx *c, hipStream_t s, bool may_time) {
   // with only the second term in reduced precision.  The state D stays FP64.
   const int fmt = product_format(c);
   run(VGTB_K_SPMM, [&] { launch_deviation_spmm(c, dcur, fmt, c->spmm_variant, s); });
-  run(VGTB_K_GEMM, [&] { launch_reduced_product(c, fmt, c->gemm_tile, s); });
   const float2 *wid = fmt == 1 ? static_cast<const float2 *>(c->w_lo) : c->w32;
   const double2 *m0 = c->m0_active ? c->m0 : nullptr;
+  if (fmt >= 2 && c->fuse_update) {
+    // The 16-bit split product and the update in one launch over mirrored tile pairs.
+    bool done = false;
+    run(VGTB_K_GEMM, [&] {
+      done = vgtb::launch_cgemm_update_split16(
+          fmt, static_cast<const uint16_t *>(c->sinv_lo), static_cast<const uint16_t *>(c->w_lo), c->y_lo,
+          wid, m0, first ? dcur : doth, doth, n, c->np, nk, first ? c->dt : 2.0 * c->dt, c->ctr,
+          fmt == 3 ? c->scale_a : nullptr, fmt == 3 ? c->scale_w : nullptr, s, c->gemm_tile);
+    });
+    if (done) return;
+  }
+  run(VGTB_K_GEMM, [&] { launch_reduced_product(c, fmt, c->gemm_tile, s); });
   run(VGTB_K_UPDATE, [&] {
     vgtb::launch_update_split(c->y_lo, wid, m0, first ? dcur : doth, doth, n, nk,
                               first ? c->dt : 2.0 * c->dt, c->ctr, s);
@@ -823,6 +834,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->ctr = dp.ctr;
   c->small_path = z.small;
   c->use_graphs = !(o->flags & VGTB_OPT_NO_GRAPHS) && !z.cn;
+  c->fuse_update = (o->flags & VGTB_OPT_FUSE_UPDATE) != 0;
   c->cn = z.cn;
   c->aug = dp.aug;
   c->cinv = dp.cinv;

@@ -130,8 +130,8 @@ void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
 // ctr (may be null): advanced by one when the update has run.
 void launch_update(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                    double fac, int64_t *ctr, hipStream_t s);
-// D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each);
-// m0 may be null.
+// D_out = D_base - i fac (Y - Y^dag) + fac m0 with Y = W + G (complex64 each,
+// summed in FP64); m0 may be null.
 void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, const double2 *dbase,
                          double2 *dout, int n, int nk, double fac, int64_t *ctr, hipStream_t s);
 // D_out = D_base - i (Y - Y^dag) (used to form the constant term m0 = -i X0).
@@ -205,6 +205,16 @@ void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n,
 // The same product on fp16 planes scaled per k by sa[k] (A) and sb[k] (B).
 void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                         const float *sa, const float *sb, hipStream_t s, int tile = 0);
+// The 16-bit split product fused with the leapfrog update (fmt 2: bf16, 3:
+// scaled fp16): G = (S^-1 - I) W into y for the tiles I <= J, and
+// dout = dbase - i fac (Y - Y^dag) + fac m0 (m0 may be null) with Y = G + w,
+// the same bits as launch_cgemm_* followed by launch_update_split; ctr (may be
+// null) advanced by one.  Only for the 128 x 128 tiles (tile 2-5, or 0 where
+// the size rule picks them); returns false, launching nothing, otherwise.
+bool launch_cgemm_update_split16(int fmt, const uint16_t *a, const uint16_t *b, float2 *y,
+                                 const float2 *w, const double2 *m0, const double2 *dbase,
+                                 double2 *dout, int n, int np, int batch, double fac, int64_t *ctr,
+                                 const float *sa, const float *sb, hipStream_t s, int tile);
 
 // ---- launchers (split_f16.hip) ------------------------------------------------
 // Power-of-two scale per k putting max(|re|, |im|) in [2^13, 2^14); part holds
@@ -240,6 +250,8 @@ struct vgtb_ctx {
   bool scc = false, z_from_ground_state = false;
   bool small_path = false;     // whole blocks of steps per launch (kSmallN)
   bool use_graphs = true;      // replay captured two-step graphs (general path)
+  bool fuse_update = false;    // 16-bit split forms: product and update in one launch
+                               // (on the 128 x 128 tiles)
   hipStream_t cap_stream = nullptr;            // private stream graphs are captured on
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps, by the parity of cur
   int64_t ring_lo = -1;        // first step whose field is in the ring (-1: none)

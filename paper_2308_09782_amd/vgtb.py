@@ -54,7 +54,7 @@ class VgtbSystem(ctypes.Structure):
     ]
 
 
-OPT_NO_GRAPHS, OPT_NO_SMALL_PATH = 1, 2
+OPT_NO_GRAPHS, OPT_NO_SMALL_PATH, OPT_FUSE_UPDATE = 1, 2, 4
 
 
 class VgtbOptions(ctypes.Structure):
@@ -203,9 +203,11 @@ def make_system_struct(system):
 def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
                  history_capacity: int = 1024, coupling: str = "peierls",
                  propagator: str = "leapfrog", tile: int = 0, spmm_variant: int = 0,
-                 spmm_group: int = 0, graphs: bool = True, small_path: bool = True) -> VgtbOptions:
+                 spmm_group: int = 0, graphs: bool = True, small_path: bool = True,
+                 fused_update: bool = False) -> VgtbOptions:
     """vgtb_options; tile, spmm_variant and spmm_group are the header's kernel
-    choices (0 = default), graphs / small_path clear the VGTB_OPT_NO_* flags."""
+    choices (0 = default); graphs / small_path clear the VGTB_OPT_NO_* flags,
+    fused_update sets VGTB_OPT_FUSE_UPDATE."""
     o = VgtbOptions()
     o.dt = float(dt)
     o.precision = PRECISIONS[precision]
@@ -216,7 +218,8 @@ def make_options(dt: float, precision: str = "fp64", rescale_every: int = 50,
     o.tile_override = int(tile)
     o.spmm_variant = int(spmm_variant)
     o.spmm_group = int(spmm_group)
-    o.flags = (0 if graphs else OPT_NO_GRAPHS) | (0 if small_path else OPT_NO_SMALL_PATH)
+    o.flags = ((0 if graphs else OPT_NO_GRAPHS) | (0 if small_path else OPT_NO_SMALL_PATH)
+               | (OPT_FUSE_UPDATE if fused_update else 0))
     return o
 
 
@@ -249,7 +252,8 @@ class Propagator:
     def __init__(self, system, dt: float, precision: str = "fp64", rescale_every: int = 50,
                  history_capacity: int = 1024, device: str = "cuda:0", coupling: str = "peierls",
                  propagator: str = "leapfrog", **kernel_options):
-        """kernel_options: tile, spmm_variant, spmm_group, graphs, small_path (make_options)."""
+        """kernel_options: tile, spmm_variant, spmm_group, graphs, small_path, fused_update
+        (make_options)."""
         torch = _torch()
         self._torch = torch
         self.lib = load_library()

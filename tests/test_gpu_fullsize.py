@@ -1,12 +1,19 @@
 """Full-size checks: the 512-atom a-Si workload (2048 orbitals, 8 k-points, SCC)
-in the launch configuration bench.py times.
+in the launch configuration bench.py times, and the 216-atom c-Si cell on its
+6 x 6 x 6 mesh (216 k-points in every launch).
 
-The oracle cannot propagate this size quickly, so it checks (1) one step from a
-seeded non-stationary density on sampled columns, which it evaluates one by
-one with the column form of Eq. 6, and (2) properties that hold at any size:
+(1) 30 steps at the pulse peak from the ground state against a fixture the
+oracle wrote (tests/golden/make_fullsize_fixtures.py): the current, energy,
+trace and charges of every step and two columns of both final levels of all
+8 k-points, with the benchmark's dense-product tiles forced; (2) 20 steps of
+the 216-k kick against its oracle fixture (J, E, Tr per step, sixteen
+sampled elements of both levels of every k-point); (3) one step from a seeded
+non-stationary density on sampled columns, which the oracle evaluates one by
+one with the column form of Eq. 6; (4) properties that hold at any size:
 bit-exact Hermiticity, Tr(D S) conservation and stationarity of the ground
 state at zero field.
 """
+import os
 import dataclasses
 
 import numpy as np
@@ -60,6 +67,76 @@ def _one_step(sysm, d0, a, precision):
         cols = out[:, :, COLS].cpu().numpy()
         rows = out[:, COLS, :].cpu().numpy()
     return cols, rows
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.parametrize("precision,tile", [("fp64", 3), ("fp16x3", 2)])
+def test_pulse_peak_30_steps_against_oracle_fixture(precision, tile):
+    fx = np.load(os.path.join(GOLDEN, "asi512_k8_scc_pulse30.npz"))
+    sysm = vs.config_system("asi512_k8_scc")
+    n = int(fx["n_steps"])
+    cols = fx["cols"]
+    print(f"asi512 {precision} tile {tile}: {n} steps", flush=True)
+    with pkg.Propagator(sysm, DT, precision, history_capacity=n, tile=tile) as p:
+        p.ground_state()
+        p.set_field_table(fx["field"])
+        p.step(n)
+        h = p.read_observables(0, n)
+        tc = torch.as_tensor(cols, dtype=torch.long)
+        cur = p.get_density(0)[:, :, tc].cpu().numpy()
+        prev = p.get_density(1)[:, :, tc].cpu().numpy()
+    jmax = np.abs(fx["J"]).max()
+    jerr = np.abs(h["J"] - fx["J"]).max() / jmax
+    print(f"asi512 {precision}: J err {jerr:.2e}", flush=True)
+    assert jmax > 0
+    if precision == "fp64":
+        for k in range(sysm.n_k):
+            for got, want in ((cur[k], fx["cur_cols"][k]), (prev[k], fx["prev_cols"][k])):
+                assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-10
+        assert jerr < 1e-10
+        assert np.abs(h["E"] - fx["E"]).max() < 1e-11 * np.abs(fx["E"]).max()
+        assert np.abs(h["trace"] - fx["trace"]).max() < 1e-11 * np.abs(fx["trace"]).max()
+        assert np.abs(h["q"] - fx["q"]).max() < 1e-10
+    else:
+        assert jerr < 1e-5
+        assert np.abs(h["q"] - fx["q"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_csi216_all_k_kick_against_oracle_fixture(precision):
+    fx = np.load(os.path.join(GOLDEN, "csi216_k216_kick20.npz"))
+    c = vs.CONFIGS["csi216_k216"]
+    sysm = vs.config_system("csi216_k216")
+    n = int(fx["n_steps"])
+    print(f"csi216 {precision}: {n} steps over {sysm.n_k} k-points", flush=True)
+    with pkg.Propagator(sysm, c["dt"], precision, history_capacity=n) as p:
+        p.ground_state()
+        d_init = p.get_density(0)
+        p.set_field_table(vs.kick_table(1, c["a0"]))
+        p.step(n)
+        h = p.read_observables(0, n)
+        kk = torch.arange(sysm.n_k, device=d_init.device)[:, None]
+        rows = torch.from_numpy(fx["rows"]).to(d_init.device)
+        cols = torch.from_numpy(fx["cols"]).to(d_init.device)
+        d0s = d_init[kk, rows, cols].cpu().numpy()
+        cur = p.get_density(0)[kk, rows, cols].cpu().numpy()
+        prev = p.get_density(1)[kk, rows, cols].cpu().numpy()
+    jmax = np.abs(fx["J"]).max()
+    jerr = np.abs(h["J"] - fx["J"]).max() / jmax
+    print(f"csi216 {precision}: J err {jerr:.2e}", flush=True)
+    assert jmax > 0
+    scale = np.abs(fx["d0_samples"]).max()
+    assert np.abs(d0s - fx["d0_samples"]).max() < 1e-11 * scale
+    if precision == "fp64":
+        assert np.abs(cur - fx["cur"]).max() < 1e-10 * scale
+        assert np.abs(prev - fx["prev"]).max() < 1e-10 * scale
+        assert jerr < 1e-10
+        assert np.abs(h["E"] - fx["E"]).max() < 1e-11 * np.abs(fx["E"]).max()
+        assert np.abs(h["trace"] - fx["trace"]).max() < 1e-11 * np.abs(fx["trace"]).max()
+    else:
+        assert jerr < 1e-5
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp16x3", "bf16x3", "fp32"])

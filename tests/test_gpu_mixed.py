@@ -74,8 +74,9 @@ def test_c1_mixed_current_within_tolerance(c1_reference, precision):
     assert np.abs(h["trace"] - sysm.n_electrons).max() < 1e-9
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
-def test_c2_mixed_scc_pulse(precision):
+@pytest.fixture(scope="module")
+def c2_reference():
+    """The oracle's 1000 steps of the 64-atom SCC pulse at the pulse peak."""
     c = vs.CONFIGS["asi64_k8_scc"]
     sysm = vs.config_system("asi64_k8_scc")
     n = 1000
@@ -83,11 +84,43 @@ def test_c2_mixed_scc_pulse(precision):
     atab = full[1500:1500 + n]
     d0, z, _ = oracle.ground_state(sysm)
     ref, st = oracle.propagate(sysm, d0, atab, c["dt"], n, z=z)
-    h, cur, _ = run_gpu(sysm, atab, c["dt"], n, precision)
+    return sysm, atab, c["dt"], n, ref, st
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_c2_mixed_scc_pulse(c2_reference, precision):
+    sysm, atab, dt, n, ref, st = c2_reference
+    h, cur, _ = run_gpu(sysm, atab, dt, n, precision)
     err = j_err(h, ref)
     print(f"{precision}: J err {err:.2e}, rho err {rho_err(cur, st.d_cur):.2e}")
     assert err < J_TOL
     assert np.abs(h["q"] - ref["q"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("precision,tile", [("fp64", 3), ("fp64", 2), ("fp16x3", 2), ("fp16x3", 5),
+                                            ("bf16x3", 2)])
+def test_c2_scc_pulse_with_the_timed_tiles(c2_reference, precision, tile):
+    """The dense-product tiles the benchmark times (FP64: 128 x 64; the split
+    forms: 128 x 128 with sixteen wavefronts, fused with the update), forced on
+    the 1000-step 64-atom SCC pulse: FP64 density within 1e-10 on both levels
+    and current within 1e-10 of max|J|; the split forms' current within 1e-5."""
+    sysm, atab, dt, n, ref, st = c2_reference
+    with pkg.Propagator(sysm, dt, precision, history_capacity=n, tile=tile) as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.step(n)
+        h = p.read_observables(0, n)
+        cur = p.get_density(0).cpu().numpy()
+        prev = p.get_density(1).cpu().numpy()
+    err = j_err(h, ref)
+    print(f"{precision} tile {tile}: J err {err:.2e}, rho err {rho_err(cur, st.d_cur):.2e}")
+    if precision == "fp64":
+        assert rho_err(cur, st.d_cur) < 1e-10
+        assert rho_err(prev, st.d_prev) < 1e-10
+        assert err < 1e-10
+        assert np.abs(h["q"] - ref["q"]).max() < 1e-10
+    else:
+        assert err < J_TOL
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])

@@ -162,7 +162,7 @@ def test_kernel_choices_are_validated_options():
     _expect_inval(s, pkg.make_options(0.2, spmm_group=5), match="spmm_group")
     _expect_inval(s, pkg.make_options(0.2, spmm_variant=1, spmm_group=16), match="matrix-core")
     bad = pkg.make_options(0.2)
-    bad.flags = 4
+    bad.flags = 8
     _expect_inval(s, bad, match="flags")
     for kw in ({"spmm_variant": -4, "spmm_group": 16}, {"spmm_variant": 2, "spmm_group": 4},
                {"graphs": False, "small_path": False}):
