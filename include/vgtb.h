@@ -446,6 +446,25 @@ vgtb_status vgtb_spectrum(vgtb_ctx *ctx, int64_t n_t, const double *j_host, doub
                           int subtract_mean, void *sigma_host, void *eps_host);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): vgtb_spectrum without a
+ * context and without any allocation.  The same arithmetic and arguments as
+ * vgtb_spectrum; work is queued on hip_stream (a hipStream_t; NULL = the null
+ * stream) of the current device, and the call returns when sigma_host and
+ * eps_host (either may be NULL) hold the n_w results.
+ * Scratch: a fixed 1 MiB array in the library's device image, one per GPU,
+ * kept until the process ends; the trace and the grid stream through it, so
+ * the limits are those of vgtb_spectrum: 2 <= n_t <= 2^30, 1 <= n_w <= 2^24
+ * (VGTB_E_INVAL beyond them, message in vgtb_last_error(NULL)).  Calls on one
+ * GPU share the array: calls that overlap in time on one GPU (from several
+ * threads) race and must be serialised by the caller.
+ */
+vgtb_status vgtb_spectrum_noalloc(int64_t n_t, const double *j_host, double dt, int64_t n_w,
+                                  const double *omega_host, double e0, double tau0,
+                                  int subtract_mean, void *sigma_host, void *eps_host,
+                                  void *hip_stream);
+
+/*
  * Stand-alone kernel entry: C = A * B for `batch` row-major N x N complex128
  * matrices (strides N*N), on the FP64 matrix cores - the dense product
  * S_k^-1 (H_k D_k) of Eq. 6.  Device pointers, queued on hip_stream.

@@ -21,6 +21,7 @@ from .vgtb import (  # noqa: F401
     load_library,
     make_options,
     make_system_struct,
+    spectrum_noalloc,
     vgtb_workspace_size,
     vgtb_zgemm,
 )

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "vgtb_internal.h"
@@ -148,4 +149,71 @@ hipError_t spectrum_chunked(double *scratch, size_t cap, hipStream_t s, int64_t 
   return hipStreamSynchronize(s);
 }
 
+// ---------------------------------------------------------------------------
+// The same spectrum without any allocation, for callers that cannot allocate
+// device memory (code under stream capture, tight serving loops): its scratch
+// is a fixed array in the library's device image, one copy per GPU, held until
+// the process ends.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kStaticSpectrumDoubles = size_t(1) << 17;   // 1 MiB per GPU
+static __device__ __align__(256) double scratch[kStaticSpectrumDoubles];
+
+constexpr int kMaxDevices = 64;
+// Device address of scratch per GPU, looked up once per device (the host-side
+// name of the array is not a device address).
+std::atomic<double *> g_scratch_ptr[kMaxDevices];
+
+double *scratch_on(int device) {
+  double *p = g_scratch_ptr[device].load(std::memory_order_acquire);
+  if (p) return p;
+  void *addr = nullptr;
+  if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) return nullptr;
+  p = static_cast<double *>(addr);
+  g_scratch_ptr[device].store(p, std::memory_order_release);
+  return p;
+}
+
+}  // namespace
 }  // namespace vgtb
+
+extern "C" vgtb_status vgtb_spectrum_noalloc(int64_t n_t, const double *j_host, double dt, int64_t n_w,
+                                             const double *omega_host, double e0, double tau0,
+                                             int subtract_mean, void *sigma_host, void *eps_host,
+                                             void *hip_stream) {
+  if (n_t < 2 || n_w < 1 || !j_host || !omega_host || !(std::fabs(e0) > 0.0) || !(tau0 > 0.0) ||
+      !std::isfinite(dt)) {
+    vgtb::set_last_error("vgtb_spectrum_noalloc: needs n_t >= 2, n_w >= 1, the trace and the grid, "
+                         "e0 != 0, tau0 > 0 and a finite dt");
+    return VGTB_E_INVAL;
+  }
+  if (n_t > (int64_t)1 << 30 || n_w > (int64_t)1 << 24) {
+    vgtb::set_last_error("vgtb_spectrum_noalloc: n_t above 2^30 or n_w above 2^24");
+    return VGTB_E_INVAL;
+  }
+  for (int64_t i = 0; i < n_w; ++i)
+    if (!(std::fabs(omega_host[i]) > 0.0)) {
+      vgtb::set_last_error("vgtb_spectrum_noalloc: frequencies must be nonzero");
+      return VGTB_E_INVAL;
+    }
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= vgtb::kMaxDevices) {
+    vgtb::set_last_error("vgtb_spectrum_noalloc: no usable current device");
+    return VGTB_E_DEVICE;
+  }
+  double *sp = vgtb::scratch_on(device);
+  if (!sp) {
+    vgtb::set_last_error("vgtb_spectrum_noalloc: hipGetSymbolAddress of the static scratch failed");
+    return VGTB_E_DEVICE;
+  }
+  const hipError_t e = vgtb::spectrum_chunked(sp, vgtb::kStaticSpectrumDoubles,
+                                              static_cast<hipStream_t>(hip_stream), n_t, j_host, dt, n_w,
+                                              omega_host, e0, tau0, subtract_mean != 0, sigma_host,
+                                              eps_host);
+  if (e != hipSuccess) {
+    vgtb::set_last_error(hipGetErrorString(e));
+    return VGTB_E_DEVICE;
+  }
+  return VGTB_OK;
+}

@@ -20,14 +20,21 @@ using vgtb::PairGraph;
 
 namespace {
 
-thread_local std::string g_global_err;
+// Message of the last error raised before a context existed (per thread; a
+// fixed buffer, so that setting it never allocates).
+thread_local char g_global_err[512];
+void set_global_err(const char *m) {
+  size_t i = 0;
+  for (; m && m[i] && i + 1 < sizeof(g_global_err); ++i) g_global_err[i] = m[i];
+  g_global_err[i] = '\0';
+}
 
 vgtb_status fail(vgtb_ctx *ctx, vgtb_status st, const std::string &msg) {
   if (ctx) {
     ctx->err = msg;
     if (st == VGTB_E_DEVICE || st == VGTB_E_NONFINITE) ctx->poisoned = true;
   } else {
-    g_global_err = msg;
+    set_global_err(msg.c_str());
   }
   return st;
 }
@@ -695,6 +702,10 @@ vgtb_status check_ready(vgtb_ctx *ctx) {
 
 }  // namespace
 
+namespace vgtb {
+void set_last_error(const char *m) { set_global_err(m); }
+}  // namespace vgtb
+
 extern "C" {
 
 vgtb_status vgtb_workspace_size(const vgtb_system *s, const vgtb_options *o, size_t *bytes) {
@@ -757,7 +768,7 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   if (s->z_ref) c->z_host.assign(s->z_ref, s->z_ref + z.na);
 
   auto bail = [&](vgtb_status code, const std::string &m) {
-    g_global_err = m;
+    set_global_err(m.c_str());
     if (c->blas) rocblas_destroy_handle(c->blas);
     delete c;
     return code;
@@ -1420,7 +1431,7 @@ vgtb_status vgtb_spectrum(vgtb_ctx *c, int64_t n_t, const double *j, double dt, 
 
 int64_t vgtb_step_index(const vgtb_ctx *c) { return c ? c->step : -1; }
 
-const char *vgtb_last_error(const vgtb_ctx *c) { return c ? c->err.c_str() : g_global_err.c_str(); }
+const char *vgtb_last_error(const vgtb_ctx *c) { return c ? c->err.c_str() : g_global_err; }
 
 void vgtb_destroy(vgtb_ctx *c) {
   if (!c) return;

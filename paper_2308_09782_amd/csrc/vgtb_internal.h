@@ -151,6 +151,9 @@ void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk,
 // in chunks; sigma_host / eps_host (host, n_w complex128 each, either may be
 // null) receive the results.  Synchronises s.
 size_t spectrum_min_scratch();
+// The message vgtb_last_error(NULL) returns on this thread (copied into a
+// fixed buffer: no allocation).
+void set_last_error(const char *m);
 hipError_t spectrum_chunked(double *scratch, size_t cap, hipStream_t s, int64_t n_t,
                             const double *j_host, double dt, int64_t n_w, const double *omega_host,
                             double e0, double tau0, bool subtract_mean, void *sigma_host,

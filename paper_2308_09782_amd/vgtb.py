@@ -32,6 +32,7 @@ EXPORTED = [
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
     "vgtb_spectrum", "vgtb_autotune", "vgtb_server_create", "vgtb_server_run",
     "vgtb_server_destroy", "vgtb_set_coefficients", "vgtb_num_states", "vgtb_get_coefficients",
+    "vgtb_spectrum_noalloc",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
            "assemble": 6, "small": 7, "cn_pattern": 8, "cn_solve": 9, "cn_update": 10}
@@ -125,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_profile_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "vgtb_spectrum": [vp, i64, vp, ctypes.c_double, i64, vp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, vp, vp],
+        "vgtb_spectrum_noalloc": [i64, vp, ctypes.c_double, i64, vp, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, vp, vp, vp],
         "vgtb_autotune": [vp, i32, ctypes.POINTER(VgtbTuning)],
         "vgtb_set_coefficients": [vp, vp, vp, i32, ctypes.c_int],
         "vgtb_get_coefficients": [vp, vp, vp, ctypes.c_int],
@@ -244,6 +247,23 @@ def vgtb_zgemm(a, b, c, stream=None):
     st = torch.cuda.current_stream(a.device).cuda_stream if stream is None else stream
     _check(lib.vgtb_zgemm(a.data_ptr(), b.data_ptr(), c.data_ptr(), int(a.shape[1]),
                           int(a.shape[0]), st))
+
+
+def spectrum_noalloc(j, dt: float, omegas, e0: float, tau0: float = 200.0,
+                     subtract_mean: bool = True, stream=None):
+    """(sigma, epsilon) of Eqs. 15-16 through vgtb_spectrum_noalloc (no context,
+    no allocation: the library's fixed device scratch) on the current device."""
+    torch = _torch()
+    lib = load_library()
+    j = np.ascontiguousarray(j, dtype=np.float64).reshape(-1)
+    w = np.ascontiguousarray(omegas, dtype=np.float64).reshape(-1)
+    sig = np.zeros(w.size, dtype=np.complex128)
+    eps = np.zeros(w.size, dtype=np.complex128)
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    _check(lib.vgtb_spectrum_noalloc(j.size, j.ctypes.data, float(dt), w.size, w.ctypes.data,
+                                     float(e0), float(tau0), 1 if subtract_mean else 0,
+                                     sig.ctypes.data, eps.ctypes.data, st))
+    return sig, eps
 
 
 class Propagator:
