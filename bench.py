@@ -170,7 +170,7 @@ def counter_traffic(precision, workload):
 
 
 def run_form(vg, torch, sysm, atab, dt, precision, warmup, steps, offset, workload, tune=True,
-             coupling="peierls", propagator="leapfrog", j_steps=0, fused_update=True):
+             coupling="peierls", propagator="leapfrog", j_steps=0, fused_update=False):
     """Ground state, warmup, then `steps` timed steps of one precision form, then
     single-step calls for the latency, then more steps (untimed) until j_steps
     steps have been taken; J of every step is returned."""
