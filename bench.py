@@ -74,6 +74,13 @@ def parse():
     ap.add_argument("--serve-precision", default="fp16x3", choices=["fp64", "fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-arena-gib", type=float, default=64.0)
+    ap.add_argument("--group", type=int, default=0, metavar="M",
+                    help="instead of timing one workload: M seeded 8-atom a-Si cells (2x2x1 mesh) "
+                         "stepped as one group (one launch per block of steps for all of them), "
+                         "against the same cells stepped one after the other and on M streams")
+    ap.add_argument("--group-steps", type=int, default=640)
+    ap.add_argument("--group-precision", default="fp16x3", choices=["fp64", "fp32", "bf16x3", "fp16x3"])
+    ap.add_argument("--group-scc", action="store_true", help="the cells with the SCC shift (Eq. 10)")
     ap.add_argument("--accuracy", action="store_true",
                     help="instead of timing: run the workload's full step count in the reduced "
                          "forms and in FP64 and report the current and spectrum errors")
@@ -395,6 +402,77 @@ def serve_run(vg, args):
     }
 
 
+def group_run(vg, torch, args):
+    """M small systems (8-atom a-Si cells of different seeds, 4 k-points each) under
+    sin^2 pulses of different frequencies: k*steps/s when stepped as one group,
+    one after the other on one stream, and each on its own stream."""
+    import vgtb_synth as vs
+    m, steps, warm = args.group, args.group_steps, 64
+    gu = 0.25 if args.group_scc else None
+    cells = [vs.amorphous_si(1, (2, 2, 1), seed=3000 + i, gamma_u=gu) for i in range(m)]
+    fields = [vs.sin2_pulse_table(warm + steps, 0.2, 0.05 + 0.25 * i / max(m - 1, 1), 100.0, 0.05)
+              for i in range(m)]
+    kst = sum(c.n_k for c in cells) * steps
+
+    def open_all(streams=None):
+        props = []
+        for i, c in enumerate(cells):
+            ctx = torch.cuda.stream(streams[i]) if streams else torch.cuda.stream(torch.cuda.current_stream())
+            with ctx:
+                p = vg.Propagator(c, 0.2, args.group_precision, history_capacity=warm + steps)
+                p.ground_state()
+                p.set_field_table(fields[i])
+            props.append(p)
+        torch.cuda.synchronize()
+        return props
+
+    out = {}
+    props = open_all()
+    with vg.Group(props) as g:
+        g.step(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        out["grouped"] = time.perf_counter() - t0
+    j_group = [p.read_observables(warm, steps)["J"] for p in props]
+    for p in props:
+        p.close()
+    props = open_all()
+    for p in props:
+        p.step(warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in props:
+        p.step(steps)
+    torch.cuda.synchronize()
+    out["one_stream"] = time.perf_counter() - t0
+    same = all(np.array_equal(p.read_observables(warm, steps)["J"], j) for p, j in zip(props, j_group))
+    for p in props:
+        p.close()
+    streams = [torch.cuda.Stream() for _ in range(m)]
+    props = open_all(streams)
+    for p in props:
+        p.step(warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in props:
+        p.step(steps)
+    torch.cuda.synchronize()
+    out["m_streams"] = time.perf_counter() - t0
+    for p in props:
+        p.close()
+    return {
+        "metric": "group of small systems: k*steps/s", "unit": "k*steps/s", "systems": m,
+        "k_points_each": 4, "atoms_each": 8, "steps": steps, "scc": bool(args.group_scc),
+        "dtype": args.group_precision,
+        "value": kst / out["grouped"],
+        "one_stream": kst / out["one_stream"], "m_streams": kst / out["m_streams"],
+        "grouped_equals_alone": bool(same),
+        "data": "synthetic (seeded 8-atom a-Si cells, sin^2 pulses of different frequencies)",
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -409,6 +487,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.group:
+        print(json.dumps(group_run(vg, torch, args)), flush=True)
+        return 0
     if args.serve:
         rec = serve_run(vg, args)
         print(json.dumps(rec), flush=True)

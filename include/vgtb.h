@@ -134,8 +134,17 @@ typedef enum { VGTB_PROP_LEAPFROG = 0, VGTB_PROP_CRANK_NICOLSON = 1 } vgtb_propa
 enum {
   VGTB_OPT_NO_GRAPHS = 1,      /* launch every step directly (no captured two-step
                                   graphs); same results bit for bit               */
-  VGTB_OPT_NO_SMALL_PATH = 2,  /* no whole-steps-per-launch path for small FP64
-                                  non-SCC systems; same results to rounding       */
+  VGTB_OPT_NO_SMALL_PATH = 2,  /* no whole-steps-per-launch path for small
+                                  systems (N <= 40, Peierls, leapfrog); same
+                                  results to rounding.  With the SCC term that
+                                  path is one cooperative launch whose workgroups
+                                  (one per k-point, at most 256) meet at a
+                                  grid-wide barrier every step: it needs them all
+                                  resident at once, which kernels of other
+                                  streams can prevent; its wait is bounded
+                                  (VGTB_E_DEVICE after about a second), so set
+                                  this flag for SCC contexts that share the GPU
+                                  with concurrent work                           */
   VGTB_OPT_FUSE_UPDATE = 4     /* 3xBF16 / FP16X3 on 128x128 tiles: the dense
                                   product and the leapfrog update as one kernel over
                                   mirrored tile pairs instead of two launches; same
@@ -302,6 +311,41 @@ const char *vgtb_last_error(const vgtb_ctx *ctx);
 void vgtb_destroy(vgtb_ctx *ctx);
 
 /*
+ * Several small systems in one launch.  The paper distributes k-points over
+ * processes (Section 3); a small system (N <= 40) has too few k-points to
+ * fill a GPU, so a group steps many contexts together: each block of up to
+ * 64 steps is one launch with one workgroup per (system, k-point), followed
+ * by one launch that writes every system's history rows.  Each system
+ * follows exactly the steps vgtb_step takes for it (Eqs. 6 and 13, the SCC
+ * shift of Eq. 10 from its own charges, its own field table, dt and
+ * rescale cadence), with the same arithmetic, so its state and history are
+ * the same as when it is stepped alone.
+ *
+ * vgtb_group_create: ctxs[0..n_ctx) (1 to 4096 distinct contexts, not
+ * copied; the caller keeps them alive until vgtb_group_destroy) must all be
+ * on the small-system path (VGTB_K_SMALL), on one device, with the same
+ * orbitals per atom, precision form and SCC setting (VGTB_E_INVAL
+ * otherwise).  With the SCC term the group's launches are cooperative and the
+ * systems' k-points together must fit on the GPU at once (one workgroup per
+ * compute unit: 256 on MI355X), VGTB_E_INVAL beyond.  The group allocates a
+ * small pinned host buffer and its device copy (four blocks of per-system
+ * arguments and field values).
+ *
+ * vgtb_group_step: queues n_steps steps of every system on the first
+ * context's stream, after the work already queued on every context's stream
+ * and before any work queued on them later (events join the streams).
+ * VGTB_E_STATE if a context has no density or is poisoned; a launch failure
+ * poisons every context of the group (VGTB_E_DEVICE).  Observables and
+ * densities are read per context as usual.  The group's launches are not
+ * recorded in the contexts' profiles.  Errors are reported through
+ * vgtb_last_error(NULL).
+ */
+typedef struct vgtb_group vgtb_group;
+vgtb_status vgtb_group_create(vgtb_ctx *const *ctxs, int32_t n_ctx, vgtb_group **out);
+vgtb_status vgtb_group_step(vgtb_group *grp, int64_t n_steps);
+void vgtb_group_destroy(vgtb_group *grp);
+
+/*
  * Serving: several propagations overlapped on one GPU.
  *
  * A server owns a caller-provided device arena (dev_arena, arena_bytes; the
@@ -377,9 +421,11 @@ typedef enum {
   VGTB_K_UPDATE = 4,    /* leapfrog D_{n+1} = D_{n-1} - 2 i dt (Y - Y^dag)     */
   VGTB_K_RESCALE = 5,   /* deviation forms: re-Hermitise + trace rescale       */
   VGTB_K_ASSEMBLE = 6,  /* Peierls assembly of the pair blocks of H_k(t)       */
-  VGTB_K_SMALL = 7,     /* small N, FP64, no SCC: up to 64 whole steps in one
-                           launch (the other classes then stay at zero except
-                           REDUCE, which is the per-block history reduction)  */
+  VGTB_K_SMALL = 7,     /* small N (<= 40), Peierls, leapfrog, any precision
+                           form, with or without SCC: up to 64 whole steps in
+                           one launch (the other classes then stay at zero
+                           except REDUCE, which is the per-block history
+                           reduction)                                          */
   VGTB_K_CN_PATTERN = 8, /* Crank-Nicolson: D = sum f C C^dag on the pair pattern */
   VGTB_K_CN_SOLVE = 9,  /* Crank-Nicolson: [S + i dt/2 H | S C] build and the
                            recursive block elimination (leaf-block inverses +

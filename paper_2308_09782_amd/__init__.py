@@ -6,6 +6,7 @@ and the ctypes binding (vgtb.py).
 """
 from .vgtb import (  # noqa: F401
     EXPORTED,
+    Group,
     LIB_PATH,
     Propagator,
     Server,

@@ -747,19 +747,251 @@ __device__ inline void lds_zgemm(const double2 *At, const double2 *B, double2 *C
   }
 }
 
+// (cos, sin) of (k + A/c).d for every periodic image, into ph.
+__device__ inline void small_phases(const PairGraph &g, double kx, double ky, double kz, double2 *ph) {
+  for (int m = threadIdx.x; m < g.n_images; m += blockDim.x) {
+    double sn, cs;
+    sincos(kx * g.img_d[3 * m] + ky * g.img_d[3 * m + 1] + kz * g.img_d[3 * m + 2], &sn, &cs);
+    ph[m] = make_double2(cs, sn);
+  }
+}
+
+// H_k from the phase table, dense and transposed (Hm[c n + r] = H[r][c]),
+// with the SCC term 1/2 (V_I + V_J) S_k of Eq. 10 when v is given.
 template <int NO>
-__global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *__restrict__ kpts,
-                                                     const double2 *__restrict__ spk,
-                                                     const double2 *__restrict__ sinv,
-                                                     double2 *dlev0, double2 *dlev1, int cur,
-                                                     int have_prev, int n, FieldChunk f,
-                                                     int nsteps, double dt,
-                                                     double *__restrict__ part) {
+__device__ inline void small_assemble(const PairGraph &g, const double2 *ph, double2 *Hm, int n,
+                                      const double *v = nullptr, const double2 *spk = nullptr,
+                                      int k = 0) {
+  constexpr int E2 = NO * NO;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) Hm[t] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int t = threadIdx.x; t < g.n_pairs * E2; t += blockDim.x) {
+    const int p = t / E2, ee = t % E2;
+    double2 h = make_double2(0.0, 0.0);
+    for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
+      const double hv = g.img_h0[(size_t)m * E2 + ee];
+      h.x += ph[m].x * hv;
+      h.y += ph[m].y * hv;
+    }
+    if (v != nullptr) {
+      const double vs = 0.5 * (v[g.pair_row[p]] + v[g.pair_col[p]]);
+      const double2 sv = spk[((size_t)k * g.n_pairs + p) * E2 + ee];
+      h.x += vs * sv.x;
+      h.y += vs * sv.y;
+    }
+    Hm[(g.pair_col[p] * NO + ee % NO) * n + g.pair_row[p] * NO + ee / NO] = h;
+  }
+}
+
+// Grid-wide barrier of a cooperative launch: every workgroup adds one arrival
+// to *bar and waits until target arrivals are in.  The wait is bounded (about
+// a second of sleeps); past it *err is set and false is returned, and the
+// caller ends its launch.  Global writes before the barrier are visible to
+// every workgroup after it (device-scope release and acquire).
+__device__ inline bool small_grid_barrier(unsigned *bar, unsigned target, int *err) {
+  __shared__ int ok;
+  __threadfence();   // every wavefront's own writes of this step reach device scope
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(bar, 1u);
+    int spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins > (1 << 22) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        atomicExch(err, 1);
+        ok = 0;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();   // and every wavefront reads the other workgroups' writes
+  return ok != 0;
+}
+
+// C0 = H0_k D0 (A = 0) of the deviation forms on the small path, with the same
+// assembly and LDS product as the step kernel, so that a stationary density
+// gives W = H D - C0 = 0 exactly.
+template <int NO>
+__global__ __launch_bounds__(256) void k_small_c0(PairGraph g, const double *__restrict__ kpts,
+                                                  const double2 *__restrict__ d0,
+                                                  double2 *__restrict__ c0, int n) {
+  __shared__ double2 lds[3 * kSmallN * kSmallN];
+  __shared__ double2 ph[kSmallImages];
+  const int k = blockIdx.x;
+  const int n2 = n * n;
+  double2 *Hm = lds, *Dm = lds + n2, *Cm = lds + 2 * n2;
+  const size_t base = (size_t)k * n2;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) Dm[t] = d0[base + t];
+  small_phases(g, kpts[3 * k] + 0.0, kpts[3 * k + 1] + 0.0, kpts[3 * k + 2] + 0.0, ph);
+  __syncthreads();
+  small_assemble<NO>(g, ph, Hm, n);
+  __syncthreads();
+  lds_zgemm(Hm, Dm, Cm, n);
+  __syncthreads();
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) c0[base + t] = Cm[t];
+}
+
+// One complex multiply-add of the reduced product (S^-1 - I) W in the
+// arithmetic of each deviation form, as the dense product kernels do it: FP32
+// on complex64 operands; 3xBF16 / FP16X3 on hi/lo splits (x = hi + lo) of both
+// operands, A_hi B_hi + A_hi B_lo + A_lo B_hi, with fp32 accumulation (products
+// of two 16-bit values are exact in fp32); FP16X3 splits x s with the per-k
+// powers of two sa, sw.
+template <int FORM>
+__device__ inline void small_mac(double2 a, double2 w, float sa, float sw, float &gr, float &gi) {
+  if (FORM == 1) {
+    const float ar = (float)a.x, ai = (float)a.y, wr = (float)w.x, wi = (float)w.y;
+    gr = fmaf(ar, wr, gr);
+    gr = fmaf(-ai, wi, gr);
+    gi = fmaf(ar, wi, gi);
+    gi = fmaf(ai, wr, gi);
+    return;
+  }
+  float arh, arl, aih, ail, wrh, wrl, wih, wil;
+  // W as the sparse product splits it; S^-1 - I as it is split once at creation
+  // (the scaled value in FP64, then hi = fp16(x s), lo = fp16(x s - hi)).
+  auto split = [&](double x, float sc, bool a_operand, float &hi, float &lo) {
+    uint16_t h, l;
+    if (FORM == 2) {
+      split_bf16(x, h, l);
+      hi = from_bf16(h);
+      lo = from_bf16(l);
+    } else if (a_operand) {
+      const double xs = x * (double)sc;
+      hi = (float)(_Float16)(float)xs;
+      lo = (float)(_Float16)(float)(xs - (double)hi);
+    } else {
+      split_f16(x, sc, h, l);
+      hi = (float)__builtin_bit_cast(_Float16, h);
+      lo = (float)__builtin_bit_cast(_Float16, l);
+    }
+  };
+  split(a.x, sa, true, arh, arl);
+  split(a.y, sa, true, aih, ail);
+  split(w.x, sw, false, wrh, wrl);
+  split(w.y, sw, false, wih, wil);
+  gr = fmaf(arh, wrh, gr);
+  gr = fmaf(arh, wrl, gr);
+  gr = fmaf(arl, wrh, gr);
+  gr = fmaf(-aih, wih, gr);
+  gr = fmaf(-aih, wil, gr);
+  gr = fmaf(-ail, wih, gr);
+  gi = fmaf(arh, wih, gi);
+  gi = fmaf(arh, wil, gi);
+  gi = fmaf(arl, wih, gi);
+  gi = fmaf(aih, wrh, gi);
+  gi = fmaf(aih, wrl, gi);
+  gi = fmaf(ail, wrh, gi);
+}
+
+// Block-wide sum (thread 0's value valid for every thread after the call).
+__device__ inline double block_sum_small(double v, double *red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Deviation form of the product on the small path: W <- H D - C0 (FP64, in
+// place), then Y = W + (S^-1 - I) W with the second term in the form's
+// arithmetic (per element: complex64 W plus the complex64 product, summed in
+// FP64, as the update of the per-step path reads them).  St = (S^-1)^T.
+template <int FORM>
+__device__ void small_deviation_product(const double2 *St, double2 *Wm, double2 *Y, int n,
+                                        const SmallDeviation &dev, int k, size_t base, double *red) {
+  const int n2 = n * n;
+  float m = 0.0f;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    double2 w = Wm[t];
+    const double2 c = dev.c0[base + t];
+    w.x -= c.x;
+    w.y -= c.y;
+    Wm[t] = w;
+    if (FORM == 3) m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+  }
+  float sw = 1.0f, sa = 1.0f;
+  if (FORM == 3) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)m;
+    __syncthreads();
+    float mm = 0.0f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mm = fmaxf(mm, (float)red[w]);
+    sw = f16_pow2_scale(mm);
+    sa = dev.scale_a[k];
+  }
+  __syncthreads();
+  const float us = FORM == 3 ? 1.0f / (sa * sw) : 1.0f;
+  for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+    const int i = t / n, j = t - i * n;
+    float gr = 0.0f, gi = 0.0f;
+    for (int kk = 0; kk < n; ++kk) {
+      double2 a = St[kk * n + i];             // S^-1[i][kk]
+      if (kk == i) a.x -= 1.0;
+      small_mac<FORM>(a, Wm[kk * n + j], sa, sw, gr, gi);
+    }
+    const double2 w = Wm[t];
+    const float2 g = make_float2(us * gr, us * gi);
+    double2 y = make_double2((double)g.x, (double)g.y);
+    y.x += (double)(float)w.x;
+    y.y += (double)(float)w.y;
+    Y[t] = y;
+  }
+  __syncthreads();
+}
+
+// Rescale of the deviation forms on the small path: both levels
+// D <- c 1/2 (D + D^dag) with c = target / Re Tr(D S_k) (S on the pair pattern).
+template <int NO>
+__device__ void small_rescale(const PairGraph &g, const double2 *__restrict__ spk, double2 *Da,
+                              double2 *Db, int n, int k, double target, double *red) {
+  constexpr int E2 = NO * NO;
+  double ta = 0.0, tb = 0.0;
+  for (int q = threadIdx.x; q < g.n_pairs * E2; q += blockDim.x) {
+    const int p = q / E2, e = q - p * E2;
+    const int idx = (g.pair_row[p] * NO + e / NO) * n + g.pair_col[p] * NO + e % NO;
+    const double2 sv = spk[((size_t)k * g.n_pairs + p) * E2 + e];
+    ta += Da[idx].x * sv.x + Da[idx].y * sv.y;
+    tb += Db[idx].x * sv.x + Db[idx].y * sv.y;
+  }
+  const double ca = target / block_sum_small(ta, red);
+  const double cb = target / block_sum_small(tb, red);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t - i * n;
+    if (i > j) continue;
+    for (int lev = 0; lev < 2; ++lev) {
+      double2 *d = lev ? Db : Da;
+      const double c = lev ? cb : ca;
+      const double2 a = d[i * n + j], m = d[j * n + i];
+      d[i * n + j] = make_double2(c * 0.5 * (a.x + m.x), c * 0.5 * (a.y - m.y));
+      if (i != j) d[j * n + i] = make_double2(c * 0.5 * (m.x + a.x), c * 0.5 * (m.y - a.y));
+    }
+  }
+  __syncthreads();
+}
+
+// The block of steps of k-point k (of nk) of one system, run by the calling
+// workgroup; fa holds A(t_n)/c of the block's steps, three per step.  Shared
+// by the one-system launch and the launch of several systems.
+template <int NO, int FORM, bool SCC>
+__device__ __forceinline__ void small_steps_body(const PairGraph &g, const double *__restrict__ kpts,
+                                                 const double2 *__restrict__ spk,
+                                                 const double2 *__restrict__ sinv, double2 *dlev0,
+                                                 double2 *dlev1, int cur, int have_prev, int n,
+                                                 const double *__restrict__ fa, int nsteps, double dt,
+                                                 double *part, const SmallDeviation &dev, int k,
+                                                 int nk) {
   constexpr int E2 = NO * NO;
   constexpr int P = 64 / E2;
   __shared__ double2 lds[5 * kSmallN * kSmallN];
   __shared__ double2 ph[kSmallImages];        // (cos, sin) of (k + A/c).d per image
-  const int k = blockIdx.x, nk = gridDim.x;
+  __shared__ double red[8];
+  __shared__ double qv[SCC ? kSmallN : 1], vv[SCC ? kSmallN : 1];   // charges, SCC shift
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
   const int n2 = n * n;
   // St = (S_k^-1)^T; Hm holds H_k(t)^T, then Y = S^-1 W (row-major).
@@ -777,14 +1009,9 @@ __global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *
   const int e = lane % E2, slot = lane / E2, mu = e / NO, nu = e % NO;
   bool hp = have_prev != 0;
   for (int s = 0; s < nsteps; ++s) {
-    const double kx = kpts[3 * k] + f.a[3 * s], ky = kpts[3 * k + 1] + f.a[3 * s + 1],
-                 kz = kpts[3 * k + 2] + f.a[3 * s + 2];
-    // Peierls phases of step n, once per image.
-    for (int m = tid; m < g.n_images; m += blockDim.x) {
-      double sn, cs;
-      sincos(kx * g.img_d[3 * m] + ky * g.img_d[3 * m + 1] + kz * g.img_d[3 * m + 2], &sn, &cs);
-      ph[m] = make_double2(cs, sn);
-    }
+    const double kx = kpts[3 * k] + fa[3 * s], ky = kpts[3 * k + 1] + fa[3 * s + 1],
+                 kz = kpts[3 * k + 2] + fa[3 * s + 2];
+    small_phases(g, kx, ky, kz, ph);   // Peierls phases of step n, once per image
     __syncthreads();
     // Observables of D_n: Mulliken row sums, band energy and current.
     for (int I = wave; I < g.n_atoms; I += nwaves) {
@@ -820,24 +1047,44 @@ __global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *
         o[4] = jz;
       }
     }
-    // H_k(t_n), dense and transposed.
-    for (int t = tid; t < n2; t += blockDim.x) Hm[t] = make_double2(0.0, 0.0);
-    __syncthreads();
-    for (int t = tid; t < g.n_pairs * E2; t += blockDim.x) {
-      const int p = t / E2, ee = t % E2;
-      double2 h = make_double2(0.0, 0.0);
-      for (int m = g.img_ptr[p]; m < g.img_ptr[p + 1]; ++m) {
-        const double hv = g.img_h0[(size_t)m * E2 + ee];
-        h.x += ph[m].x * hv;
-        h.y += ph[m].y * hv;
+    if (SCC) {
+      // Mulliken charges of D_n summed over every k-point (Eq. 10): wait for all
+      // workgroups' partials of this step, then dq = q - Z and V = gamma dq.
+      if (!small_grid_barrier(dev.bar, dev.bar_base + (unsigned)(s + 1) * (unsigned)nk, dev.err)) {
+        nsteps = s;   // ends the launch with the state of this step
+        break;
       }
-      Hm[(g.pair_col[p] * NO + ee % NO) * n + g.pair_row[p] * NO + ee / NO] = h;
+      const int na = g.n_atoms;
+      for (int I = tid; I < na; I += blockDim.x) {
+        double q = 0.0;
+        for (int kk = 0; kk < nk; ++kk) q += dev.kw[kk] * part[(((size_t)s * nk + kk) * na + I) * 5];
+        qv[I] = q - dev.z[I];
+      }
+      __syncthreads();
+      for (int I = tid; I < na; I += blockDim.x) {
+        double v = 0.0;
+        for (int K = 0; K < na; ++K) v += dev.gamma[(size_t)I * na + K] * qv[K];
+        vv[I] = v;
+      }
+      __syncthreads();
+      if (k == 0 && tid == 0) {
+        double e = 0.0;
+        for (int I = 0; I < na; ++I) e += 0.5 * qv[I] * vv[I];
+        dev.escc[s] = e;
+      }
+      small_assemble<NO>(g, ph, Hm, n, vv, spk, k);   // H_k(t_n) with the SCC term
+    } else {
+      small_assemble<NO>(g, ph, Hm, n);  // H_k(t_n), dense and transposed
     }
     __syncthreads();
     lds_zgemm(Hm, Dc, Wm, n);     // W = H D_n
     __syncthreads();
-    lds_zgemm(St, Wm, Hm, n);     // Y = S^-1 W (H no longer needed)
-    __syncthreads();
+    if (FORM == 0) {
+      lds_zgemm(St, Wm, Hm, n);   // Y = S^-1 W (H no longer needed)
+      __syncthreads();
+    } else {
+      small_deviation_product<FORM>(St, Wm, Hm, n, dev, k, base, red);
+    }
     const double fac = hp ? 2.0 * dt : dt;
     const double2 *Db = hp ? Dp : Dc;
     for (int t = tid; t < n2; t += blockDim.x) {
@@ -846,13 +1093,21 @@ __global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *
       const double xr = y.x - yt.x;           // X = Y - conj(Y^T)
       const double xi = y.y + yt.y;
       const double2 b = Db[t];
-      Dp[t] = make_double2(b.x + fac * xi, b.y - fac * xr);
+      double2 o = make_double2(b.x + fac * xi, b.y - fac * xr);
+      if (FORM != 0 && dev.m0 != nullptr) {
+        const double2 mv = dev.m0[base + t];
+        o.x += fac * mv.x;
+        o.y += fac * mv.y;
+      }
+      Dp[t] = o;
     }
     __syncthreads();
     double2 *tmp = Dc;
     Dc = Dp;
     Dp = tmp;
     hp = true;
+    if (FORM != 0 && dev.rescale_every > 0 && (dev.step0 + s + 1) % dev.rescale_every == 0)
+      small_rescale<NO>(g, spk, Dc, Dp, n, k, dev.trace0[k], red);
   }
   double2 *dc = ((cur ^ (nsteps & 1)) != 0) ? dlev1 : dlev0;
   double2 *dp = ((cur ^ (nsteps & 1)) != 0) ? dlev0 : dlev1;
@@ -862,17 +1117,39 @@ __global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *
   }
 }
 
+template <int NO, int FORM, bool SCC>
+__global__ __launch_bounds__(256) void k_small_steps(PairGraph g, const double *__restrict__ kpts,
+                                                     const double2 *__restrict__ spk,
+                                                     const double2 *__restrict__ sinv,
+                                                     double2 *dlev0, double2 *dlev1, int cur,
+                                                     int have_prev, int n, FieldChunk f,
+                                                     int nsteps, double dt,
+                                                     double *part, SmallDeviation dev) {
+  small_steps_body<NO, FORM, SCC>(g, kpts, spk, sinv, dlev0, dlev1, cur, have_prev, n, f.a, nsteps, dt,
+                                  part, dev, blockIdx.x, gridDim.x);
+}
+
+// Several systems in one launch: workgroup w runs k-point w - wg0 of system
+// wg_job[w].  With the SCC shift each system's workgroups meet at that
+// system's own grid-wide barrier (the launch is cooperative, so all are
+// resident).
+template <int NO, int FORM, bool SCC>
+__global__ __launch_bounds__(256) void k_small_group(const SmallJob *__restrict__ jobs,
+                                                     const int *__restrict__ wg_job, int nsteps) {
+  const SmallJob &J = jobs[wg_job[blockIdx.x]];
+  small_steps_body<NO, FORM, SCC>(J.g, J.kpts, J.spk, J.sinv, J.dlev0, J.dlev1, J.cur, J.have_prev, J.n,
+                                  J.field, nsteps, J.dt, J.part, J.dev, (int)blockIdx.x - J.wg0, J.nk);
+}
+
 // History rows of a block of steps from the per-(step, k, atom) partials of
-// k_small_steps (no SCC term): for each step the same sums, in the same order,
-// as k_reduce_atoms followed by k_reduce_final.
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_steps(const double *__restrict__ part,
-                                                                 int nk, int na,
-                                                                 const double *__restrict__ kw,
-                                                                 double jscale, double *hist,
-                                                                 int64_t step0, int cap,
-                                                                 int *flag) {
+// k_small_steps: for each step the same sums, in the same order, as
+// k_reduce_atoms followed by k_reduce_final; with the SCC term the energy of
+// each step adds the SCC energy the step kernel wrote to escc.
+__device__ __forceinline__ void reduce_step_row(const double *__restrict__ part, int nk, int na,
+                                                const double *__restrict__ kw, double jscale,
+                                                double *hist, int64_t step0, int cap, int *flag,
+                                                const double *__restrict__ escc, int s) {
   __shared__ double red[6][kReduceWaves];
-  const int s = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   double *row = hist + (size_t)((step0 + s) % cap) * (5 + na);
   const double *ps = part + (size_t)s * nk * na * 5;
@@ -908,10 +1185,27 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_steps(const double *_
     row[0] = o[1] * jscale;
     row[1] = o[2] * jscale;
     row[2] = o[3] * jscale;
-    row[3] = o[0] + o[4];
+    row[3] = o[0] + (escc != nullptr ? escc[s] : o[4]);
     row[4] = o[5];
     if (!isfinite(o[5]) || !isfinite(o[0])) *flag = 1;
   }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_steps(const double *__restrict__ part,
+                                                                 int nk, int na,
+                                                                 const double *__restrict__ kw,
+                                                                 double jscale, double *hist,
+                                                                 int64_t step0, int cap,
+                                                                 int *flag,
+                                                                 const double *__restrict__ escc) {
+  reduce_step_row(part, nk, na, kw, jscale, hist, step0, cap, flag, escc, blockIdx.x);
+}
+
+// History rows of several systems' blocks: step blockIdx.x of system blockIdx.y.
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_group(const SmallJob *__restrict__ jobs) {
+  const SmallJob &J = jobs[blockIdx.y];
+  reduce_step_row(J.part, J.nk, J.na, J.kw, J.jscale, J.hist, J.step0, J.cap, J.flag, J.dev.escc,
+                  blockIdx.x);
 }
 
 // Leapfrog (Eq. 13) in the form D_out = D_base - i fac (Y - Y^dag), Y = S^-1 H D,
@@ -1393,23 +1687,131 @@ void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk,
   hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, fac, n, nt);
 }
 
-void launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
-                        const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
-                        bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
-                        double *part, hipStream_t s) {
+template <int NO, int FORM, bool SCC>
+static hipError_t small_steps_launch(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                                     const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
+                                     bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
+                                     double *part, const SmallDeviation &dev, hipStream_t s) {
+  if (!SCC) {
+    hipLaunchKernelGGL((k_small_steps<NO, FORM, false>), dim3(nk), dim3(256), 0, s, g, kpts, spk, sinv,
+                       dlev0, dlev1, cur, have_prev ? 1 : 0, n, f, nsteps, dt, part, dev);
+    return hipGetLastError();
+  }
+  PairGraph ga = g;
+  const double *ka = kpts;
+  const double2 *sa = spk, *si = sinv;
+  double2 *d0 = dlev0, *d1 = dlev1;
+  int ca = cur, hpa = have_prev ? 1 : 0, na = n, ns = nsteps;
+  FieldChunk fa = f;
+  double dta = dt;
+  double *pa = part;
+  SmallDeviation da = dev;
+  void *args[] = {&ga, &ka, &sa, &si, &d0, &d1, &ca, &hpa, &na, &fa, &ns, &dta, &pa, &da};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_small_steps<NO, FORM, true>),
+                                    dim3(nk), dim3(256), args, 0, s);
+}
+
+template <int NO>
+static hipError_t small_steps_form(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                                   const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
+                                   bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
+                                   double *part, const SmallDeviation &dev, hipStream_t s) {
+#define VG_SMALL(FORM, SCC)                                                                        \
+  return small_steps_launch<NO, FORM, SCC>(g, kpts, nk, spk, sinv, dlev0, dlev1, cur, have_prev, n, f, \
+                                           nsteps, dt, part, dev, s)
+  const bool scc = dev.gamma != nullptr;
+  if (dev.form == 1) { if (scc) VG_SMALL(1, true); else VG_SMALL(1, false); }
+  if (dev.form == 2) { if (scc) VG_SMALL(2, true); else VG_SMALL(2, false); }
+  if (dev.form == 3) { if (scc) VG_SMALL(3, true); else VG_SMALL(3, false); }
+  if (scc) VG_SMALL(0, true);
+  VG_SMALL(0, false);
+#undef VG_SMALL
+}
+
+int small_scc_max_kpoints(int norb) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void *kfn = norb == 4 ? reinterpret_cast<const void *>(&k_small_steps<4, 0, true>)
+                              : reinterpret_cast<const void *>(&k_small_steps<1, 0, true>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 256, 0) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+template <int NO, int FORM, bool SCC>
+static hipError_t small_group_launch(const SmallJob *jobs, const int *wg_job, int n_wg, int nsteps,
+                                     hipStream_t s) {
+  if (!SCC) {
+    hipLaunchKernelGGL((k_small_group<NO, FORM, false>), dim3(n_wg), dim3(256), 0, s, jobs, wg_job, nsteps);
+    return hipGetLastError();
+  }
+  const SmallJob *ja = jobs;
+  const int *wa = wg_job;
+  int ns = nsteps;
+  void *args[] = {&ja, &wa, &ns};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_small_group<NO, FORM, true>),
+                                    dim3(n_wg), dim3(256), args, 0, s);
+}
+
+template <int NO>
+static hipError_t small_group_form(const SmallJob *jobs, const int *wg_job, int n_wg, int form, bool scc,
+                                   int nsteps, hipStream_t s) {
+#define VG_GROUP(FORM, SCC) return small_group_launch<NO, FORM, SCC>(jobs, wg_job, n_wg, nsteps, s)
+  if (form == 1) { if (scc) VG_GROUP(1, true); else VG_GROUP(1, false); }
+  if (form == 2) { if (scc) VG_GROUP(2, true); else VG_GROUP(2, false); }
+  if (form == 3) { if (scc) VG_GROUP(3, true); else VG_GROUP(3, false); }
+  if (scc) VG_GROUP(0, true);
+  VG_GROUP(0, false);
+#undef VG_GROUP
+}
+
+hipError_t launch_small_group(const SmallJob *jobs, const int *wg_job, int n_jobs, int n_wg, int norb,
+                              int form, bool scc, int nsteps, hipStream_t s) {
+  const hipError_t e = norb == 4 ? small_group_form<4>(jobs, wg_job, n_wg, form, scc, nsteps, s)
+                                 : small_group_form<1>(jobs, wg_job, n_wg, form, scc, nsteps, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_group, dim3(nsteps, n_jobs), dim3(kReduceThreads), 0, s, jobs);
+  return hipGetLastError();
+}
+
+int small_group_max_workgroups(int norb, int form) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void *kfn = nullptr;
+#define VG_FN(NO, FORM) kfn = reinterpret_cast<const void *>(&k_small_group<NO, FORM, true>)
+  if (norb == 4) {
+    if (form == 1) VG_FN(4, 1); else if (form == 2) VG_FN(4, 2); else if (form == 3) VG_FN(4, 3); else VG_FN(4, 0);
+  } else {
+    if (form == 1) VG_FN(1, 1); else if (form == 2) VG_FN(1, 2); else if (form == 3) VG_FN(1, 3); else VG_FN(1, 0);
+  }
+#undef VG_FN
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 256, 0) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+void launch_small_c0(const PairGraph &g, const double *kpts, int nk, const double2 *d0, double2 *c0,
+                     int n, hipStream_t s) {
+  if (g.norb == 4) hipLaunchKernelGGL(k_small_c0<4>, dim3(nk), dim3(256), 0, s, g, kpts, d0, c0, n);
+  else hipLaunchKernelGGL(k_small_c0<1>, dim3(nk), dim3(256), 0, s, g, kpts, d0, c0, n);
+}
+
+hipError_t launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                              const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
+                              bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
+                              double *part, const SmallDeviation &dev, hipStream_t s) {
   if (g.norb == 4)
-    hipLaunchKernelGGL(k_small_steps<4>, dim3(nk), dim3(256), 0, s, g, kpts, spk, sinv, dlev0, dlev1,
-                       cur, have_prev ? 1 : 0, n, f, nsteps, dt, part);
-  else
-    hipLaunchKernelGGL(k_small_steps<1>, dim3(nk), dim3(256), 0, s, g, kpts, spk, sinv, dlev0, dlev1,
-                       cur, have_prev ? 1 : 0, n, f, nsteps, dt, part);
+    return small_steps_form<4>(g, kpts, nk, spk, sinv, dlev0, dlev1, cur, have_prev, n, f, nsteps, dt,
+                               part, dev, s);
+  return small_steps_form<1>(g, kpts, nk, spk, sinv, dlev0, dlev1, cur, have_prev, n, f, nsteps, dt,
+                             part, dev, s);
 }
 
 void launch_reduce_steps(const double *part, int nk, int na, const double *kw, double jscale,
                          double *hist, int64_t step0, int cap, int nsteps, int *flag,
-                         hipStream_t s) {
+                         const double *escc, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_steps, dim3(nsteps), dim3(kReduceThreads), 0, s, part, nk, na, kw,
-                     jscale, hist, step0, cap, flag);
+                     jscale, hist, step0, cap, flag, escc);
 }
 
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s) {

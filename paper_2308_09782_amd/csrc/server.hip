@@ -8,9 +8,12 @@
 //
 // Contexts of a server launch every step directly (VGTB_OPT_NO_GRAPHS): no
 // stream capture runs while the worker thread initialises another request,
-// and the requests' streams carry no cross-stream dependency.  Every context
-// is independent and its kernels are deterministic, so a result does not
-// depend on what else is running.
+// and the requests' streams carry no cross-stream dependency.  SCC requests
+// also stay off the small-system path: its workgroups meet at a grid-wide
+// barrier, which needs every workgroup of the launch resident at once, and
+// kernels of other requests on other streams may hold the compute units it
+// waits for.  Every context is independent and its kernels are
+// deterministic, so a result does not depend on what else is running.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -29,6 +32,15 @@ struct vgtb_server {
 
 namespace {
 
+// The options every context of a server is created with (the same for its
+// workspace size and its creation).
+vgtb_options server_options(const vgtb_request &rq, const vgtb_options &opt) {
+  vgtb_options o = opt;
+  o.flags |= VGTB_OPT_NO_GRAPHS;
+  if (rq.system && rq.system->gamma) o.flags |= VGTB_OPT_NO_SMALL_PATH;
+  return o;
+}
+
 std::string ctx_error(vgtb_ctx *c, const char *what) {
   const char *m = vgtb_last_error(c);
   return std::string(what) + ": " + (m ? m : "");
@@ -40,7 +52,8 @@ class HipEngine : public vgtb_srv::Engine {
 
   vgtb_status workspace(const vgtb_request &rq, const vgtb_options &opt, size_t *bytes,
                         std::string &msg) override {
-    const vgtb_status st = vgtb_workspace_size(rq.system, &opt, bytes);
+    const vgtb_options o = server_options(rq, opt);
+    const vgtb_status st = vgtb_workspace_size(rq.system, &o, bytes);
     if (st != VGTB_OK) msg = ctx_error(nullptr, "vgtb_workspace_size");
     return st;
   }
@@ -51,8 +64,7 @@ class HipEngine : public vgtb_srv::Engine {
       msg = "hipSetDevice failed on the initialisation thread";
       return VGTB_E_DEVICE;
     }
-    vgtb_options o = opt;
-    o.flags |= VGTB_OPT_NO_GRAPHS;
+    const vgtb_options o = server_options(rq, opt);
     vgtb_ctx *c = nullptr;
     vgtb_status st = vgtb_create(rq.system, &o, s_->arena + off, bytes, s_->streams[(size_t)slot], &c);
     if (st != VGTB_OK) {

@@ -54,13 +54,7 @@ __global__ __launch_bounds__(256) void k_absmax_part(const C2 *__restrict__ src,
   if (tid == 0) part[(size_t)k * kParts + blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-// 2^e with m 2^e in [2^13, 2^14); 1 for m zero or non-finite; e clamped to
-// [-100, 100] (a float power of two).
-__device__ inline float pow2_scale(float m) {
-  float sc = 1.0f;
-  if (m > 0.0f && isfinite(m)) sc = ldexpf(1.0f, max(-100, min(100, 13 - ilogbf(m))));
-  return sc;
-}
+__device__ inline float pow2_scale(float m) { return f16_pow2_scale(m); }
 
 __global__ void k_absmax_scale(const float *__restrict__ part, int nk, float *__restrict__ scale) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;

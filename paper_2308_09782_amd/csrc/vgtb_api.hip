@@ -380,6 +380,10 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
     c->tpart = c->tfac = c->trace0 = nullptr;
   }
   c->sm_part = z.small ? cv.template take<double>((size_t)vgtb::kSmallChunk * z.nk * z.na * 5) : nullptr;
+  const bool small_scc = z.small && z.scc;
+  c->sm_bar = small_scc ? cv.template take<unsigned>(4) : nullptr;
+  c->sm_err = small_scc ? cv.template take<int>(4) : nullptr;
+  c->sm_escc = small_scc ? cv.template take<double>(vgtb::kSmallChunk) : nullptr;
   c->ring = cv.template take<double>(3 * (size_t)vgtb::kStepRing);
   c->ctr = cv.template take<int64_t>(1);
   if (z.cn) {
@@ -414,6 +418,9 @@ struct SizeProbe {
   double *tpart, *tfac, *trace0;
   double2 *m0;
   double *sm_part, *ring;
+  unsigned *sm_bar;
+  int *sm_err;
+  double *sm_escc;
   int64_t *ctr;
   double2 *aug, *cinv, *sq;
   double *cocc, *vprev, *vmid, *ring_mid;
@@ -438,7 +445,8 @@ Sizes sizes_of(const vgtb_system *s, const vgtb_options *o, const HostGraph &hg)
   z.npad = (z.n + 63) / 64 * 64;
   z.mom = o->coupling == VGTB_COUPLING_MOMENTUM;
   z.cn = o->propagator == VGTB_PROP_CRANK_NICOLSON;
-  z.small = !(o->flags & VGTB_OPT_NO_SMALL_PATH) && !z.deviation && !z.scc && !z.mom && !z.cn && z.n <= vgtb::kSmallN &&
+  z.small = !(o->flags & VGTB_OPT_NO_SMALL_PATH) && !z.mom && !z.cn && z.n <= vgtb::kSmallN &&
+            (!z.scc || z.nk <= vgtb::kSmallSccMaxK) &&
             z.ni <= vgtb::kSmallImages;
   return z;
 }
@@ -485,12 +493,51 @@ void drop_graphs(vgtb_ctx *c);
 
 // Deviation forms: C0 = H0_k(A=0) D0 (constant part of the sparse product)
 // and, for a reference that is not stationary, m0 = -i (S^-1 C0 - C0^dag S^-1).
+int product_format(const vgtb_ctx *c);
+
+// Arguments of the next block of small-path steps of c beyond the state:
+// the deviation form's constants and, with the SCC shift, the charges' inputs
+// and the grid-wide barrier (whose count restarts from zero, on stream s,
+// before it could wrap).
+vgtb::SmallDeviation small_block_args(vgtb_ctx *c, hipStream_t s) {
+  vgtb::SmallDeviation sd;
+  if (c->precision != VGTB_FP64) {
+    sd.form = product_format(c);
+    sd.c0 = c->c0;
+    sd.m0 = c->m0_active ? c->m0 : nullptr;
+    sd.scale_a = c->scale_a;
+    sd.trace0 = c->trace0;
+    sd.rescale_every = c->rescale_every;
+    sd.step0 = c->step;
+  }
+  if (c->scc) {
+    if (c->bar_count > (1u << 30)) {
+      vgtb::launch_fill_zero(reinterpret_cast<double2 *>(c->sm_bar), 1, s);
+      c->bar_count = 0;
+    }
+    sd.gamma = c->gamma;
+    sd.z = c->z;
+    sd.kw = c->kw_dev;
+    sd.bar = c->sm_bar;
+    sd.bar_base = c->bar_count;
+    sd.err = c->sm_err;
+    sd.escc = c->sm_escc;
+  }
+  return sd;
+}
+
 void prepare_reference(vgtb_ctx *c, bool with_m0) {
   drop_graphs(c);   // captured updates name m0 (or not)
-  const vgtb::StepSource zero{nullptr, nullptr};
-  vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, zero, c->spk, nullptr, c->hq, c->h0k, c->ppk, c->stream);
-  vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
-                    c->spmm_variant, c->stream);
+  if (c->small_path) {
+    // The small path forms H D itself; C0 comes from the same arithmetic.
+    vgtb::launch_small_c0(c->g, c->kpts_dev, c->nk, c->d0, c->c0, c->n, c->stream);
+  } else {
+    const vgtb::StepSource zero{nullptr, nullptr};
+    vgtb::launch_assemble(c->g, c->kpts_dev, c->nk, zero, c->spk, nullptr, c->hq, c->h0k, c->ppk,
+                          c->stream);
+    vgtb::launch_spmm(c->g, c->d0, nullptr, c->n, c->nk, c->hq, nullptr, c->c0, 0, 0, nullptr,
+                      c->spmm_variant, c->stream);
+  }
   c->m0_active = with_m0;
   if (!with_m0) return;
   vgtb::launch_zgemm_f64(c->sinv, c->c0, c->y, c->n, c->nk, c->stream);
@@ -841,9 +888,14 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
   c->trace0 = dp.trace0;
   c->m0 = dp.m0;
   c->sm_part = dp.sm_part;
+  c->sm_bar = dp.sm_bar;
+  c->sm_err = dp.sm_err;
+  c->sm_escc = dp.sm_escc;
   c->ring = dp.ring;
   c->ctr = dp.ctr;
   c->small_path = z.small;
+  // The SCC small path needs every k-point's workgroup resident at once.
+  if (z.small && z.scc && vgtb::small_scc_max_kpoints(z.no) < z.nk) c->small_path = false;
   c->use_graphs = !(o->flags & VGTB_OPT_NO_GRAPHS) && !z.cn;
   c->fuse_update = (o->flags & VGTB_OPT_FUSE_UPDATE) != 0;
   c->cn = z.cn;
@@ -883,6 +935,10 @@ vgtb_status vgtb_create(const vgtb_system *s, const vgtb_options *o, void *arena
     CREATE_HIP(hipMemcpyAsync(dp.gamma, s->gamma, sizeof(double) * z.na * z.na, hipMemcpyHostToDevice, st_));
   CREATE_HIP(hipMemsetAsync(dp.v, 0, sizeof(double) * z.na, st_));
   CREATE_HIP(hipMemsetAsync(dp.flag, 0, sizeof(int), st_));
+  if (dp.sm_bar) {
+    CREATE_HIP(hipMemsetAsync(dp.sm_bar, 0, sizeof(unsigned), st_));
+    CREATE_HIP(hipMemsetAsync(dp.sm_err, 0, sizeof(int), st_));
+  }
   vgtb::launch_set_counter(dp.ctr, 0, st_);
 
   // S_k on the pair graph (Eq. 7), dense S_k, then S_k^-1 by Cholesky.
@@ -1129,6 +1185,7 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
   const double jscale = -1.0 / c->volume;   // the k weights enter the sum
   hipStream_t s = c->stream;
   if (c->small_path) {
+    hipError_t launch_err = hipSuccess;
     for (int64_t done = 0; done < n_steps;) {
       const int ns = (int)std::min<int64_t>(vgtb::kSmallChunk, n_steps - done);
       vgtb::FieldChunk fc;
@@ -1136,13 +1193,19 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
         const double *a = c->field.data() + 3 * std::min<int64_t>(c->step + i, nf - 1);
         for (int x = 0; x < 3; ++x) fc.a[3 * i + x] = a[x] / vgtb::kLightSpeed;
       }
+      vgtb::SmallDeviation sd;
       timed(c, VGTB_K_SMALL, [&] {
-        vgtb::launch_small_steps(c->g, c->kpts_dev, nk, c->spk, c->sinv, c->dlev[0], c->dlev[1],
-                                 c->cur, c->have_prev, n, fc, ns, c->dt, c->sm_part, s);
+        sd = small_block_args(c, s);
+        launch_err = vgtb::launch_small_steps(c->g, c->kpts_dev, nk, c->spk, c->sinv, c->dlev[0],
+                                              c->dlev[1], c->cur, c->have_prev, n, fc, ns, c->dt,
+                                              c->sm_part, sd, s);
+        if (c->scc) c->bar_count += (unsigned)ns * (unsigned)nk;
       });
+      if (launch_err != hipSuccess)
+        return fail(c, VGTB_E_DEVICE, std::string("small-system launch: ") + hipGetErrorString(launch_err));
       timed(c, VGTB_K_REDUCE, [&] {
         vgtb::launch_reduce_steps(c->sm_part, nk, c->na, c->kw_dev, jscale, c->hist, c->step,
-                                  c->hist_cap, ns, c->flag, s);
+                                  c->hist_cap, ns, c->flag, c->scc ? c->sm_escc : nullptr, s);
       });
       c->cur ^= (ns & 1);
       c->have_prev = true;
@@ -1212,9 +1275,13 @@ vgtb_status vgtb_step(vgtb_ctx *c, int64_t n_steps) {
 vgtb_status vgtb_synchronize(vgtb_ctx *c) {
   vgtb_status st = check_ready(c);
   if (st != VGTB_OK) return st;
-  int flag = 0;
+  int flag = 0, barrier_err = 0;
   HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if (c->sm_err)
+    HIP_TRY(c, hipMemcpyAsync(&barrier_err, c->sm_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (barrier_err)
+    return fail(c, VGTB_E_DEVICE, "the grid-wide barrier of the small-system SCC path timed out");
   if (flag) return fail(c, VGTB_E_NONFINITE, "non-finite trace or energy observed");
   return VGTB_OK;
 }
@@ -1549,6 +1616,208 @@ vgtb_status vgtb_zgemm(const void *a, const void *b, void *cc, int32_t n, int32_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, VGTB_E_DEVICE, hipGetErrorString(e));
   return VGTB_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Several small systems stepped in one launch per block of steps.
+// ---------------------------------------------------------------------------
+struct vgtb_group {
+  std::vector<vgtb_ctx *> ctx;
+  int device = 0, no = 0, form = 0, n_wg = 0;
+  bool scc = false;
+  hipStream_t stream = nullptr;            // the first context's stream
+  static constexpr int kSlots = 4;         // blocks in flight before the host waits
+  size_t jobs_off = 0, map_off = 0, field_off = 0, slot_bytes = 0;
+  char *host = nullptr;                    // pinned staging, kSlots * slot_bytes
+  char *dev = nullptr;                     // device copy of the slots
+  hipEvent_t slot_ev[kSlots] = {};
+  bool slot_used[kSlots] = {};
+  int next = 0;
+  hipEvent_t join = nullptr;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static vgtb_status group_fail(vgtb_group *g, vgtb_status st, const std::string &msg) {
+  if (g && (st == VGTB_E_DEVICE || st == VGTB_E_NONFINITE))
+    for (vgtb_ctx *c : g->ctx) fail(c, st, msg);
+  set_global_err(msg.c_str());
+  return st;
+}
+
+#define GROUP_HIP(g, expr)                                                                 \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return group_fail(g, VGTB_E_DEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+vgtb_status vgtb_group_create(vgtb_ctx *const *ctxs, int32_t n_ctx, vgtb_group **out) {
+  if (!ctxs || !out || n_ctx < 1 || n_ctx > 4096)
+    return fail(nullptr, VGTB_E_INVAL, "vgtb_group_create: needs 1 to 4096 contexts and an output handle");
+  *out = nullptr;
+  std::vector<vgtb_ctx *> v(ctxs, ctxs + n_ctx);
+  for (vgtb_ctx *c : v) {
+    if (!c) return fail(nullptr, VGTB_E_INVAL, "vgtb_group_create: null context");
+    if (c->poisoned) return fail(nullptr, VGTB_E_STATE, "vgtb_group_create: a context is poisoned");
+  }
+  std::vector<vgtb_ctx *> sorted = v;
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(nullptr, VGTB_E_INVAL, "vgtb_group_create: a context appears twice");
+  const vgtb_ctx *c0 = v[0];
+  int n_wg = 0;
+  for (const vgtb_ctx *c : v) {
+    if (!c->small_path)
+      return fail(nullptr, VGTB_E_INVAL,
+                  "vgtb_group_create: every context must be on the small-system path "
+                  "(N <= 40, Peierls, leapfrog, small path not switched off)");
+    if (c->device != c0->device || c->no != c0->no || c->precision != c0->precision || c->scc != c0->scc)
+      return fail(nullptr, VGTB_E_INVAL,
+                  "vgtb_group_create: contexts differ in device, orbitals per atom, precision form "
+                  "or the SCC term");
+    n_wg += c->nk;
+  }
+  if (hipSetDevice(c0->device) != hipSuccess)
+    return fail(nullptr, VGTB_E_DEVICE, "vgtb_group_create: hipSetDevice failed");
+  const int form = product_format(c0);
+  if (c0->scc) {
+    const int cap = vgtb::small_group_max_workgroups(c0->no, form);
+    if (n_wg > cap)
+      return fail(nullptr, VGTB_E_INVAL,
+                  "vgtb_group_create: with the SCC term the systems' k-points together (" +
+                      std::to_string(n_wg) + ") must fit the GPU at once (" + std::to_string(cap) + ")");
+  } else if (n_wg > 65535) {
+    return fail(nullptr, VGTB_E_INVAL, "vgtb_group_create: more than 65535 k-points in all");
+  }
+  auto *g = new vgtb_group;
+  g->ctx = v;
+  g->device = c0->device;
+  g->no = c0->no;
+  g->form = form;
+  g->scc = c0->scc;
+  g->n_wg = n_wg;
+  g->stream = c0->stream;
+  g->jobs_off = 0;
+  g->map_off = align256(sizeof(vgtb::SmallJob) * v.size());
+  g->field_off = g->map_off + align256(sizeof(int) * (size_t)n_wg);
+  g->slot_bytes = g->field_off + align256(sizeof(double) * 3 * vgtb::kSmallChunk * v.size());
+  const size_t total = g->slot_bytes * vgtb_group::kSlots;
+  hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&g->host), total, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&g->dev), total);
+  for (int i = 0; e == hipSuccess && i < vgtb_group::kSlots; ++i)
+    e = hipEventCreateWithFlags(&g->slot_ev[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    const std::string m = std::string("vgtb_group_create: ") + hipGetErrorString(e);
+    vgtb_group_destroy(g);
+    return fail(nullptr, e == hipErrorOutOfMemory ? VGTB_E_NOMEM : VGTB_E_DEVICE, m);
+  }
+  // Workgroup -> system map: the same in every slot.
+  for (int slot = 0; slot < vgtb_group::kSlots; ++slot) {
+    int *map = reinterpret_cast<int *>(g->host + slot * g->slot_bytes + g->map_off);
+    int w = 0;
+    for (size_t j = 0; j < v.size(); ++j)
+      for (int k = 0; k < v[j]->nk; ++k) map[w++] = (int)j;
+  }
+  *out = g;
+  return VGTB_OK;
+}
+
+vgtb_status vgtb_group_step(vgtb_group *g, int64_t n_steps) {
+  if (!g) return fail(nullptr, VGTB_E_INVAL, "null group");
+  if (n_steps < 0) return fail(nullptr, VGTB_E_INVAL, "vgtb_group_step: negative step count");
+  for (vgtb_ctx *c : g->ctx) {
+    if (c->poisoned) return fail(nullptr, VGTB_E_STATE, "vgtb_group_step: a context is poisoned");
+    if (!c->have_density) return fail(nullptr, VGTB_E_STATE, "vgtb_group_step: a context has no density");
+  }
+  if (n_steps == 0) return VGTB_OK;
+  GROUP_HIP(g, hipSetDevice(g->device));
+  hipStream_t s = g->stream;
+  // Each context's earlier work comes first.
+  for (vgtb_ctx *c : g->ctx) {
+    if (c->stream == s) continue;
+    GROUP_HIP(g, hipEventRecord(g->join, c->stream));
+    GROUP_HIP(g, hipStreamWaitEvent(s, g->join, 0));
+  }
+  const size_t nj = g->ctx.size();
+  for (int64_t done = 0; done < n_steps;) {
+    const int ns = (int)std::min<int64_t>(vgtb::kSmallChunk, n_steps - done);
+    const int slot = g->next;
+    g->next = (g->next + 1) % vgtb_group::kSlots;
+    if (g->slot_used[slot]) GROUP_HIP(g, hipEventSynchronize(g->slot_ev[slot]));
+    char *hs = g->host + slot * g->slot_bytes;
+    char *ds = g->dev + slot * g->slot_bytes;
+    auto *jobs = reinterpret_cast<vgtb::SmallJob *>(hs + g->jobs_off);
+    auto *fields = reinterpret_cast<double *>(hs + g->field_off);
+    int wg0 = 0;
+    for (size_t j = 0; j < nj; ++j) {
+      vgtb_ctx *c = g->ctx[j];
+      vgtb::SmallJob J;
+      J.g = c->g;
+      J.kpts = c->kpts_dev;
+      J.spk = c->spk;
+      J.sinv = c->sinv;
+      J.dlev0 = c->dlev[0];
+      J.dlev1 = c->dlev[1];
+      J.field = reinterpret_cast<const double *>(ds + g->field_off) + j * 3 * vgtb::kSmallChunk;
+      J.part = c->sm_part;
+      J.dev = small_block_args(c, s);
+      J.kw = c->kw_dev;
+      J.jscale = -1.0 / c->volume;
+      J.dt = c->dt;
+      J.hist = c->hist;
+      J.step0 = c->step;
+      J.flag = c->flag;
+      J.cap = c->hist_cap;
+      J.cur = c->cur;
+      J.have_prev = c->have_prev ? 1 : 0;
+      J.n = c->n;
+      J.nk = c->nk;
+      J.na = c->na;
+      J.wg0 = wg0;
+      wg0 += c->nk;
+      std::memcpy(&jobs[j], &J, sizeof(J));
+      const int64_t nf = (int64_t)(c->field.size() / 3);
+      double *fj = fields + j * 3 * vgtb::kSmallChunk;
+      for (int i = 0; i < ns; ++i) {
+        const double *a = c->field.data() + 3 * std::min<int64_t>(c->step + i, nf - 1);
+        for (int x = 0; x < 3; ++x) fj[3 * i + x] = a[x] / vgtb::kLightSpeed;
+      }
+    }
+    GROUP_HIP(g, hipMemcpyAsync(ds, hs, g->slot_bytes, hipMemcpyHostToDevice, s));
+    const hipError_t e = vgtb::launch_small_group(
+        reinterpret_cast<const vgtb::SmallJob *>(ds + g->jobs_off),
+        reinterpret_cast<const int *>(ds + g->map_off), (int)nj, g->n_wg, g->no, g->form, g->scc, ns, s);
+    if (e != hipSuccess)
+      return group_fail(g, VGTB_E_DEVICE, std::string("small-system group launch: ") + hipGetErrorString(e));
+    GROUP_HIP(g, hipEventRecord(g->slot_ev[slot], s));
+    g->slot_used[slot] = true;
+    for (vgtb_ctx *c : g->ctx) {
+      c->cur ^= (ns & 1);
+      c->have_prev = true;
+      c->step += ns;
+      if (c->scc) c->bar_count += (unsigned)ns * (unsigned)c->nk;
+    }
+    done += ns;
+  }
+  // Each context's later work waits for the group's.
+  GROUP_HIP(g, hipEventRecord(g->join, s));
+  for (vgtb_ctx *c : g->ctx)
+    if (c->stream != s) GROUP_HIP(g, hipStreamWaitEvent(c->stream, g->join, 0));
+  return VGTB_OK;
+}
+
+void vgtb_group_destroy(vgtb_group *g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (hipEvent_t &e : g->slot_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (g->join) (void)hipEventDestroy(g->join);
+  if (g->dev) (void)hipFree(g->dev);
+  if (g->host) (void)hipHostFree(g->host);
+  delete g;
 }
 
 }  // extern "C"

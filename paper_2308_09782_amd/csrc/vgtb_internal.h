@@ -23,6 +23,15 @@ constexpr double kLightSpeed = 137.035999084;
 // output tiles of one batch entry in blocks of gm row panels, column-major
 // within a block, so the workgroups resident on one XCD share A row panels
 // and B column panels in its L2.
+// The power-of-two scale of the fp16 split: 2^e with m 2^e in [2^13, 2^14)
+// for the largest |re|, |im| m; 1 for m zero or non-finite; e clamped to
+// [-100, 100] (a float power of two).
+__device__ inline float f16_pow2_scale(float m) {
+  float sc = 1.0f;
+  if (m > 0.0f && isfinite(m)) sc = ldexpf(1.0f, max(-100, min(100, 13 - ilogbf(m))));
+  return sc;
+}
+
 __device__ inline int xcd_slot(int lin, int total) {
   return (total & 7) == 0 ? (lin & 7) * (total >> 3) + (lin >> 3) : lin;
 }
@@ -79,10 +88,13 @@ struct StepSource {
   const int64_t *ctr;
 };
 
-// Small systems without the SCC shift: a block of up to kSmallChunk steps per
-// launch, one workgroup per k with everything in LDS (N <= kSmallN, at most
-// kSmallImages periodic images).
+// Small systems: a block of up to kSmallChunk steps per launch, one workgroup
+// per k with everything in LDS (N <= kSmallN, at most kSmallImages periodic
+// images), in every precision form.  With the SCC shift the k-sum of the
+// charges needs every k-point's partials each step: the launch is cooperative
+// (at most kSmallSccMaxK workgroups, all resident) with a grid-wide barrier.
 constexpr int kSmallN = 40;
+constexpr int kSmallSccMaxK = 256;   // k-points (workgroups) of an SCC small-path launch, at most
 constexpr int kSmallImages = 1536;
 constexpr int kSmallChunk = 64;
 struct FieldChunk {
@@ -158,15 +170,73 @@ hipError_t spectrum_chunked(double *scratch, size_t cap, hipStream_t s, int64_t 
                             const double *j_host, double dt, int64_t n_w, const double *omega_host,
                             double e0, double tau0, bool subtract_mean, void *sigma_host,
                             void *eps_host);
+// The deviation (reduced-precision) forms on the small-system path: form 1
+// FP32, 2 3xBF16, 3 FP16X3; 0 = the FP64 form (the rest unused).  c0 = H0 D0,
+// m0 (may be null) the constant term of a set density, scale_a the per-k
+// scale of S^-1 - I (FP16X3), trace0 the per-k target of the rescale every
+// rescale_every steps (0 = never) counted from the context's step index step0.
+//
+// The SCC shift (Eq. 10) on the small path: gamma (na x na) and Z switch it on.
+// Its Mulliken charges sum over all k-points, so every step waits at a
+// grid-wide barrier (bar: arrival counter; the launch is cooperative, so all
+// workgroups are resident) for the per-(k, atom) partials of that step; the
+// wait is bounded, and a barrier that times out sets *err and ends the launch
+// early.  escc[s] receives the SCC energy 1/2 dq^T gamma dq of block step s.
+struct SmallDeviation {
+  int form = 0;
+  const double2 *c0 = nullptr, *m0 = nullptr;
+  const float *scale_a = nullptr;
+  const double *trace0 = nullptr;
+  int rescale_every = 0;
+  int64_t step0 = 0;
+  const double *gamma = nullptr, *z = nullptr, *kw = nullptr;
+  unsigned *bar = nullptr;
+  unsigned bar_base = 0;
+  int *err = nullptr;
+  double *escc = nullptr;
+};
+// One system of a launch of several small systems: where its state, its block
+// of field values and its history live, and its first workgroup in the launch.
+struct SmallJob {
+  PairGraph g;
+  const double *kpts = nullptr;
+  const double2 *spk = nullptr, *sinv = nullptr;
+  double2 *dlev0 = nullptr, *dlev1 = nullptr;
+  const double *field = nullptr;   // A(t_n)/c of the block's steps, three per step (device)
+  double *part = nullptr;          // per-(step, k, atom) partials, as for one system
+  SmallDeviation dev;
+  const double *kw = nullptr;
+  double jscale = 0.0, dt = 0.0;
+  double *hist = nullptr;
+  int64_t step0 = 0;
+  int *flag = nullptr;
+  int cap = 1, cur = 0, have_prev = 0, n = 0, nk = 0, na = 0, wg0 = 0;
+};
+// Steps of several small systems in one launch (one workgroup per system and
+// k-point; wg_job maps workgroup to system), then their history rows.  All
+// systems share orbitals per atom norb, the precision form and whether the
+// SCC shift is on (then the launch is cooperative and n_wg is bounded by
+// small_group_max_workgroups).  jobs and wg_job are device memory.
+hipError_t launch_small_group(const SmallJob *jobs, const int *wg_job, int n_jobs, int n_wg, int norb,
+                              int form, bool scc, int nsteps, hipStream_t s);
+int small_group_max_workgroups(int norb, int form);
+// C0 = H0_k D0 of the small path (its own assembly and LDS product).
+void launch_small_c0(const PairGraph &g, const double *kpts, int nk, const double2 *d0, double2 *c0,
+                     int n, hipStream_t s);
 // Steps [step, step + nsteps) of a small system (see kSmallN); per-step
 // partials [nsteps][nk][na][5] into part, then launch_reduce_steps.
-void launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
-                        const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
-                        bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
-                        double *part, hipStream_t s);
+// With the SCC shift the launch is cooperative; it returns its error (a grid
+// too large to be resident at once is hipErrorCooperativeLaunchTooLarge).
+hipError_t launch_small_steps(const PairGraph &g, const double *kpts, int nk, const double2 *spk,
+                              const double2 *sinv, double2 *dlev0, double2 *dlev1, int cur,
+                              bool have_prev, int n, const FieldChunk &f, int nsteps, double dt,
+                              double *part, const SmallDeviation &dev, hipStream_t s);
+// Largest k-point count the SCC small path can run (workgroups resident at once).
+int small_scc_max_kpoints(int norb);
+// escc (may be null): per-step SCC energy of the block, added to E.
 void launch_reduce_steps(const double *part, int nk, int na, const double *kw, double jscale,
                          double *hist, int64_t step0, int cap, int nsteps, int *flag,
-                         hipStream_t s);
+                         const double *escc, hipStream_t s);
 void launch_hermitian_from_lower(double2 *m, int n, int nk, hipStream_t s);
 void launch_density_from_vectors(const double2 *evec, const double *occ, double2 *d, int n,
                                  int nk, hipStream_t s);
@@ -307,6 +377,10 @@ struct vgtb_ctx {
   double *tfac = nullptr;      // 2 * nk
   double *trace0 = nullptr;    // nk
   double *sm_part = nullptr;   // kSmallChunk * nk * na * 5 per-step partials (small path)
+  unsigned *sm_bar = nullptr;  // small path with SCC: grid-barrier arrival counter
+  int *sm_err = nullptr;       //   and its time-out flag
+  double *sm_escc = nullptr;   //   kSmallChunk per-step SCC energies
+  unsigned bar_count = 0;      //   arrivals so far (the next launch's base)
   double *ring = nullptr;      // kStepRing * 3, A(t)/c of the steps in flight
   int64_t *ctr = nullptr;      // device step counter
   double2 *m0 = nullptr;       // nk * n * n, -i (S^-1 H0 D0 - D0 H0 S^-1) for a set density

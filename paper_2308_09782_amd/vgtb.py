@@ -32,7 +32,7 @@ EXPORTED = [
     "vgtb_last_error", "vgtb_destroy", "vgtb_zgemm", "vgtb_profile_enable", "vgtb_profile_read",
     "vgtb_spectrum", "vgtb_autotune", "vgtb_server_create", "vgtb_server_run",
     "vgtb_server_destroy", "vgtb_set_coefficients", "vgtb_num_states", "vgtb_get_coefficients",
-    "vgtb_spectrum_noalloc",
+    "vgtb_spectrum_noalloc", "vgtb_group_create", "vgtb_group_step", "vgtb_group_destroy",
 ]
 KERNELS = {"observe": 0, "reduce": 1, "spmm": 2, "gemm": 3, "update": 4, "rescale": 5,
            "assemble": 6, "small": 7, "cn_pattern": 8, "cn_solve": 9, "cn_update": 10}
@@ -132,6 +132,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgtb_set_coefficients": [vp, vp, vp, i32, ctypes.c_int],
         "vgtb_get_coefficients": [vp, vp, vp, ctypes.c_int],
         "vgtb_server_create": [vp, sz, i32, ctypes.POINTER(vp)],
+        "vgtb_group_create": [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)],
+        "vgtb_group_step": [vp, i64],
         "vgtb_server_run": [vp, i32, ctypes.POINTER(VgtbRequest), ctypes.POINTER(VgtbRequestStats),
                             ctypes.POINTER(VgtbServerStats)],
     }
@@ -149,6 +151,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.vgtb_destroy.restype = None
     lib.vgtb_server_destroy.argtypes = [vp]
     lib.vgtb_server_destroy.restype = None
+    lib.vgtb_group_destroy.argtypes = [vp]
+    lib.vgtb_group_destroy.restype = None
     _lib = lib
     return lib
 
@@ -452,6 +456,40 @@ class Propagator:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self.lib.vgtb_load_state(self.ctx, buf, len(blob)), self.ctx)
+
+
+class Group:
+    """Several small-system Propagators stepped together, one launch per block
+    of steps with a workgroup per (system, k-point) (vgtb_group_*).  The
+    propagators must outlive the group; read each one's results as usual."""
+
+    def __init__(self, propagators):
+        self.lib = load_library()
+        self.members = list(propagators)
+        arr = (ctypes.c_void_p * len(self.members))(*[p.ctx for p in self.members])
+        h = ctypes.c_void_p()
+        _check(self.lib.vgtb_group_create(arr, len(self.members), ctypes.byref(h)))
+        self.grp = h
+
+    def step(self, n_steps: int):
+        _check(self.lib.vgtb_group_step(self.grp, int(n_steps)))
+
+    def close(self):
+        if getattr(self, "grp", None):
+            self.lib.vgtb_group_destroy(self.grp)
+            self.grp = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:

@@ -1,0 +1,142 @@
+"""Several small systems in one launch per block of steps (vgtb_group_*).
+
+Each system of a group follows the same steps, with the same arithmetic, as
+when it is stepped alone, so its densities (both leapfrog levels) and its
+history must equal the lone run bit for bit.  The groups below mix k-point
+counts (1 to 8), atom counts (8 and 9), field tables (kicks and pulses along
+different axes), time steps and rescale cadences, and are stepped in calls
+that cross the 64-step blocks.  With the SCC shift (Eq. 10) every system's
+workgroups meet at that system's own grid-wide barrier.  One member of each
+FP64 group is also compared with the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import vgtb_synth as vs
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2308_09782_amd")
+
+pytestmark = pytest.mark.gpu
+
+CALLS = [1, 63, 70, 16]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.load_library()
+
+
+def _members(scc):
+    gu = 0.25 if scc else None
+    n = sum(CALLS) + 8
+    return [
+        (vs.amorphous_si(1, (2, 2, 1), seed=1002, gamma_u=gu), 0.2,
+         vs.sin2_pulse_table(n, 0.2, 0.15, 30.0, 0.4)),
+        (vs.diamond_supercell(1, (2, 2, 2), gamma_u=gu), 0.2, vs.kick_table(1, 0.01, (0.0, 0.0, 1.0))),
+        (vs.random_cell(9, (1, 1, 1), seed=21, gamma_u=gu), 0.15,
+         vs.sin2_pulse_table(n, 0.15, 0.3, 20.0, 0.2, (0.0, 1.0, 0.0))),
+        (vs.amorphous_si(1, (3, 1, 1), seed=1003, gamma_u=gu), 0.25, vs.kick_table(1, 0.02)),
+    ]
+
+
+def _open(members, precision, cap, streams=None):
+    props = []
+    for i, (sysm, dt, atab) in enumerate(members):
+        if streams is not None and streams[i] is not None:
+            with torch.cuda.stream(streams[i]):
+                p = pkg.Propagator(sysm, dt, precision, rescale_every=10 + i, history_capacity=cap)
+        else:
+            p = pkg.Propagator(sysm, dt, precision, rescale_every=10 + i, history_capacity=cap)
+        p.ground_state()
+        p.set_field_table(atab)
+        props.append(p)
+    return props
+
+
+def _results(props, total):
+    out = []
+    for p in props:
+        h = p.read_observables(0, total)
+        out.append((h, p.get_density(0).cpu().numpy(), p.get_density(1).cpu().numpy(), p.step_index))
+        p.close()
+    return out
+
+
+def _same(a, b):
+    (ha, ca, pa, sa), (hb, cb, pb, sb) = a, b
+    assert sa == sb
+    assert np.array_equal(ca, cb) and np.array_equal(pa, pb)
+    for key in ("J", "E", "trace", "q"):
+        assert np.array_equal(ha[key], hb[key]), key
+
+
+@pytest.mark.parametrize("scc", [False, True])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_group_equals_each_system_alone(precision, scc):
+    members = _members(scc)
+    total = sum(CALLS)
+    print(f"group of {len(members)} ({precision}, scc={scc}): alone", flush=True)
+    alone = _open(members, precision, total)
+    for p in alone:
+        for c in CALLS:
+            p.step(c)
+    ref = _results(alone, total)
+    print("grouped", flush=True)
+    props = _open(members, precision, total)
+    with pkg.Group(props) as g:
+        for c in CALLS:
+            g.step(c)
+    got = _results(props, total)
+    for a, b in zip(got, ref):
+        _same(a, b)
+    if precision == "fp64":
+        sysm, dt, atab = members[0]
+        d_init, z, _ = oracle.ground_state(sysm)
+        want, _ = oracle.propagate(sysm, d_init, atab, dt, total, z=z)
+        jmax = np.abs(want["J"]).max()
+        assert jmax > 0
+        assert np.abs(got[0][0]["J"] - want["J"]).max() <= 1e-10 * jmax
+        assert np.abs(got[0][0]["q"] - want["q"]).max() < 1e-10
+
+
+def test_group_interleaved_with_lone_steps_on_two_streams():
+    """A member stepped alone between group calls, and members created on
+    another stream than the group's: the group joins their streams both ways."""
+    members = _members(False)
+    side = torch.cuda.Stream()
+    streams = [None, side, None, side]
+    plan_group = [50, 30]
+    extra = 20                                  # member 1 alone, between the group calls
+    totals = [sum(plan_group) + (extra if i == 1 else 0) for i in range(len(members))]
+    alone = _open(members, "fp64", max(totals))
+    for i, p in enumerate(alone):
+        p.step(totals[i])
+    ref = [_results([p], t)[0] for p, t in zip(alone, totals)]
+    props = _open(members, "fp64", max(totals), streams)
+    with pkg.Group(props) as g:
+        g.step(plan_group[0])
+        props[1].step(extra)
+        g.step(plan_group[1])
+    got = [_results([p], t)[0] for p, t in zip(props, totals)]
+    for a, b in zip(got, ref):
+        _same(a, b)
+
+
+def test_group_rejects_what_it_cannot_launch():
+    si = vs.amorphous_si(1, (1, 1, 1), seed=1002, gamma_u=None)
+    chain = vs.linear_chain(16)
+    with pkg.Propagator(si, 0.2, "fp64") as a, pkg.Propagator(si, 0.2, "fp16x3") as b, \
+            pkg.Propagator(chain, 0.2, "fp64") as c, \
+            pkg.Propagator(si, 0.2, "fp64", small_path=False) as d:
+        for bad in ([a, b], [a, c], [a, d], [a, a], []):
+            with pytest.raises(pkg.VgtbError) as e:
+                pkg.Group(bad)
+            assert e.value.status == pkg.VGTB_E_INVAL
+        with pkg.Group([a]) as g:                 # no density yet
+            with pytest.raises(pkg.VgtbError) as e:
+                g.step(1)
+            assert e.value.status == pkg.VGTB_E_STATE

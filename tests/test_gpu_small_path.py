@@ -1,9 +1,16 @@
-"""Small systems take whole blocks of steps in one launch (FP64, no SCC shift,
-N <= 40): the result must match the per-step kernels and the oracle.
+"""Small systems take whole blocks of steps in one launch (no SCC shift,
+N <= 40), in every precision form: the result must match the per-step kernels
+and the oracle.
 
 The calls below use step counts that cross the 64-step blocks (1, 63, 70,
 16), a history ring smaller than the run, a checkpoint taken in the middle,
-and both orbital counts (sp3 silicon and the one-orbital chain).
+and both orbital counts (sp3 silicon and the one-orbital chain).  The
+reduced-precision forms (FP32, 3xBF16, FP16X3 on the deviation from the
+reference density) run their own arithmetic inside the whole-step kernel: they
+are checked against the oracle (current within 1e-5 of its maximum) and
+against the per-step path, across rescales every 10 steps, from a
+non-stationary start (the constant term of a set density), and through a
+checkpoint.
 """
 import numpy as np
 import pytest
@@ -94,3 +101,146 @@ def test_small_path_against_oracle_with_checkpoint():
     jmax = np.abs(ref["J"]).max()
     assert np.abs(h_a["J"] - ref["J"]).max() <= 1e-10 * jmax
     assert np.abs(h_a["q"] - ref["q"]).max() < 1e-10
+
+
+REDUCED_TOL = {"fp32": 1e-6, "bf16x3": 5e-6, "fp16x3": 1e-6}
+
+
+def _run_form(small, sysm, dt, atab, calls, precision, start=None):
+    total = sum(calls)
+    with pkg.Propagator(sysm, dt, precision, rescale_every=10, history_capacity=total,
+                        small_path=small) as p:
+        if start is None:
+            p.ground_state()
+        else:
+            p.set_density(start)
+        p.set_field_table(atab)
+        p.profile(True)
+        for c in calls:
+            p.step(c)
+        prof = p.profile_read()
+        hist = p.read_observables(0, total)
+        cur = p.get_density(0).cpu().numpy()
+        prev = p.get_density(1).cpu().numpy()
+    return hist, cur, prev, prof
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("case", ["si8_k64", "chain16"])
+def test_reduced_forms_on_the_small_path(case, precision):
+    name, sysm, dt, atab = next(x for x in _cases() if x[0] == case)
+    calls = [1, 63, 70, 16]
+    total = sum(calls)
+    h1, d1, p1, prof1 = _run_form(True, sysm, dt, atab, calls, precision)
+    h0, d0, p0, prof0 = _run_form(False, sysm, dt, atab, calls, precision)
+    assert prof1["small"][1] == sum((c + 63) // 64 for c in calls)
+    assert prof1["gemm"][1] == 0 and prof0["small"][1] == 0
+    d_init, z, _ = oracle.ground_state(sysm)
+    ref, st = oracle.propagate(sysm, d_init, atab, dt, total, z=z)
+    jmax = np.abs(ref["J"]).max()
+    e_small = np.abs(h1["J"] - ref["J"]).max() / jmax
+    e_step = np.abs(h0["J"] - ref["J"]).max() / jmax
+    print(f"{case} {precision}: J err small path {e_small:.2e}, per-step path {e_step:.2e}")
+    assert e_small < 1e-5
+    assert np.abs(h1["J"] - h0["J"]).max() < REDUCED_TOL[precision] * jmax
+    for m in (d1, p1):
+        for k in range(sysm.n_k):
+            assert np.array_equal(m[k], m[k].conj().T)
+    # the rescale every 10 steps holds the trace
+    assert np.abs(h1["trace"] - sysm.n_electrons).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+def test_reduced_small_path_nonstationary_start_and_checkpoint(precision):
+    c = vs.CONFIGS["si8_k64"]
+    sysm = vs.config_system("si8_k64")
+    sysm = sysm.with_kpts(sysm.kpts[:16], np.full(16, 1.0 / 16))
+    d_init, z, _ = oracle.ground_state(sysm)
+    rng = np.random.default_rng(6)
+    start = []
+    for d in d_init:
+        a = rng.normal(size=d.shape) + 1j * rng.normal(size=d.shape)
+        start.append(d + 0.002 * (a + a.conj().T))
+    import dataclasses
+    sysm = dataclasses.replace(sysm, z_ref=z)
+    atab = vs.sin2_pulse_table(400, c["dt"], 0.2, 60.0, 0.3)
+    n1, n2 = 75, 60
+    with pkg.Propagator(sysm, c["dt"], precision, rescale_every=10, history_capacity=n1 + n2) as p:
+        p.set_density(np.stack(start))
+        p.set_field_table(atab)
+        p.profile(True)
+        p.step(n1)
+        blob = p.save_state()
+        p.step(n2)
+        assert p.profile_read()["small"][1] > 0
+        h_a = p.read_observables(0, n1 + n2)
+        cur_a = p.get_density(0).cpu().numpy()
+        p.load_state(blob)
+        p.step(n2)
+        cur_b = p.get_density(0).cpu().numpy()
+    assert np.array_equal(cur_a, cur_b)          # resume is bit-exact
+    ref, _ = oracle.propagate(sysm, start, atab, c["dt"], n1 + n2, z=z)
+    jmax = np.abs(ref["J"]).max()
+    assert np.abs(h_a["J"] - ref["J"]).max() < 1e-5 * jmax
+
+
+def _scc_case():
+    sysm = vs.amorphous_si(1, (2, 2, 1), seed=1002, gamma_u=0.25)
+    assert sysm.n_orb <= 40 and sysm.gamma is not None
+    atab = vs.sin2_pulse_table(400, 0.2, 0.15, 50.0, 0.4)
+    return sysm, atab
+
+
+def test_scc_small_path_matches_per_step_path_and_oracle():
+    """The SCC shift on the whole-steps path: every step waits at a grid-wide
+    barrier for the charges of all k-points.  Same trajectory as the per-step
+    kernels (1e-12) and the oracle (density 1e-10 on both levels, current 1e-10
+    of its maximum), across 64-step blocks and a wrapping history ring."""
+    sysm, atab = _scc_case()
+    cap = 100
+    h1, d1, p1, prof1 = _run(True, sysm, 0.2, atab, CALLS, cap)
+    h0, d0, p0, prof0 = _run(False, sysm, 0.2, atab, CALLS, cap)
+    assert prof1["small"][1] == sum((c + 63) // 64 for c in CALLS)
+    assert prof1["gemm"][1] == 0 and prof0["small"][1] == 0
+    for a, b in ((d1, d0), (p1, p0)):
+        err = max(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) for k in range(sysm.n_k))
+        assert err < 1e-12
+    jmax = np.abs(h0["J"]).max()
+    assert jmax > 0
+    for key, tol in (("J", 1e-12 * jmax), ("E", 1e-12 * np.abs(h0["E"]).max()), ("q", 1e-12)):
+        assert np.abs(h1[key] - h0[key]).max() < tol, key
+    total = sum(CALLS)
+    d_init, z, _ = oracle.ground_state(sysm)
+    ref, st = oracle.propagate(sysm, d_init, atab, 0.2, total, z=z)
+    for got, want in ((d1, st.d_cur), (p1, st.d_prev)):
+        err = max(np.linalg.norm(got[k] - want[k]) / np.linalg.norm(want[k]) for k in range(sysm.n_k))
+        assert err < 1e-10
+    jref = ref["J"][total - cap:]
+    assert np.abs(h1["J"] - jref).max() <= 1e-10 * np.abs(ref["J"]).max()
+    assert np.abs(h1["E"] - ref["E"][total - cap:]).max() < 1e-11 * np.abs(ref["E"]).max()
+    assert np.abs(h1["q"] - ref["q"][total - cap:]).max() < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+def test_scc_small_path_checkpoint_and_reduced_form(precision):
+    sysm, atab = _scc_case()
+    n1, n2 = 90, 60
+    with pkg.Propagator(sysm, 0.2, precision, rescale_every=10, history_capacity=n1 + n2) as p:
+        p.ground_state()
+        p.set_field_table(atab)
+        p.profile(True)
+        p.step(n1)
+        blob = p.save_state()
+        p.step(n2)
+        assert p.profile_read()["small"][1] > 0
+        h_a = p.read_observables(0, n1 + n2)
+        cur_a = p.get_density(0).cpu().numpy()
+        p.load_state(blob)
+        p.step(n2)
+        cur_b = p.get_density(0).cpu().numpy()
+    assert np.array_equal(cur_a, cur_b)          # resume is bit-exact
+    d_init, z, _ = oracle.ground_state(sysm)
+    ref, _ = oracle.propagate(sysm, d_init, atab, 0.2, n1 + n2, z=z)
+    jmax = np.abs(ref["J"]).max()
+    bar = 1e-10 if precision == "fp64" else 1e-5
+    assert np.abs(h_a["J"] - ref["J"]).max() <= bar * jmax
