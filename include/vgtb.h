@@ -447,8 +447,10 @@ typedef enum {
  *     wavefronts of 32x32, 3 = 8 of 64x32, 4 = 8 of 32x64, 5 = 4 of 64x64
  *     (3xBF16 and FP16X3; the 128x128 shapes when the padded size is a
  *     multiple of 128),
- * each launched `reps` times after one warm-up launch, and keeps the fastest
- * of each for the following steps.  Only scratch buffers are written: the
+ * after one warm-up launch of each, in `reps` interleaved rounds (every
+ * candidate once per round, each launch between its own events), and keeps
+ * the fastest of each kernel by the mean over rounds for the following steps;
+ * the current choice is kept unless another is at least 1% faster.  Only scratch buffers are written: the
  * densities, history and step index are unchanged.  The variants differ in
  * summation order only.  Needs a density (VGTB_E_STATE otherwise), reps >= 1
  * (VGTB_E_INVAL).  out_host may be NULL.  Synchronises the stream.  For a

@@ -180,12 +180,14 @@ void run(const typename Mfma<T>::C2 *a, const typename Mfma<T>::C2 *b, typename 
 
 }  // namespace
 
+int zgemm_default_tile(int n) { return n >= 1024 ? 2 : 1; }
+
 // tile: 1 = 32 x 32, 2 = 64 x 64 (four wavefronts), 3 = 128 x 64 (eight);
 // 0 = 64 x 64 from N = 1024 up, else 32 x 32.
 template <typename T>
 static void run_tile(const typename Mfma<T>::C2 *a, const typename Mfma<T>::C2 *b,
                      typename Mfma<T>::C2 *c, int n, int batch, int tile, hipStream_t s) {
-  if (tile == 0) tile = n >= 1024 ? 2 : 1;
+  if (tile == 0) tile = zgemm_default_tile(n);
   if (tile == 3) run<T, 128, 64, 16, 4, 2>(a, b, c, n, batch, s);
   else if (tile == 2) run<T, 64, 64, 16, 2, 2>(a, b, c, n, batch, s);
   else run<T, 32, 32, 16, 2, 2>(a, b, c, n, batch, s);

@@ -526,7 +526,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128_update(
 template <int E>
 static void launch_e(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                      hipStream_t s, int tile, const float *sa, const float *sb) {
-  if (tile == 0) tile = (np % BM2 == 0 && np >= 512) ? 2 : 1;
+  if (tile == 0) tile = split16_default_tile(np);
   if (tile >= 2 && tile <= 5 && np % BM2 == 0) {
     const int tm = np / BM2, tn = np / BN2;
     const dim3 grid(tm * tn, batch);
@@ -550,7 +550,7 @@ static bool launch_update_e(const uint16_t *a, const uint16_t *b, float2 *y, con
                             const double2 *m0, const double2 *dbase, double2 *dout, int n, int np,
                             int batch, double fac, int64_t *ctr, hipStream_t s, int tile,
                             const float *sa, const float *sb) {
-  if (tile == 0) tile = (np % BM2 == 0 && np >= 512) ? 2 : 1;
+  if (tile == 0) tile = split16_default_tile(np);
   if (tile < 2 || tile > 5 || np % BM2 != 0) return false;
   const int T = np / BM2;
   const dim3 grid(T * (T + 1) / 2 * batch);
@@ -566,6 +566,8 @@ static bool launch_update_e(const uint16_t *a, const uint16_t *b, float2 *y, con
 }
 
 }  // namespace
+
+int split16_default_tile(int np) { return (np % BM2 == 0 && np >= 512) ? 2 : 1; }
 
 bool launch_cgemm_update_split16(int fmt, const uint16_t *a, const uint16_t *b, float2 *y,
                                  const float2 *w, const double2 *m0, const double2 *dbase,

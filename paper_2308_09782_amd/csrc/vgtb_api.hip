@@ -1531,47 +1531,77 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   const bool dev = c->precision != VGTB_FP64;
   const int fmt = product_format(c);
   hipStream_t s = c->stream;
-  hipEvent_t e0, e1;
-  HIP_TRY(c, hipEventCreate(&e0));
-  HIP_TRY(c, hipEventCreate(&e1));
-  auto time_it = [&](auto &&launch, double &ms) -> vgtb_status {
-    launch();   // warm-up (code load, caches)
-    HIP_TRY(c, hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) launch();
-    HIP_TRY(c, hipEventRecord(e1, s));
-    HIP_TRY(c, hipEventSynchronize(e1));
-    float el = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&el, e0, e1));
-    ms = el / reps;
-    return VGTB_OK;
+  // The candidates of one kernel are timed in interleaved rounds (each launch
+  // between its own events), so that a drift of the clock during the
+  // measurement does not favour the ones timed first; the mean over rounds is
+  // kept.  A candidate replaces the first one (the current choice) only when it
+  // is at least 1% faster: closer than that, the timings are noise.
+  std::vector<hipEvent_t> ev;
+  auto time_all = [&](int count, auto &&launch, double *ms) -> vgtb_status {
+    ev.assign((size_t)2 * count * reps, nullptr);
+    vgtb_status rs = VGTB_OK;
+    for (auto &e : ev) {
+      const hipError_t he = hipEventCreate(&e);
+      if (he != hipSuccess) {
+        rs = fail(c, VGTB_E_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(he));
+        break;
+      }
+    }
+    for (int i = 0; rs == VGTB_OK && i < count; ++i) launch(i);   // warm-up (code load, caches)
+    for (int r = 0; rs == VGTB_OK && r < reps; ++r)
+      for (int i = 0; i < count; ++i) {
+        hipEvent_t *e = &ev[(size_t)2 * (r * count + i)];
+        if (hipEventRecord(e[0], s) != hipSuccess) rs = VGTB_E_DEVICE;
+        launch(i);
+        if (hipEventRecord(e[1], s) != hipSuccess) rs = VGTB_E_DEVICE;
+      }
+    if (rs == VGTB_OK && hipStreamSynchronize(s) != hipSuccess) rs = VGTB_E_DEVICE;
+    for (int i = 0; rs == VGTB_OK && i < count; ++i) {
+      double sum = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        float el = 0.f;
+        hipEvent_t *e = &ev[(size_t)2 * (r * count + i)];
+        if (hipEventElapsedTime(&el, e[0], e[1]) != hipSuccess) rs = VGTB_E_DEVICE;
+        sum += el;
+      }
+      ms[i] = sum / reps;
+    }
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (rs == VGTB_E_DEVICE && c->err.empty()) fail(c, rs, "vgtb_autotune: event timing failed");
+    return rs;
+  };
+  auto pick = [](const std::vector<int> &cand, const double *ms, int &choice) {
+    int best = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+      if (ms[i] < ms[best]) best = (int)i;
+    choice = (ms[best] < 0.99 * ms[0]) ? cand[(size_t)best] : cand[0];
   };
   // Operands: H_k at A = 0 and the current level (only scratch buffers are written).
   vgtb::launch_assemble(c->g, c->kpts_dev, nk, vgtb::StepSource{nullptr, nullptr}, c->spk,
                         c->scc ? c->v : nullptr, c->hq, c->h0k, c->ppk, s);
   const double2 *dcur = c->dlev[c->cur];
+  // Candidates, the current choice first.
   std::vector<int> sv;
   if (c->g.norb == 4) sv = {-1, -2, -4};
   if (c->g.group_size <= 8) {
     sv.push_back(1);
     sv.push_back(2);
   }
-  double best = 1e300;
-  for (int v : sv) {
-    double ms = 0.0;
-    st = time_it([&] {
-      if (dev) launch_deviation_spmm(c, dcur, fmt, v, s);
-      else vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, c->np, nullptr, v, s);
-    }, ms);
-    if (st != VGTB_OK) break;
-    if (t.n_spmm < 8) {
-      t.spmm_candidates[t.n_spmm] = v;
-      t.spmm_ms[t.n_spmm++] = ms;
-    }
-    if (ms < best) {
-      best = ms;
-      t.spmm_variant = v;
-    }
+  auto cur_sv = std::find(sv.begin(), sv.end(), c->spmm_variant);
+  if (cur_sv != sv.end()) std::rotate(sv.begin(), cur_sv, cur_sv + 1);
+  std::vector<double> sms(sv.size(), 0.0);
+  st = time_all((int)sv.size(), [&](int i) {
+    if (dev) launch_deviation_spmm(c, dcur, fmt, sv[(size_t)i], s);
+    else vgtb::launch_spmm(c->g, dcur, nullptr, n, nk, c->hq, nullptr, c->w, 0, c->np, nullptr,
+                           sv[(size_t)i], s);
+  }, sms.data());
+  if (st != VGTB_OK) return st;
+  for (size_t i = 0; i < sv.size() && t.n_spmm < 8; ++i) {
+    t.spmm_candidates[t.n_spmm] = sv[i];
+    t.spmm_ms[t.n_spmm++] = sms[i];
   }
+  pick(sv, sms.data(), t.spmm_variant);
   std::vector<int> gv;
   if (fmt >= 2) {
     gv.push_back(1);
@@ -1579,27 +1609,23 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   } else {
     gv = {1, 2, 3};
   }
-  best = 1e300;
-  for (int tile : gv) {
-    if (st != VGTB_OK) break;
-    double ms = 0.0;
-    st = time_it([&] {
-      if (fmt == 0) vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s, tile);
-      else launch_reduced_product(c, fmt, tile, s);
-    }, ms);
-    if (st != VGTB_OK) break;
-    if (t.n_gemm < 8) {
-      t.gemm_candidates[t.n_gemm] = tile;
-      t.gemm_ms[t.n_gemm++] = ms;
-    }
-    if (ms < best) {
-      best = ms;
-      t.gemm_tile = tile;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  // The current tile first (0, the size rule, counts as the tile it picks).
+  const int cur_tile = c->gemm_tile != 0 ? c->gemm_tile
+                                         : (fmt >= 2 ? vgtb::split16_default_tile(c->np)
+                                                     : vgtb::zgemm_default_tile(n));
+  auto cur_gv = std::find(gv.begin(), gv.end(), cur_tile);
+  if (cur_gv != gv.end()) std::rotate(gv.begin(), cur_gv, cur_gv + 1);
+  std::vector<double> gms(gv.size(), 0.0);
+  st = time_all((int)gv.size(), [&](int i) {
+    if (fmt == 0) vgtb::launch_zgemm_f64(c->sinv, c->w, c->y, n, nk, s, gv[(size_t)i]);
+    else launch_reduced_product(c, fmt, gv[(size_t)i], s);
+  }, gms.data());
   if (st != VGTB_OK) return st;
+  for (size_t i = 0; i < gv.size() && t.n_gemm < 8; ++i) {
+    t.gemm_candidates[t.n_gemm] = gv[i];
+    t.gemm_ms[t.n_gemm++] = gms[i];
+  }
+  pick(gv, gms.data(), t.gemm_tile);
   HIP_TRY(c, hipGetLastError());
   c->spmm_variant = t.spmm_variant;
   c->gemm_tile = t.gemm_tile;

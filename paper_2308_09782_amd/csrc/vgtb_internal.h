@@ -289,6 +289,11 @@ bool launch_cgemm_update_split16(int fmt, const uint16_t *a, const uint16_t *b, 
                                  double2 *dout, int n, int np, int batch, double fac, int64_t *ctr,
                                  const float *sa, const float *sb, hipStream_t s, int tile);
 
+// Tiles the size rule picks when no tile is given (tile 0): the FP64 / FP32
+// complex product at size n, the 16-bit split product at padded size np.
+int zgemm_default_tile(int n);
+int split16_default_tile(int np);
+
 // ---- launchers (split_f16.hip) ------------------------------------------------
 // Power-of-two scale per k putting max(|re|, |im|) in [2^13, 2^14); part holds
 // nk * f16_scale_parts() floats.

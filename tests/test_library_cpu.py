@@ -174,3 +174,18 @@ def test_kernel_choices_are_validated_options():
     src = "".join(open(os.path.join(os.path.dirname(pkg.LIB_PATH), "csrc", f)).read()
                   for f in os.listdir(os.path.join(os.path.dirname(pkg.LIB_PATH), "csrc")))
     assert "getenv" not in src
+
+
+def test_group_arguments_rejected_before_any_device_call():
+    import ctypes
+    lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.vgtb_group_create(None, 1, ctypes.byref(h)) == pkg.VGTB_E_INVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.vgtb_group_create(arr, 0, ctypes.byref(h)) == pkg.VGTB_E_INVAL
+    assert lib.vgtb_group_create(arr, 5000, ctypes.byref(h)) == pkg.VGTB_E_INVAL
+    assert lib.vgtb_group_create(arr, 2, ctypes.byref(h)) == pkg.VGTB_E_INVAL   # null contexts
+    assert b"null context" in lib.vgtb_last_error(None)
+    assert lib.vgtb_group_create(arr, 2, None) == pkg.VGTB_E_INVAL
+    assert lib.vgtb_group_step(None, 1) == pkg.VGTB_E_INVAL
+    lib.vgtb_group_destroy(None)
