@@ -154,8 +154,9 @@ enum {
 /*
  * Options of one context.  Zero-initialise the struct, then set dt and
  * history_capacity: every other zero is the default.  The kernel choices (tile_override, spmm_variant,
- * spmm_group) change only the summation order of the products, never the
- * method; vgtb_autotune can choose them instead.  No process-wide setting
+ * spmm_group) change only how the terms of the products are grouped and
+ * summed (results agree to rounding), never the method; vgtb_autotune can
+ * choose them instead.  No process-wide setting
  * (environment variable, global) is read.
  */
 typedef struct {
@@ -174,7 +175,9 @@ typedef struct {
                                   products, 1 = 64x64, 2 (0) = 128x64, 3 = 128x128   */
   int32_t spmm_variant;        /* sparse product W = H D: 0 = default (-1); -1, -2, -4
                                   = FP64 matrix cores with 1, 2, 4 16-column slices per
-                                  wavefront (four orbitals per atom only); 1, 2 =
+                                  wavefront (four orbitals per atom only); -11, -12,
+                                  -14 = the same with three real products per complex
+                                  one (Dr Hr, Di Hi, (Dr + Di)(Hr + Hi)); 1, 2 =
                                   vector FMAs with 1, 2 columns per thread (always the
                                   vector form for one orbital per atom)              */
   int32_t spmm_group;          /* atoms per row group of the sparse product: 0 (= 8),
@@ -439,7 +442,8 @@ typedef enum {
  *
  * Times, on this context's own buffers and stream, every candidate of
  *   - the block-sparse product W = H D: FP64 matrix cores with 1, 2 or 4
- *     16-column slices per wavefront (variant -1, -2, -4; four orbitals per
+ *     16-column slices per wavefront, four real products per complex one
+ *     (variant -1, -2, -4) or three (variant -11, -12, -14; four orbitals per
  *     atom), or vector FMAs with 1 or 2 columns per thread (variant 1, 2;
  *     row groups of at most 8 atoms);
  *   - the dense product S^-1 W: workgroup tiles 1 = 32x32, 2 = 64x64,
@@ -450,9 +454,10 @@ typedef enum {
  * after one warm-up launch of each, in `reps` interleaved rounds (every
  * candidate once per round, each launch between its own events), and keeps
  * the fastest of each kernel by the mean over rounds for the following steps;
- * the current choice is kept unless another is at least 1% faster.  Only scratch buffers are written: the
- * densities, history and step index are unchanged.  The variants differ in
- * summation order only.  Needs a density (VGTB_E_STATE otherwise), reps >= 1
+ * the current choice is kept unless another is at least 1% faster.  Only
+ * scratch buffers are written: the densities, history and step index are
+ * unchanged; in the deviation forms the constant H0 D0 is formed again with a
+ * newly chosen sparse product.  The variants agree to rounding.  Needs a density (VGTB_E_STATE otherwise), reps >= 1
  * (VGTB_E_INVAL).  out_host may be NULL.  Synchronises the stream.  For a
  * context on the small-system path (whole steps per launch) or with the
  * Crank-Nicolson propagator nothing is timed (n_spmm = n_gemm = 0).

@@ -565,11 +565,14 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
 // (re += Dr Hr - Di Hi, im += Di Hr + Dr Hi) into separate accumulators.
 // Compared with the vector form, one LDS read of H now feeds 16 matrix
 // instructions instead of four FMAs, and no zero blocks are multiplied.
+// G3: the complex product in three real products per slice instead of four,
+// P1 = Dr Hr, P2 = Di Hi, P3 = (Dr + Di)(Hr + Hi), with re = P1 - P2 and
+// im = P3 - P1 - P2 formed in the epilogue (one accumulator more per slice).
 __device__ inline double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-template <bool DELTA, int OUT, int KG, int CB>
+template <bool DELTA, int OUT, int KG, int CB, bool G3>
 __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *__restrict__ d,
                                                    int n, const double2 *__restrict__ hq,
                                                    const double2 *__restrict__ c0,
@@ -591,11 +594,14 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) lcol[cb] = min(cw + cb * 16 + (lane & 15), n - 1);
   const size_t base = (size_t)k * n * n;
-  double accr[KG][CB], acci[KG][CB];
+  double accr[KG][CB], acci[KG][CB], accs[G3 ? KG : 1][G3 ? CB : 1];
 #pragma unroll
   for (int il = 0; il < KG; ++il)
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) accr[il][cb] = acci[il][cb] = 0.0;
+    for (int cb = 0; cb < CB; ++cb) {
+      accr[il][cb] = acci[il][cb] = 0.0;
+      if (G3) accs[il][cb] = 0.0;
+    }
   // Every atom has at least its on-site block (checked when the graph is
   // built), so a group has at least one entry and the loop runs at least
   // once; saying so keeps the accumulators in place up to the epilogue.
@@ -621,8 +627,12 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
       for (int cb = 0; cb < CB; ++cb) dn[cb] = d[roff + lcol[cb]];
     }
     for (int el = 0; el < ne; ++el) {
+      double dsum[G3 ? CB : 1];
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) dv[cb] = dn[cb];
+      for (int cb = 0; cb < CB; ++cb) {
+        dv[cb] = dn[cb];
+        if (G3) dsum[cb] = dv[cb].x + dv[cb].y;
+      }
       if (el + 1 < ne) {
         const size_t roff = base + (size_t)(s_j[el + 1] * 4 + nu) * n;
 #pragma unroll
@@ -634,13 +644,23 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
       for (int il = 0; il < KG; ++il) {
         if (mask & (1 << il)) {
           const double2 h = hs[slot * E2 + hsel];
-          const double nhi = -h.y;
+          if (G3) {
+            const double hsum = h.x + h.y;
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            accr[il][cb] = mfma4(dv[cb].x, h.x, accr[il][cb]);
-            acci[il][cb] = mfma4(dv[cb].y, h.x, acci[il][cb]);
-            accr[il][cb] = mfma4(dv[cb].y, nhi, accr[il][cb]);
-            acci[il][cb] = mfma4(dv[cb].x, h.y, acci[il][cb]);
+            for (int cb = 0; cb < CB; ++cb) {
+              accr[il][cb] = mfma4(dv[cb].x, h.x, accr[il][cb]);
+              acci[il][cb] = mfma4(dv[cb].y, h.y, acci[il][cb]);
+              accs[il][cb] = mfma4(dsum[cb], hsum, accs[il][cb]);
+            }
+          } else {
+            const double nhi = -h.y;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+              accr[il][cb] = mfma4(dv[cb].x, h.x, accr[il][cb]);
+              acci[il][cb] = mfma4(dv[cb].y, h.x, acci[il][cb]);
+              accr[il][cb] = mfma4(dv[cb].y, nhi, accr[il][cb]);
+              acci[il][cb] = mfma4(dv[cb].x, h.y, acci[il][cb]);
+            }
           }
           ++slot;
         }
@@ -660,6 +680,7 @@ __global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *_
       const int r = (I0 + il) * 4 + mu;
       const bool ok = col < n && I0 + il < g.n_atoms;
       double2 out = make_double2(accr[il][cb], acci[il][cb]);
+      if (G3) out = make_double2(accr[il][cb] - acci[il][cb], accs[il][cb] - accr[il][cb] - acci[il][cb]);
       if (DELTA && ok) {
         const double2 cv = c0[base + (size_t)r * n + col];
         out.x -= cv.x;
@@ -1571,30 +1592,39 @@ void launch_assemble(const PairGraph &g, const double *kpts, int nk, StepSource 
     hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, s, g, kpts, src, spk, v, hq, h0k, ppk);
 }
 
-template <bool DELTA, int OUT, int CB>
+template <bool DELTA, int OUT, int CB, bool G3>
 static void spmm_mfma_launch_cb(hipStream_t s, const PairGraph &g, const double2 *d, int n,
                                 const double2 *hq, const double2 *c0, void *w, int np, int nk,
                                 float2 *w32, int ncols, const float *wscale, unsigned *wmax) {
   const int nw = std::max(1, std::min(4, (ncols + 16 * CB - 1) / (16 * CB)));
   dim3 grid(blocks_for(ncols, 16 * CB * nw), g.n_groups, nk);
   if (g.group_size == 16)
-    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 16, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq,
+    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 16, CB, G3>), grid, dim3(64 * nw), 0, s, g, d, n, hq,
                        c0, w, np, nk, w32, wscale, wmax);
   else if (g.group_size == 8)
-    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 8, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
+    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 8, CB, G3>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
                        w, np, nk, w32, wscale, wmax);
   else
-    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 4, CB>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
+    hipLaunchKernelGGL((k_spmm_mfma<DELTA, OUT, 4, CB, G3>), grid, dim3(64 * nw), 0, s, g, d, n, hq, c0,
                        w, np, nk, w32, wscale, wmax);
 }
 
 template <bool DELTA, int OUT>
 static void spmm_mfma_launch(hipStream_t s, const PairGraph &g, const double2 *d, int n,
                              const double2 *hq, const double2 *c0, void *w, int np, int nk,
-                             float2 *w32, int cb, int ncols, const float *wscale, unsigned *wmax) {
-  if (cb == 4) spmm_mfma_launch_cb<DELTA, OUT, 4>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax);
-  else if (cb == 2) spmm_mfma_launch_cb<DELTA, OUT, 2>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax);
-  else spmm_mfma_launch_cb<DELTA, OUT, 1>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax);
+                             float2 *w32, int cb, bool g3, int ncols, const float *wscale,
+                             unsigned *wmax) {
+#define VG_CB(CB, G3) spmm_mfma_launch_cb<DELTA, OUT, CB, G3>(s, g, d, n, hq, c0, w, np, nk, w32, ncols, wscale, wmax)
+  if (g3) {
+    if (cb == 4) VG_CB(4, true);
+    else if (cb == 2) VG_CB(2, true);
+    else VG_CB(1, true);
+  } else {
+    if (cb == 4) VG_CB(4, false);
+    else if (cb == 2) VG_CB(2, false);
+    else VG_CB(1, false);
+  }
+#undef VG_CB
 }
 
 void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n, int nk,
@@ -1603,8 +1633,9 @@ void launch_spmm(const PairGraph &g, const double2 *d, const double2 *d0, int n,
                  unsigned *wmax) {
   if (ncols <= 0 || ncols > n) ncols = n;
   if (g.norb == 4 && variant < 0) {
-    const int cb = -variant;
-#define VG_SPMM_MFMA(DL, OUT) spmm_mfma_launch<DL, OUT>(s, g, d, n, hq, c0, w, np, nk, w32, cb, ncols, wscale, wmax)
+    const bool g3 = variant <= -10;   // -11, -12, -14: three real products per complex one
+    const int cb = g3 ? -variant - 10 : -variant;
+#define VG_SPMM_MFMA(DL, OUT) spmm_mfma_launch<DL, OUT>(s, g, d, n, hq, c0, w, np, nk, w32, cb, g3, ncols, wscale, wmax)
     if (!d0) VG_SPMM_MFMA(false, 0);
     else if (out_format == 0) VG_SPMM_MFMA(true, 0);
     else if (out_format == 1) VG_SPMM_MFMA(true, 1);

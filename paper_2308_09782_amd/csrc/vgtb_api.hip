@@ -66,7 +66,8 @@ struct HostGraph {
 
 // Kernel choices of a context, from its options (no process-wide state).
 // Sparse product W = H D: spmm_variant -1, -2, -4 = FP64 matrix cores with
-// that many 16-column slices per wavefront (four orbitals per atom), 1 or 2 =
+// that many 16-column slices per wavefront (four orbitals per atom), -11,
+// -12, -14 = the same with three real products per complex one, 1 or 2 =
 // vector FMAs with that many columns per thread; 0 = -1 (the vector form is
 // always used for one orbital per atom).  spmm_group: atoms per row group,
 // 4 or 8 (0 = 8), or 16 with the matrix-core variants.
@@ -242,8 +243,8 @@ vgtb_status validate(const vgtb_system *s, const vgtb_options *o, std::string &m
   }
   {
     const int v = o->spmm_variant, g = o->spmm_group;
-    if (v != 0 && v != -1 && v != -2 && v != -4 && v != 1 && v != 2) {
-      msg = "spmm_variant must be 0, -1, -2, -4 (matrix cores) or 1, 2 (vector FMAs)";
+    if (v != 0 && v != -1 && v != -2 && v != -4 && v != -11 && v != -12 && v != -14 && v != 1 && v != 2) {
+      msg = "spmm_variant must be 0, -1, -2, -4, -11, -12, -14 (matrix cores) or 1, 2 (vector FMAs)";
       return VGTB_E_INVAL;
     }
     if (v < 0 && s->orbs_per_atom != 4) {
@@ -1583,7 +1584,7 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   const double2 *dcur = c->dlev[c->cur];
   // Candidates, the current choice first.
   std::vector<int> sv;
-  if (c->g.norb == 4) sv = {-1, -2, -4};
+  if (c->g.norb == 4) sv = {-1, -2, -4, -11, -12, -14};
   if (c->g.group_size <= 8) {
     sv.push_back(1);
     sv.push_back(2);
@@ -1627,9 +1628,16 @@ vgtb_status vgtb_autotune(vgtb_ctx *c, int32_t reps, vgtb_tuning *out) {
   }
   pick(gv, gms.data(), t.gemm_tile);
   HIP_TRY(c, hipGetLastError());
+  const bool new_spmm = c->spmm_variant != t.spmm_variant;
   c->spmm_variant = t.spmm_variant;
   c->gemm_tile = t.gemm_tile;
   drop_graphs(c);   // captured steps name the previous kernels
+  // C0 = H0 D0 again with the chosen sparse product, whose rounding may differ:
+  // a stationary density then still gives W = H D - C0 = 0 exactly.
+  if (new_spmm && c->d0) {
+    prepare_reference(c, c->m0_active);
+    HIP_TRY(c, hipGetLastError());
+  }
   if (out) *out = t;
   return VGTB_OK;
 }

@@ -45,7 +45,7 @@ def _check_tuning(t, precision, norb, np_mult_128):
     assert t["gemm_tile"] in t["gemm_ms"]
     assert all(v > 0 for v in t["spmm_ms"].values())
     assert all(v > 0 for v in t["gemm_ms"].values())
-    want_spmm = ({-1, -2, -4} if norb == 4 else set()) | {1, 2}
+    want_spmm = ({-1, -2, -4, -11, -12, -14} if norb == 4 else set()) | {1, 2}
     assert set(t["spmm_ms"]) == want_spmm
     if precision in ("bf16x3", "fp16x3"):
         assert set(t["gemm_ms"]) == ({1, 2, 3, 4, 5} if np_mult_128 else {1})

@@ -199,15 +199,21 @@ def test_fp16_split_is_more_accurate_than_bf16():
     assert e_fp < e_bf / 4
 
 
-def test_fp16x3_exactly_stationary_when_w_vanishes():
+@pytest.mark.parametrize("small_path,tune", [(True, False), (False, False), (False, True)])
+def test_fp16x3_exactly_stationary_when_w_vanishes(small_path, tune):
     # No SCC shift and A = 0: H equals H0 and D stays D(0), so W = H D - H0 D(0)
-    # is exactly zero (the same kernel forms both products); its maximum is zero,
-    # the split keeps scale 1, and the density must stay D(0) bit for bit.
+    # is exactly zero (the same kernel forms both products, also after the
+    # autotuner has chosen another sparse product); its maximum is zero, the
+    # split keeps scale 1, and the density must stay D(0) bit for bit.  Both the
+    # whole-steps kernel of small systems and the per-step kernels.
     sysm = vs.diamond_supercell(1, (2, 2, 2), seed=1001)
     assert sysm.gamma is None
     n = 30
-    with pkg.Propagator(sysm, 0.2, "fp16x3", history_capacity=n) as p:
+    with pkg.Propagator(sysm, 0.2, "fp16x3", history_capacity=n, small_path=small_path,
+                        spmm_variant=2 if tune else 0) as p:
         p.ground_state()
+        if tune:
+            p.autotune(2)
         d_init = p.get_density(0).cpu().numpy()
         p.set_field_table(vs.kick_table(1, 0.0))
         p.step(n)

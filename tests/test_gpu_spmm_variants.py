@@ -1,8 +1,9 @@
 """Every kernel variant of the block-sparse product W = H D propagates alike.
 
 The product runs as vector FMAs (one or two columns per thread) or on the
-FP64 matrix cores (one, two or four 16-column slices per wave), over row
-groups of 4, 8 or 16 atoms; the variants differ only in summation order.
+FP64 matrix cores (one, two or four 16-column slices per wave, with four real
+products per complex one, or three: Dr Hr, Di Hi and (Dr + Di)(Hr + Hi)), over
+row groups of 4, 8 or 16 atoms; the variants agree to rounding.
 Each variant is checked against the oracle on a ragged 13-atom system (a
 partial row group and a partial column slice) from a non-stationary start,
 and against the default variant on the 64-atom a-Si pulse case in the FP64
@@ -31,6 +32,9 @@ VARIANTS = [
     {"spmm_variant": -4, "spmm_group": 4},
     {"spmm_variant": -1, "spmm_group": 16},
     {"spmm_variant": -2, "spmm_group": 16},
+    {"spmm_variant": -11},
+    {"spmm_variant": -12, "spmm_group": 4},
+    {"spmm_variant": -14, "spmm_group": 16},
 ]
 IDS = ["default"] + ["-".join(f"{k[5:]}{v}" for k, v in c.items()) for c in VARIANTS[1:]]
 

@@ -158,6 +158,8 @@ def test_kernel_choices_are_validated_options():
     assert pkg.vgtb_workspace_size(s, pkg.make_options(0.2, "fp16x3", tile=5)) > 0
     assert pkg.vgtb_workspace_size(s, pkg.make_options(0.2, propagator="crank_nicolson", tile=3)) > 0
     _expect_inval(s, pkg.make_options(0.2, spmm_variant=3), match="spmm_variant")
+    _expect_inval(s, pkg.make_options(0.2, spmm_variant=-13), match="spmm_variant")
+    _expect_inval(chain, pkg.make_options(0.2, spmm_variant=-12), match="four orbitals")
     _expect_inval(chain, pkg.make_options(0.2, spmm_variant=-2), match="four orbitals")
     _expect_inval(s, pkg.make_options(0.2, spmm_group=5), match="spmm_group")
     _expect_inval(s, pkg.make_options(0.2, spmm_variant=1, spmm_group=16), match="matrix-core")
@@ -165,6 +167,7 @@ def test_kernel_choices_are_validated_options():
     bad.flags = 8
     _expect_inval(s, bad, match="flags")
     for kw in ({"spmm_variant": -4, "spmm_group": 16}, {"spmm_variant": 2, "spmm_group": 4},
+               {"spmm_variant": -11}, {"spmm_variant": -14, "spmm_group": 16},
                {"graphs": False, "small_path": False}):
         assert pkg.vgtb_workspace_size(s, pkg.make_options(0.2, **kw)) > 0
     # the row-group size changes the stored neighbour lists, so it reaches the sizing
