@@ -572,8 +572,12 @@ __device__ inline double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
+// The four-slice three-product form of row groups up to 8 atoms is held to
+// two wavefronts per SIMD (256 registers): its independent accumulators, not
+// occupancy, cover the latencies, and left to itself the compiler moves the
+// deviation form's epilogue into one wave per SIMD.
 template <bool DELTA, int OUT, int KG, int CB, bool G3>
-__global__ __launch_bounds__(256) void k_spmm_mfma(PairGraph g, const double2 *__restrict__ d,
+__global__ __launch_bounds__(256, (G3 && CB == 4 && KG <= 8) ? 2 : 1) void k_spmm_mfma(PairGraph g, const double2 *__restrict__ d,
                                                    int n, const double2 *__restrict__ hq,
                                                    const double2 *__restrict__ c0,
                                                    void *__restrict__ wout, int np, int nk,

@@ -33,6 +33,7 @@ VARIANTS = [
     {"spmm_variant": -1, "spmm_group": 16},
     {"spmm_variant": -2, "spmm_group": 16},
     {"spmm_variant": -11},
+    {"spmm_variant": -14},
     {"spmm_variant": -12, "spmm_group": 4},
     {"spmm_variant": -14, "spmm_group": 16},
 ]
