@@ -568,6 +568,25 @@ __global__ __launch_bounds__(256) void k_spmm(PairGraph g, const double2 *__rest
 // G3: the complex product in three real products per slice instead of four,
 // P1 = Dr Hr, P2 = Di Hi, P3 = (Dr + Di)(Hr + Hi), with re = P1 - P2 and
 // im = P3 - P1 - P2 formed in the epilogue (one accumulator more per slice).
+// Lane q of each quad of lanes holds row q of a 4 x 4 matrix M of 16-bit
+// values as x0 = M[q][0] | M[q][1] << 16, x1 = M[q][2] | M[q][3] << 16; the
+// result is column q, (M[0][q] | M[1][q] << 16, M[2][q] | M[3][q] << 16).
+// Two quad permutations (DPP, no LDS traffic): first the 2 x 2 blocks are
+// exchanged between lanes q and q ^ 2, then single values between q and q ^ 1.
+// Every lane of the quad must be active.
+__device__ inline uint2 quad_transpose16(uint32_t x0, uint32_t x1, int q) {
+  const bool upper = (q & 2) != 0;
+  const uint32_t ra = (uint32_t)__builtin_amdgcn_mov_dpp((int)(upper ? x0 : x1), 0x4E, 0xF, 0xF, false);
+  // a: row q & 1 of columns 2 (q >> 1) and 2 (q >> 1) + 1; b: row (q & 1) + 2 of the same.
+  const uint32_t a = upper ? ra : x0;
+  const uint32_t b = upper ? x1 : ra;
+  const bool odd = (q & 1) != 0;
+  const uint32_t send = odd ? ((a & 0xFFFFu) | (b << 16)) : ((a >> 16) | (b & 0xFFFF0000u));
+  const uint32_t rb = (uint32_t)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);
+  if (odd) return make_uint2((rb & 0xFFFFu) | (a & 0xFFFF0000u), (rb >> 16) | (b & 0xFFFF0000u));
+  return make_uint2((a & 0xFFFFu) | (rb << 16), (b & 0xFFFFu) | (rb & 0xFFFF0000u));
+}
+
 __device__ inline double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
@@ -676,6 +695,18 @@ __global__ __launch_bounds__(256, (G3 && CB == 4 && KG <= 8) ? 2 : 1) void k_spm
   const int mu = lane & 3;
   const float sc = OUT == 3 ? wscale[k] : 1.0f;
   float wm = 0.0f;
+  // C0 of the deviation form is read one column slice ahead of its use, so
+  // that the loads of slice cb + 1 are in flight while slice cb is stored.
+  auto c0_at = [&](int cb, int il) -> double2 {
+    const int col = cw + cb * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+    if (col < n && I0 + il < g.n_atoms) return c0[base + (size_t)((I0 + il) * 4 + mu) * n + col];
+    return make_double2(0.0, 0.0);
+  };
+  double2 cpre[DELTA ? KG : 1];
+  if (DELTA) {
+#pragma unroll
+    for (int il = 0; il < KG; ++il) cpre[il] = c0_at(0, il);
+  }
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     const int col = cw + cb * 16 + 4 * ((lane >> 2) & 3) + (lane >> 4);
@@ -685,8 +716,9 @@ __global__ __launch_bounds__(256, (G3 && CB == 4 && KG <= 8) ? 2 : 1) void k_spm
       const bool ok = col < n && I0 + il < g.n_atoms;
       double2 out = make_double2(accr[il][cb], acci[il][cb]);
       if (G3) out = make_double2(accr[il][cb] - acci[il][cb], accs[il][cb] - accr[il][cb] - acci[il][cb]);
-      if (DELTA && ok) {
-        const double2 cv = c0[base + (size_t)r * n + col];
+      if (DELTA) {
+        const double2 cv = cpre[il];
+        if (cb + 1 < CB) cpre[il] = c0_at(cb + 1, il);
         out.x -= cv.x;
         out.y -= cv.y;
       }
@@ -696,8 +728,8 @@ __global__ __launch_bounds__(256, (G3 && CB == 4 && KG <= 8) ? 2 : 1) void k_spm
         if (ok) static_cast<float2 *>(wout)[base + (size_t)r * n + col] = make_float2((float)out.x, (float)out.y);
       } else {
         if (ok) w32[base + (size_t)r * n + col] = make_float2((float)out.x, (float)out.y);
-        // bf16 planes: the four rows of the atom sit in lanes 4m..4m+3; lane 4m
-        // gathers them and writes one 8-byte word per plane.
+        // 16-bit planes: the four rows of the atom sit in lanes 4m..4m+3, and
+        // lane 4m + p writes the four rows of plane p as one 8-byte word.
         uint16_t hv[4];
         if (OUT == 2) {
           split_bf16(out.x, hv[0], hv[1]);
@@ -707,16 +739,15 @@ __global__ __launch_bounds__(256, (G3 && CB == 4 && KG <= 8) ? 2 : 1) void k_spm
           split_f16(out.y, sc, hv[2], hv[3]);
           if (ok) wm = fmaxf(wm, fmaxf(fabsf((float)out.x), fabsf((float)out.y)));
         }
+        // Lane mu of the quad holds the four plane values of row mu; after the
+        // transpose it holds the four rows of plane mu, one 8-byte word.
+        const uint2 pk = quad_transpose16((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                                          (uint32_t)hv[2] | ((uint32_t)hv[3] << 16), mu);
         uint16_t *w = static_cast<uint16_t *>(wout);
         const size_t plane = (size_t)nk * np * np;
-        const size_t off = (size_t)k * np * np + ((size_t)(r >> 3) * np + col) * 8 + (r & 7);
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const uint32_t v = hv[p];
-          const uint32_t lo = v | ((uint32_t)__shfl_down((int)v, 1) << 16);
-          const uint32_t hi = (uint32_t)__shfl_down((int)lo, 2);
-          if (ok && mu == 0) *reinterpret_cast<uint2 *>(w + p * plane + off) = make_uint2(lo, hi);
-        }
+        const int r0 = r - mu;   // first row of the atom (a multiple of 4)
+        const size_t off = (size_t)k * np * np + ((size_t)(r0 >> 3) * np + col) * 8 + (r0 & 7);
+        if (ok) *reinterpret_cast<uint2 *>(w + mu * plane + off) = pk;
       }
       // One atom's results at a time: keeps the accumulators from being
       // moved out of the matrix registers all at once.
