@@ -26,9 +26,9 @@ def _need_gpu():
     pkg.load_library()
 
 
-def run_gpu(sysm, atab, dt, n_steps, precision, rescale_every=50, d0=None):
+def run_gpu(sysm, atab, dt, n_steps, precision, rescale_every=50, d0=None, **kernel_options):
     with pkg.Propagator(sysm, dt, precision, rescale_every=rescale_every,
-                        history_capacity=max(n_steps, 1)) as p:
+                        history_capacity=max(n_steps, 1), **kernel_options) as p:
         if d0 is None:
             p.ground_state()
         else:
@@ -123,9 +123,10 @@ def test_c2_scc_pulse_with_the_timed_tiles(c2_reference, precision, tile):
         assert err < J_TOL
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
-def test_ragged_padding_and_arbitrary_start(precision):
-    """N = 52 (bf16 planes padded to 64), non-stationary start."""
+@pytest.fixture(scope="module")
+def ragged_reference():
+    """13 atoms (N = 52: a partial row group of the sparse product, 16-bit planes
+    padded to 64), SCC, non-stationary start, 400 steps of the oracle."""
     sysm = vs.random_cell(13, (2, 1, 1), seed=3, gamma_u=0.25)
     d0, z, _ = oracle.ground_state(sysm)
     rng = np.random.default_rng(1)
@@ -136,7 +137,26 @@ def test_ragged_padding_and_arbitrary_start(precision):
     sysm = dataclasses.replace(sysm, z_ref=z)
     atab = vs.kick_table(1, 0.02)
     ref, st = oracle.propagate(sysm, start, atab, 0.2, 400, z=z)
-    h, cur, _ = run_gpu(sysm, atab, 0.2, 400, precision, d0=np.stack(start))
+    return sysm, np.stack(start), atab, ref, st
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16x3"])
+def test_ragged_padding_and_arbitrary_start(ragged_reference, precision):
+    """N = 52 (bf16 planes padded to 64), non-stationary start."""
+    sysm, start, atab, ref, st = ragged_reference
+    h, cur, _ = run_gpu(sysm, atab, 0.2, 400, precision, d0=start)
+    assert j_err(h, ref) < J_TOL
+    assert rho_err(cur, st.d_cur) < 1e-4
+
+
+@pytest.mark.parametrize("variant", [-2, -4, -11, -12, -14])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+def test_ragged_deviation_epilogue_every_matrix_core_variant(ragged_reference, precision, variant):
+    """The 16-bit planes of W as each matrix-core sparse-product variant writes them
+    (C0 subtracted, the rows of an atom gathered across a quad of lanes): a partial
+    row group and a column slice mostly beyond N, against the oracle."""
+    sysm, start, atab, ref, st = ragged_reference
+    h, cur, _ = run_gpu(sysm, atab, 0.2, 400, precision, d0=start, spmm_variant=variant)
     assert j_err(h, ref) < J_TOL
     assert rho_err(cur, st.d_cur) < 1e-4
 
