@@ -8,6 +8,14 @@
 // sa[k], sb[k] into fp16's range, about 2^-21; the epilogue divides by
 // sa[k] sb[k] (exact).
 //
+// The imaginary part is accumulated as +Im in even 32-deep stages and as -Im in
+// odd ones (operands and accumulator negated, which is exact): the matrix
+// instruction's accumulation is biased toward -infinity (on random operands
+// about -0.09 ulp of the largest term per instruction), and in Y - Y^dag the
+// imaginary parts of (i, j) and (j, i) add, so an unalternated bias would drift
+// the density at every step; alternating the sign cancels it.  The real parts
+// subtract in Y - Y^dag, so their biases cancel by themselves.
+//
 // Operand storage (16-bit planes, p = re_hi, re_lo, im_hi, im_lo; np = padded N,
 // a multiple of 64, zero-filled beyond N):
 //   A: plane p, batch k: row-major np x np            (A[i][kk] at i*np + kk)
@@ -17,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "vgtb_internal.h"
 
@@ -117,12 +126,15 @@ __global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict
 #pragma unroll
       for (int p = 0; p < 4; ++p) fb[b][p] = Bs[p][lg][wn0 + b * 16 + lr];
     // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+    const bool flip = (kt & 1) != 0;   // odd stages accumulate -Im
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const u32x4 nih = negate8(fa[a][2]), nil = negate8(fa[a][3]);
+      const u32x4 i0 = flip ? negate8(fa[a][0]) : fa[a][0], i1 = flip ? negate8(fa[a][1]) : fa[a][1];
+      const u32x4 i2 = flip ? nih : fa[a][2], i3 = flip ? nil : fa[a][3];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        v4f r = cr[a][b], m = ci[a][b];
+        v4f r = cr[a][b], m = flip ? -ci[a][b] : ci[a][b];
         // Re += ar br - ai bi
         r = mma<E>(fa[a][0], fb[b][0], r);
         r = mma<E>(fa[a][0], fb[b][1], r);
@@ -130,15 +142,15 @@ __global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict
         r = mma<E>(nih, fb[b][2], r);
         r = mma<E>(nih, fb[b][3], r);
         r = mma<E>(nil, fb[b][2], r);
-        // Im += ar bi + ai br
-        m = mma<E>(fa[a][0], fb[b][2], m);
-        m = mma<E>(fa[a][0], fb[b][3], m);
-        m = mma<E>(fa[a][1], fb[b][2], m);
-        m = mma<E>(fa[a][2], fb[b][0], m);
-        m = mma<E>(fa[a][2], fb[b][1], m);
-        m = mma<E>(fa[a][3], fb[b][0], m);
+        // Im += ar bi + ai br (its negative in odd stages)
+        m = mma<E>(i0, fb[b][2], m);
+        m = mma<E>(i0, fb[b][3], m);
+        m = mma<E>(i1, fb[b][2], m);
+        m = mma<E>(i2, fb[b][0], m);
+        m = mma<E>(i2, fb[b][1], m);
+        m = mma<E>(i3, fb[b][0], m);
         cr[a][b] = r;
-        ci[a][b] = m;
+        ci[a][b] = flip ? -m : m;
       }
     }
   }
@@ -234,7 +246,11 @@ __device__ __forceinline__ void split128_accumulate(
   // One stage: the twelve partial products of LDS buffer cur; between the
   // first group and the rest, LDS buffer cur^1 receives stage kt+1 from (ra, rb)
   // and (ra, rb) starts loading stage kt+1+PF.
-  auto stage = [&](int kt, int cur, u32x4 (&ra)[LD], u32x4 (&rb)[LD]) {
+  // FLIP: the stage accumulates -Im into ci (the caller negates ci around it);
+  // its imaginary-part operands are then -A: the two im planes of A are needed
+  // only negated (nf2, nf3), so fa[a][2], fa[a][3] take -re_hi, -re_lo.
+  auto stage = [&](int kt, int cur, u32x4 (&ra)[LD], u32x4 (&rb)[LD], auto flip_tag) {
+    constexpr bool FLIP = decltype(flip_tag)::value;
     u32x4 fa[TM][4], nf2[TM], nf3[TM], fb0[TN], fb1[TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
@@ -242,7 +258,16 @@ __device__ __forceinline__ void split128_accumulate(
       for (int p = 0; p < 4; ++p) fa[a][p] = As[cur][p][wm0 + a * 16 + lr][lg];
       nf2[a] = negate8(fa[a][2]);
       nf3[a] = negate8(fa[a][3]);
+      if (FLIP) {
+        fa[a][2] = negate8(fa[a][0]);
+        fa[a][3] = negate8(fa[a][1]);
+      }
     }
+    // Operands of the imaginary part: ai (with B re planes), ar (with B im planes).
+    auto ai_hi = [&](int a) -> const u32x4 & { return FLIP ? nf2[a] : fa[a][2]; };
+    auto ai_lo = [&](int a) -> const u32x4 & { return FLIP ? nf3[a] : fa[a][3]; };
+    auto ar_hi = [&](int a) -> const u32x4 & { return FLIP ? fa[a][2] : fa[a][0]; };
+    auto ar_lo = [&](int a) -> const u32x4 & { return FLIP ? fa[a][3] : fa[a][1]; };
     VG_READB(fb0, cur, 0);
     VG_READB(fb1, cur, 1);
     // B plane 0 (re_hi): Re += Ar_hi Br_hi + Ar_lo Br_hi;  Im += Ai_hi Br_hi + Ai_lo Br_hi
@@ -251,9 +276,9 @@ __device__ __forceinline__ void split128_accumulate(
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma<E>(fa[a][0], fb0[b], cr[a][b]);
-        ci[a][b] = mma<E>(fa[a][2], fb0[b], ci[a][b]);
+        ci[a][b] = mma<E>(ai_hi(a), fb0[b], ci[a][b]);
         cr[a][b] = mma<E>(fa[a][1], fb0[b], cr[a][b]);
-        ci[a][b] = mma<E>(fa[a][3], fb0[b], ci[a][b]);
+        ci[a][b] = mma<E>(ai_lo(a), fb0[b], ci[a][b]);
       }
     if (kt + 1 < nkt) {
       VG_STORE128(ra, rb, cur ^ 1);
@@ -266,7 +291,7 @@ __device__ __forceinline__ void split128_accumulate(
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma<E>(fa[a][0], fb1[b], cr[a][b]);
-        ci[a][b] = mma<E>(fa[a][2], fb1[b], ci[a][b]);
+        ci[a][b] = mma<E>(ai_hi(a), fb1[b], ci[a][b]);
       }
     VG_READB(fb1, cur, 3);
     // B plane 2 (im_hi): Re -= Ai_hi Bi_hi + Ai_lo Bi_hi;  Im += Ar_hi Bi_hi + Ar_lo Bi_hi
@@ -275,9 +300,9 @@ __device__ __forceinline__ void split128_accumulate(
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma<E>(nf2[a], fb0[b], cr[a][b]);
-        ci[a][b] = mma<E>(fa[a][0], fb0[b], ci[a][b]);
+        ci[a][b] = mma<E>(ar_hi(a), fb0[b], ci[a][b]);
         cr[a][b] = mma<E>(nf3[a], fb0[b], cr[a][b]);
-        ci[a][b] = mma<E>(fa[a][1], fb0[b], ci[a][b]);
+        ci[a][b] = mma<E>(ar_lo(a), fb0[b], ci[a][b]);
       }
     // B plane 3 (im_lo): Re -= Ai_hi Bi_lo;  Im += Ar_hi Bi_lo
 #pragma unroll
@@ -285,7 +310,7 @@ __device__ __forceinline__ void split128_accumulate(
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
         cr[a][b] = mma<E>(nf2[a], fb1[b], cr[a][b]);
-        ci[a][b] = mma<E>(fa[a][0], fb1[b], ci[a][b]);
+        ci[a][b] = mma<E>(ar_hi(a), fb1[b], ci[a][b]);
       }
     __syncthreads();
   };
@@ -295,10 +320,19 @@ __device__ __forceinline__ void split128_accumulate(
   __syncthreads();
   if (nkt > 1) VG_LOAD128(ra0, rb0, BK);                 // stage 1, stored during stage 0
   if (PF == 2 && nkt > 2) VG_LOAD128(ra1, rb1, 2 * BK);  // stage 2, stored during stage 1
+  // Even stages accumulate +Im, odd ones -Im (ci negated around them).
+  auto negate_ci = [&] {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) ci[a][b] = -ci[a][b];
+  };
   for (int kt = 0; kt < nkt; kt += 2) {
-    stage(kt, 0, ra0, rb0);
-    if (PF == 2) stage(kt + 1, 1, ra1, rb1);
-    else stage(kt + 1, 1, ra0, rb0);
+    stage(kt, 0, ra0, rb0, std::false_type{});
+    negate_ci();
+    if (PF == 2) stage(kt + 1, 1, ra1, rb1, std::true_type{});
+    else stage(kt + 1, 1, ra0, rb0, std::true_type{});
+    negate_ci();
   }
 #undef VG_LOAD128
 #undef VG_STORE128
