@@ -18,6 +18,10 @@
 //
 // Operand storage (16-bit planes, p = re_hi, re_lo, im_hi, im_lo; np = padded N,
 // a multiple of 64, zero-filled beyond N):
+//   A (bf16 form): kADither copies of the four planes, whose lo planes carry
+//      dithered roundings of the constant S^-1 - I; the product of step n
+//      reads copy n mod kADither (lev_ctr = the device step counter; the
+//      plainly rounded middle copy without it).  The fp16 form has one copy;
 //   A: plane p, batch k: row-major np x np            (A[i][kk] at i*np + kk)
 //   B: plane p, batch k: k-packed (np/8) x np x 8     (B[kk][j] at ((kk/8)*np + j)*8 + kk%8)
 // so that the eight consecutive kk one lane feeds to an MFMA are 16 bytes.
@@ -53,17 +57,26 @@ __device__ inline float unscale(const float *sa, const float *sb, int k) {
   return sa ? 1.0f / (sa[k] * sb[k]) : 1.0f;
 }
 
+// The copy of A for this step (see kADither): bf16 only, the fp16 form keeps one.
+template <int E>
+__device__ inline const uint16_t *a_copy(const uint16_t *A, const int64_t *lev_ctr, size_t plane) {
+  if constexpr (E != 0) return A;
+  const int lev = lev_ctr != nullptr ? (int)(*lev_ctr % kADither) : kADither / 2;
+  return A + (size_t)lev * 4 * plane;
+}
+
 constexpr int BM = 64, BN = 64, BK = 32;   // workgroup tile; 4 wavefronts of 32x32
 constexpr int NT = 256;
 constexpr int APAD = 40;                    // 16-bit values per LDS row of A (32 + 8 pad)
 
 template <int E>
-__global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict__ A,
+__global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict__ A0,
                                                      const uint16_t *__restrict__ B,
                                                      float2 *__restrict__ Y, int n, int np,
                                                      int batch_count, int tiles_m, int tiles_n,
                                                      const float *__restrict__ sa,
-                                                     const float *__restrict__ sb) {
+                                                     const float *__restrict__ sb,
+                                                     const int64_t *__restrict__ lev_ctr) {
   // LDS: A [plane][row][k] (padded rows), B [plane][k/8][col][8].
   __shared__ u32x4 As[4][BM][APAD / 8];
   __shared__ u32x4 Bs[4][BK / 8][BN];
@@ -78,6 +91,7 @@ __global__ __launch_bounds__(NT) void k_cgemm_split16(const uint16_t *__restrict
 
   const size_t plane = (size_t)batch_count * np * np;     // elements per plane
   const size_t boff = (size_t)batch * np * np;
+  const uint16_t *__restrict__ A = a_copy<E>(A0, lev_ctr, plane);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
   const int lr = lane & 15, lg = lane >> 4;
@@ -343,13 +357,14 @@ __device__ __forceinline__ void split128_accumulate(
 }
 
 template <int E, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint16_t *__restrict__ A,
+__global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint16_t *__restrict__ A0,
                                                                      const uint16_t *__restrict__ B,
                                                                      float2 *__restrict__ Y, int n,
                                                                      int np, int batch_count,
                                                                      int tiles_m, int tiles_n,
                                                                      const float *__restrict__ sa,
-                                                                     const float *__restrict__ sb) {
+                                                                     const float *__restrict__ sb,
+                                                                     const int64_t *__restrict__ lev_ctr) {
   constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
   __shared__ u32x4 As[2][4][BM2][APAD / 8];
   __shared__ u32x4 Bs[2][4][BK / 8][BN2];
@@ -364,6 +379,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint
 
   const size_t plane = (size_t)batch_count * np * np;
   const size_t boff = (size_t)batch * np * np;
+  const uint16_t *__restrict__ A = a_copy<E>(A0, lev_ctr, plane);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm0 = (wave / WGN) * (BM2 / WGM), wn0 = (wave % WGN) * (BN2 / WGN);
   const int lr = lane & 15, lg = lane >> 4;
@@ -406,10 +422,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128(const uint
 // per-wavefront LDS buffers to the lane that needs it transposed.
 template <int E, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128_update(
-    const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float2 *__restrict__ Y,
+    const uint16_t *__restrict__ A0, const uint16_t *__restrict__ B, float2 *__restrict__ Y,
     const float2 *__restrict__ W, const double2 *__restrict__ m0, const double2 *dbase,
     double2 *dout, int n, int np, int batch_count, int T, double fac, const float *__restrict__ sa,
-    const float *__restrict__ sb, int64_t *ctr) {
+    const float *__restrict__ sb, const int64_t *__restrict__ lev_ctr) {
   constexpr int TM = BM2 / WGM / 16, TN = BN2 / WGN / 16;
   __shared__ u32x4 As[2][4][BM2][APAD / 8];
   __shared__ u32x4 Bs[2][4][BK / 8][BN2];
@@ -449,6 +465,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128_update(
 
   const size_t plane = (size_t)batch_count * np * np;
   const size_t boff = (size_t)batch * np * np;
+  const uint16_t *__restrict__ A = a_copy<E>(A0, lev_ctr, plane);
   const size_t base = (size_t)batch * n * n;
   float2 *Yb = Y + base;
   const float2 *Wb = W + base;
@@ -547,9 +564,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128_update(
       }
       __syncthreads();
     }
-  // The step is done once this kernel has run: advance the device step index
-  // (no other workgroup of this kernel reads it).
-  if (ctr != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *ctr += 1;
 }
 
 // tile: 1 = 64 x 64 (four wavefronts); 128 x 128 (np a multiple of 128 only)
@@ -559,23 +573,24 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_cgemm_split16_128_update(
 // np = 512 up, else 1.
 template <int E>
 static void launch_e(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
-                     hipStream_t s, int tile, const float *sa, const float *sb) {
+                     hipStream_t s, int tile, const float *sa, const float *sb,
+                     const int64_t *lev_ctr) {
   if (tile == 0) tile = split16_default_tile(np);
   if (tile >= 2 && tile <= 5 && np % BM2 == 0) {
     const int tm = np / BM2, tn = np / BN2;
     const dim3 grid(tm * tn, batch);
     if (tile == 2)
-      hipLaunchKernelGGL((k_cgemm_split16_128<E, 4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 4, 4>), grid, dim3(64 * 16), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb, lev_ctr);
     else if (tile == 3)
-      hipLaunchKernelGGL((k_cgemm_split16_128<E, 2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 2, 4>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb, lev_ctr);
     else if (tile == 4)
-      hipLaunchKernelGGL((k_cgemm_split16_128<E, 4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 4, 2>), grid, dim3(64 * 8), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb, lev_ctr);
     else
-      hipLaunchKernelGGL((k_cgemm_split16_128<E, 2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb);
+      hipLaunchKernelGGL((k_cgemm_split16_128<E, 2, 2>), grid, dim3(64 * 4), 0, s, a, b, y, n, np, batch, tm, tn, sa, sb, lev_ctr);
   } else {
     const int tm = np / BM, tn = np / BN;
     hipLaunchKernelGGL((k_cgemm_split16<E>), dim3(tm * tn, batch), dim3(NT), 0, s, a, b, y, n, np, batch,
-                       tm, tn, sa, sb);
+                       tm, tn, sa, sb, lev_ctr);
   }
 }
 
@@ -596,6 +611,9 @@ static bool launch_update_e(const uint16_t *a, const uint16_t *b, float2 *y, con
   else if (tile == 4) VG_UPD(4, 2);
   else VG_UPD(2, 2);
 #undef VG_UPD
+  // The step is done once the product and update have run: advance the device
+  // step index (a launch of its own: every workgroup reads it for its copy of A).
+  if (ctr != nullptr) launch_advance_counter(ctr, s);
   return true;
 }
 
@@ -612,13 +630,13 @@ bool launch_cgemm_update_split16(int fmt, const uint16_t *a, const uint16_t *b, 
 }
 
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
-                         hipStream_t s, int tile) {
-  launch_e<0>(a, b, y, n, np, batch, s, tile, nullptr, nullptr);
+                         hipStream_t s, int tile, const int64_t *lev_ctr) {
+  launch_e<0>(a, b, y, n, np, batch, s, tile, nullptr, nullptr, lev_ctr);
 }
 
 void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                         const float *sa, const float *sb, hipStream_t s, int tile) {
-  launch_e<1>(a, b, y, n, np, batch, s, tile, sa, sb);
+  launch_e<1>(a, b, y, n, np, batch, s, tile, sa, sb, nullptr);
 }
 
 }  // namespace vgtb

@@ -124,6 +124,7 @@ __global__ void k_store_ring(FieldChunk f, int64_t step0, int ns, double *ring) 
 }
 
 __global__ void k_set_counter(int64_t *ctr, int64_t v) { *ctr = v; }
+__global__ void k_advance_counter(int64_t *ctr) { *ctr += 1; }
 
 // One wavefront per (atom I, k): sweep the pair blocks of row I of D_k and
 // accumulate  q = Re sum D conj(S)  (Mulliken, row I),  E = Re sum conj(D) H0,
@@ -303,6 +304,18 @@ __device__ inline void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
   const float xf = (float)x;
   hi = to_bf16(xf);
   lo = to_bf16(xf - from_bf16(hi));
+}
+// The lo part of the bf16 split of S^-1 - I in copy `level` of the dithered
+// representation (see kADither): r the remainder after hi.
+__device__ inline uint16_t dithered_bf16(float r, int level) {
+  if (r == 0.0f) return to_bf16(r);
+  const double ar = fabs((double)r);
+  const double d = dither_offset(level);
+  int e;
+  frexp(ar, &e);   // ar = m 2^e, m in [0.5, 1): the bf16 grid step there is 2^(e - 8)
+  const float t = d == 0.0 ? (float)ar : (float)(ar + d * ldexp(1.0, e - 8));
+  const uint16_t m = to_bf16(t);
+  return r < 0.0f ? (uint16_t)(m ^ 0x8000u) : m;
 }
 // x sc = hi + lo with hi = f16(x sc), lo = f16(x sc - hi); sc a power of two
 // chosen so that the largest |x sc| of the matrix lies in [2^13, 2^14).
@@ -1448,16 +1461,25 @@ __global__ void k_convert_operand(const double2 *__restrict__ src, void *__restr
     double2 v = make_double2(0.0, 0.0);
     if (i < n && j < n) v = src[(size_t)k * n * n + (size_t)i * n + j];
     if (i == j && i < n) v.x -= 1.0;
-    uint16_t rh, rl, ih, il;
-    split_bf16(v.x, rh, rl);
-    split_bf16(v.y, ih, il);
+    uint16_t rh, ih;
+    float rr, ri;   // remainders after hi (exact in float)
+    {
+      const float xr = (float)v.x, xi = (float)v.y;
+      rh = to_bf16(xr);
+      ih = to_bf16(xi);
+      rr = xr - from_bf16(rh);
+      ri = xi - from_bf16(ih);
+    }
     uint16_t *o = static_cast<uint16_t *>(dst);
     const size_t plane = (size_t)nk * np * np;
     const size_t idx = (size_t)k * np * np + (size_t)i * np + j;
-    o[idx] = rh;
-    o[plane + idx] = rl;
-    o[2 * plane + idx] = ih;
-    o[3 * plane + idx] = il;
+    for (int lev = 0; lev < kADither; ++lev) {
+      uint16_t *ol = o + (size_t)lev * 4 * plane;
+      ol[idx] = rh;
+      ol[plane + idx] = dithered_bf16(rr, lev);
+      ol[2 * plane + idx] = ih;
+      ol[3 * plane + idx] = dithered_bf16(ri, lev);
+    }
   }
 }
 
@@ -1577,6 +1599,10 @@ void launch_pair_bloch_momentum(const PairGraph &g, const double *kpts, int nk, 
 
 void launch_store_ring(const FieldChunk &f, int64_t step0, int ns, double *ring, hipStream_t s) {
   hipLaunchKernelGGL(k_store_ring, dim3(1), dim3(3 * kSmallChunk), 0, s, f, step0, ns, ring);
+}
+
+void launch_advance_counter(int64_t *ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(1), 0, s, ctr);
 }
 
 void launch_set_counter(int64_t *ctr, int64_t v, hipStream_t s) {

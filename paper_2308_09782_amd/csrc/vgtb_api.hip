@@ -351,7 +351,8 @@ void carve(Carver &cv, const Sizes &z, Ctx *c) {
   if (z.deviation) {
     const size_t lo = (z.precision == VGTB_FP32) ? n2 * sizeof(float2)
                                                   : (size_t)4 * z.npad * z.npad * z.nk * sizeof(uint16_t);
-    c->sinv_lo = cv.template take<char>(lo);
+    // S^-1 - I: the bf16 form keeps kADither copies with dithered lo planes.
+    c->sinv_lo = cv.template take<char>(z.precision == VGTB_BF16X3 ? lo * vgtb::kADither : lo);
     c->w_lo = cv.template take<char>(lo);
     c->y_lo = cv.template take<float2>(n2);
     c->w32 = (z.precision == VGTB_BF16X3 || z.precision == VGTB_FP16X3) ? cv.template take<float2>(n2)
@@ -646,7 +647,8 @@ void launch_reduced_product(vgtb_ctx *c, int fmt, int tile, hipStream_t s) {
                            c->y_lo, n, nk, s, tile);
   else if (fmt == 2)
     vgtb::launch_cgemm_bf16x3(static_cast<const uint16_t *>(c->sinv_lo),
-                              static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s, tile);
+                              static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, s, tile,
+                              c->ctr);
   else
     vgtb::launch_cgemm_f16x3(static_cast<const uint16_t *>(c->sinv_lo),
                              static_cast<const uint16_t *>(c->w_lo), c->y_lo, n, c->np, nk, c->scale_a,

@@ -32,6 +32,23 @@ __device__ inline float f16_pow2_scale(float m) {
   return sc;
 }
 
+// The constant S^-1 - I enters the bf16 split product as hi + lo, and the error
+// of that representation (about 2^-17 relative) is the same at every step: it
+// acts like a slightly different overlap and shifts the response frequencies.
+// Its lo part is therefore stored kADither times with dithered rounding, and
+// step n uses copy n mod kADither (odd, so that both leapfrog sublattices see
+// every copy): copy j rounds |r| + d_j u to the bf16 grid, r the remainder
+// after hi, u the grid step at |r|, d_j = (j + 1/2)/kADither - 1/2, so the
+// copies average to r within u / (2 kADither).  The middle copy (d = 0) is the
+// plain rounding; a remainder of zero stays zero.  Magnitude and sign are
+// dithered separately, so the (j, i) copy of a Hermitian matrix stays the
+// conjugate of the (i, j) one.  The scaled fp16 split carries 2^-22 and keeps
+// one plainly rounded copy.
+constexpr int kADither = 5;
+__device__ inline double dither_offset(int level) {
+  return ((double)level + 0.5) / (double)kADither - 0.5;
+}
+
 __device__ inline int xcd_slot(int lin, int total) {
   return (total & 7) == 0 ? (lin & 7) * (total >> 3) + (lin >> 3) : lin;
 }
@@ -118,6 +135,7 @@ void launch_pair_bloch_momentum(const PairGraph &g, const double *kpts, int nk, 
 // ring slots of steps [step0, step0 + ns), ns <= kSmallChunk (= kStepRing).
 void launch_store_ring(const FieldChunk &f, int64_t step0, int ns, double *ring, hipStream_t s);
 void launch_set_counter(int64_t *ctr, int64_t v, hipStream_t s);
+void launch_advance_counter(int64_t *ctr, hipStream_t s);   // *ctr += 1
 // History row = hist + (step mod cap) (5 + na), step from ctr (row 0 if null).
 void launch_reduce(const double *part, int nk, int na, const double *kw, double jscale,
                    const double *gamma, const double *z, double *v, double *qbuf,
@@ -149,6 +167,8 @@ void launch_update_split(const float2 *g, const float2 *w, const double2 *m0, co
 // D_out = D_base - i (Y - Y^dag) (used to form the constant term m0 = -i X0).
 void launch_update_const(const double2 *y, const double2 *dbase, double2 *dout, int n, int nk,
                          hipStream_t s);
+// fmt 1: S^-1 - I as complex64; fmt 2: its bf16 hi/lo planes in kADither
+// copies with dithered lo planes.
 void launch_convert_operand(const double2 *src, void *dst, int n, int np, int nk, int fmt,
                             hipStream_t s);
 // target[k] = Tr(D_k S_k) of the density dd.
@@ -273,17 +293,23 @@ void launch_zgemm_f64(const double2 *a, const double2 *b, double2 *c, int n, int
                       hipStream_t s, int tile = 0);
 void launch_cgemm_f32(const float2 *a, const float2 *b, float2 *c, int n, int batch,
                       hipStream_t s, int tile = 0);
+// a holds kADither copies of the four planes of A (each 4 np^2 batch values);
+// the product uses copy (*lev_ctr) mod kADither, the plainly rounded middle
+// copy when lev_ctr is null.
 void launch_cgemm_bf16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
-                         hipStream_t s, int tile = 0);
-// The same product on fp16 planes scaled per k by sa[k] (A) and sb[k] (B).
+                         hipStream_t s, int tile = 0, const int64_t *lev_ctr = nullptr);
+// The same product on fp16 planes scaled per k by sa[k] (A, one copy) and
+// sb[k] (B).
 void launch_cgemm_f16x3(const uint16_t *a, const uint16_t *b, float2 *y, int n, int np, int batch,
                         const float *sa, const float *sb, hipStream_t s, int tile = 0);
 // The 16-bit split product fused with the leapfrog update (fmt 2: bf16, 3:
 // scaled fp16): G = (S^-1 - I) W into y for the tiles I <= J, and
 // dout = dbase - i fac (Y - Y^dag) + fac m0 (m0 may be null) with Y = G + w,
-// the same bits as launch_cgemm_* followed by launch_update_split; ctr (may be
-// null) advanced by one.  Only for the 128 x 128 tiles (tile 2-5, or 0 where
-// the size rule picks them); returns false, launching nothing, otherwise.
+// the same bits as launch_cgemm_* followed by launch_update_split; the copy of
+// the bf16 A is chosen by ctr as there, and ctr (may be null) is then advanced by one
+// (by a launch of its own, after the product).  Only for the 128 x 128 tiles
+// (tile 2-5, or 0 where the size rule picks them); returns false, launching
+// nothing, otherwise.
 bool launch_cgemm_update_split16(int fmt, const uint16_t *a, const uint16_t *b, float2 *y,
                                  const float2 *w, const double2 *m0, const double2 *dbase,
                                  double2 *dout, int n, int np, int batch, double fac, int64_t *ctr,
@@ -370,7 +396,7 @@ struct vgtb_ctx {
   int *flag = nullptr;         // 1
   // deviation (reduced-precision) forms
   int np = 0;                  // padded N of the bf16 planes
-  void *sinv_lo = nullptr;     // S^-1 as complex64 (n) or 4 bf16 planes (np)
+  void *sinv_lo = nullptr;     // S^-1 - I as complex64 (n), its 4 fp16 planes, or kADither copies of its 4 bf16 planes (np)
   void *w_lo = nullptr;        // W in the same format
   float2 *y_lo = nullptr;      // nk * n * n, G = (S^-1 - I) W
   float2 *w32 = nullptr;       // nk * n * n, W as complex64 (bf16 and fp16 forms; the fp32 form uses w_lo)
