@@ -72,7 +72,7 @@ def _one_step(sysm, d0, a, precision):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("precision,tile", [("fp64", 3), ("fp16x3", 2)])
+@pytest.mark.parametrize("precision,tile", [("fp64", 3), ("fp16x3", 2), ("bf16x3", 2)])
 def test_pulse_peak_30_steps_against_oracle_fixture(precision, tile):
     fx = np.load(os.path.join(GOLDEN, "asi512_k8_scc_pulse30.npz"))
     sysm = vs.config_system("asi512_k8_scc")
@@ -104,7 +104,7 @@ def test_pulse_peak_30_steps_against_oracle_fixture(precision, tile):
         assert np.abs(h["q"] - fx["q"]).max() < 1e-5
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3", "bf16x3"])
 def test_csi216_all_k_kick_against_oracle_fixture(precision):
     fx = np.load(os.path.join(GOLDEN, "csi216_k216_kick20.npz"))
     c = vs.CONFIGS["csi216_k216"]
