@@ -907,9 +907,11 @@ __global__ __launch_bounds__(256) void k_small_c0(PairGraph g, const double *__r
 // on complex64 operands; 3xBF16 / FP16X3 on hi/lo splits (x = hi + lo) of both
 // operands, A_hi B_hi + A_hi B_lo + A_lo B_hi, with fp32 accumulation (products
 // of two 16-bit values are exact in fp32); FP16X3 splits x s with the per-k
-// powers of two sa, sw.
+// powers of two sa, sw.  3xBF16 takes the lo part of S^-1 - I from copy
+// `level` of its dithered representation (see kADither), as the per-step path.
 template <int FORM>
-__device__ inline void small_mac(double2 a, double2 w, float sa, float sw, float &gr, float &gi) {
+__device__ inline void small_mac(double2 a, double2 w, float sa, float sw, int level, float &gr,
+                                 float &gi) {
   if (FORM == 1) {
     const float ar = (float)a.x, ai = (float)a.y, wr = (float)w.x, wi = (float)w.y;
     gr = fmaf(ar, wr, gr);
@@ -924,7 +926,13 @@ __device__ inline void small_mac(double2 a, double2 w, float sa, float sw, float
   auto split = [&](double x, float sc, bool a_operand, float &hi, float &lo) {
     uint16_t h, l;
     if (FORM == 2) {
-      split_bf16(x, h, l);
+      if (a_operand) {
+        const float xf = (float)x;
+        h = to_bf16(xf);
+        l = dithered_bf16(xf - from_bf16(h), level);
+      } else {
+        split_bf16(x, h, l);
+      }
       hi = from_bf16(h);
       lo = from_bf16(l);
     } else if (a_operand) {
@@ -972,7 +980,8 @@ __device__ inline double block_sum_small(double v, double *red) {
 // FP64, as the update of the per-step path reads them).  St = (S^-1)^T.
 template <int FORM>
 __device__ void small_deviation_product(const double2 *St, double2 *Wm, double2 *Y, int n,
-                                        const SmallDeviation &dev, int k, size_t base, double *red) {
+                                        const SmallDeviation &dev, int k, size_t base, int level,
+                                        double *red) {
   const int n2 = n * n;
   float m = 0.0f;
   for (int t = threadIdx.x; t < n2; t += blockDim.x) {
@@ -1002,7 +1011,7 @@ __device__ void small_deviation_product(const double2 *St, double2 *Wm, double2 
     for (int kk = 0; kk < n; ++kk) {
       double2 a = St[kk * n + i];             // S^-1[i][kk]
       if (kk == i) a.x -= 1.0;
-      small_mac<FORM>(a, Wm[kk * n + j], sa, sw, gr, gi);
+      small_mac<FORM>(a, Wm[kk * n + j], sa, sw, level, gr, gi);
     }
     const double2 w = Wm[t];
     const float2 g = make_float2(us * gr, us * gi);
@@ -1152,7 +1161,8 @@ __device__ __forceinline__ void small_steps_body(const PairGraph &g, const doubl
       lds_zgemm(St, Wm, Hm, n);   // Y = S^-1 W (H no longer needed)
       __syncthreads();
     } else {
-      small_deviation_product<FORM>(St, Wm, Hm, n, dev, k, base, red);
+      small_deviation_product<FORM>(St, Wm, Hm, n, dev, k, base, (int)((dev.step0 + s) % kADither),
+                                    red);
     }
     const double fac = hp ? 2.0 * dt : dt;
     const double2 *Db = hp ? Dp : Dc;
