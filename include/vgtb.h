@@ -56,7 +56,9 @@ typedef enum {
 typedef enum {
   VGTB_FP64 = 0,   /* every product in FP64 on the FP64 matrix cores                       */
   VGTB_FP32 = 1,   /* deviation form, S^-1 (H D - H0 D0) product in FP32 on matrix cores   */
-  VGTB_BF16X3 = 2, /* deviation form, the same product as three BF16 products (hi/lo split) */
+  VGTB_BF16X3 = 2, /* deviation form, the same product as three BF16 products (hi/lo split;
+                      the lo part of the constant S^-1 - I dithered over five steps, held
+                      in five copies)                                                       */
   VGTB_FP16X3 = 3  /* deviation form, three FP16 products of hi/lo splits scaled per k by
                       powers of two (same matrix-core rate, about 16x smaller product error) */
 } vgtb_precision;
