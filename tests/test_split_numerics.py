@@ -7,7 +7,9 @@ numpy (float16; bfloat16 by round-to-nearest-even on float32 bits) and check
 the error bounds the design relies on: a power-of-two scale putting the
 largest |x| in [2^13, 2^14) keeps the fp16 pair inside fp16's range and
 accurate to about 2^-22 of |x|, against about 2^-16 for the bf16 pair, and
-the three-product sum inherits that difference.  No GPU code is involved.
+the three-product sum inherits that difference; the five dithered bf16 copies
+of the lo part of S^-1 - I average to it within a tenth of its grid step.  No
+GPU code is involved.
 """
 import numpy as np
 
@@ -104,3 +106,47 @@ def test_three_product_sum_error():
     ebf = (np.abs(gbf - exact) / scale).max()
     assert e16 < 2.0 ** -20
     assert ebf > 16 * e16
+
+
+def _dithered_bf16(r, level, copies=5):
+    """The lo part of the bf16 split of S^-1 - I in copy `level` (0..copies-1):
+    |r| + d u rounded to bf16, d = (level + 1/2)/copies - 1/2, u the bf16 grid
+    step at |r|, the sign of r applied afterwards; r = 0 stays 0."""
+    r = np.asarray(r, dtype=np.float32)
+    ar = np.abs(r).astype(np.float64)
+    d = (level + 0.5) / copies - 0.5
+    _, e = np.frexp(ar)
+    u = np.ldexp(1.0, e - 8)
+    t = (ar + d * u).astype(np.float32) if d != 0.0 else ar.astype(np.float32)
+    m = _bf16(t).astype(np.float64)
+    out = np.where(r < 0, -m, m)
+    return np.where(r == 0, 0.0, out)
+
+
+def test_dithered_bf16_copies_average_to_the_remainder():
+    # The constant S^-1 - I enters every step; its bf16 lo part is stored in five
+    # copies with rounding offsets -2/5 .. 2/5 of the grid step, one per step.
+    # Their mean is within u/10 of the remainder (plain rounding: up to u/2),
+    # the middle copy is the plain rounding, and the sign is applied after the
+    # magnitude, so mirror elements (conjugates) stay exact mirrors.
+    rng = np.random.default_rng(8)
+    x = _values(rng, 100_000)
+    hi = _bf16(x)
+    r = (x - hi).astype(np.float32)
+    ar = np.abs(r).astype(np.float64)
+    _, e = np.frexp(ar)
+    u = np.ldexp(1.0, e - 8)
+    copies = [_dithered_bf16(r, j) for j in range(5)]
+    plain = _split_bf16(x)[1]
+    assert np.array_equal(copies[2], plain)
+    for j, c in enumerate(copies):
+        assert np.array_equal(_dithered_bf16(-r, j), -c)
+        assert np.all(c[r == 0] == 0.0)
+    mean = np.mean(copies, axis=0)
+    # away from a binade edge (where the grid step of the rounded value doubles)
+    inner = (ar > 0) & (np.frexp(ar + 0.5 * u)[1] == e) & (np.frexp(np.maximum(ar - 0.5 * u, 0))[1] == e)
+    err_mean = np.abs(mean - r.astype(np.float64))[inner] / u[inner]
+    err_plain = np.abs(plain - r.astype(np.float64))[inner] / u[inner]
+    assert err_mean.max() <= 0.1 + 1e-6
+    assert err_plain.max() > 0.45
+    assert np.sqrt(np.mean(err_mean ** 2)) < 0.25 * np.sqrt(np.mean(err_plain ** 2))
