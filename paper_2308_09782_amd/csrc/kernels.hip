@@ -1528,30 +1528,47 @@ __global__ void k_trace_factors(const double *__restrict__ tpart, double *target
   }
 }
 
-// Both levels: D <- c * 1/2 (D + D^dag).  Tile pairs (bi <= bj) are handled
-// by one block so the in-place update never races with its mirror.
+// Both levels: D <- c * 1/2 (D + D^dag).  A tile pair (bi <= bj) is handled by
+// one block so the in-place update never races with its mirror; the grid holds
+// only the pairs (blockIdx.x = bj (bj + 1) / 2 + bi, as in k_update), and each
+// thread issues all its loads of both tiles before the first LDS write.
 __global__ __launch_bounds__(256) void k_rescale(double2 *da, double2 *db,
-                                                 const double *__restrict__ fac, int n, int nt) {
+                                                 const double *__restrict__ fac, int n) {
   __shared__ double2 t1[32][33], t2[32][33];
-  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
-  if (bi > bj) return;
+  const int p = blockIdx.x;
+  int tj = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+  while ((tj + 1) * (tj + 2) / 2 <= p) ++tj;
+  while (tj * (tj + 1) / 2 > p) --tj;
+  const int bi = p - tj * (tj + 1) / 2, bj = tj;
   const int k = blockIdx.y, lev = blockIdx.z;
   double2 *d = lev ? db : da;
   const double c = fac[lev * gridDim.y + k];
   const size_t base = (size_t)k * n * n;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
+  const double2 z = make_double2(0.0, 0.0);
+  double2 v1[4], v2[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
     const int i1 = bi * 32 + r, j1 = bj * 32 + tx;
     const int i2 = bj * 32 + r, j2 = bi * 32 + tx;
-    const double2 z = make_double2(0.0, 0.0);
-    t1[r][tx] = (i1 < n && j1 < n) ? d[base + (size_t)i1 * n + j1] : z;   // tile (bi, bj)
-    t2[r][tx] = (i2 < n && j2 < n) ? d[base + (size_t)i2 * n + j2] : z;   // tile (bj, bi)
+    v1[q] = (i1 < n && j1 < n) ? d[base + (size_t)i1 * n + j1] : z;   // tile (bi, bj)
+    v2[q] = (bi != bj && i2 < n && j2 < n) ? d[base + (size_t)i2 * n + j2] : z;   // tile (bj, bi)
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    t1[ty + 8 * q][tx] = v1[q];
+    t2[ty + 8 * q][tx] = v2[q];
   }
   __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
+  // On the diagonal the mirror of tile (bi, bi) is itself.
+  auto mirror = [&](int r, int cc) -> const double2 & { return bi != bj ? t2[cc][r] : t1[cc][r]; };
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
     const int i1 = bi * 32 + r, j1 = bj * 32 + tx;
     if (i1 < n && j1 < n) {
-      const double2 a = t1[r][tx], m = t2[tx][r];        // D[i][j], D[j][i]
+      const double2 a = t1[r][tx], m = mirror(r, tx);        // D[i][j], D[j][i]
       d[base + (size_t)i1 * n + j1] = make_double2(c * 0.5 * (a.x + m.x), c * 0.5 * (a.y - m.y));
     }
     if (bi != bj) {
@@ -1786,7 +1803,7 @@ void launch_rescale(const PairGraph &g, double2 *da, double2 *db, int n, int nk,
   hipLaunchKernelGGL(k_trace_factors, dim3(blocks_for(2 * nk, 64)), dim3(64), 0, s, tpart,
                      const_cast<double *>(target), fac, nk, g.n_atoms, 0);
   const int nt = (int)blocks_for(n, 32);
-  hipLaunchKernelGGL(k_rescale, dim3(nt * nt, nk, 2), dim3(256), 0, s, da, db, fac, n, nt);
+  hipLaunchKernelGGL(k_rescale, dim3(nt * (nt + 1) / 2, nk, 2), dim3(256), 0, s, da, db, fac, n);
 }
 
 template <int NO, int FORM, bool SCC>
