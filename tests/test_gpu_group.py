@@ -75,7 +75,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("scc", [False, True])
-@pytest.mark.parametrize("precision", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16x3", "bf16x3"])
 def test_group_equals_each_system_alone(precision, scc):
     members = _members(scc)
     total = sum(CALLS)
